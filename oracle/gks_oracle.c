@@ -1,0 +1,1427 @@
+/*
+ * gks_oracle.c -- slow, plain FP64 CPU oracle for the compact 6th/8th-order
+ * gas-kinetic scheme (Zhao, Ji, Shyy, Xu, "Compact higher-order gas-kinetic
+ * schemes with spectral-like resolution for compressible flow simulations",
+ * arXiv:1901.00261).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent checker of the HIP
+ * library.  Only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or constant
+ * generator with the GPU path and must never be used as a fallback for it.
+ *
+ * Structure (each step cites the part of the paper it follows):
+ *   - Linear compact reconstruction P^5 / P^7 at x_{i+1/2} (Sec. 3.1): built
+ *     from its defining conditions (exact cell averages and cell-averaged
+ *     slopes; least squares on the outer cells for P^5) by solving the small
+ *     linear systems once at start-up.  The printed coefficient formulas are
+ *     NOT typed in here; the tests compare against them.
+ *   - Compact WENO-Z (Sec. 3.3): every candidate polynomial w_k (and the cubic
+ *     w~_1 used for beta_1) is built from its sub-stencil conditions; beta_k
+ *     is the Jiang-Shu indicator integral evaluated exactly; Z_ref, alpha,
+ *     delta follow the WENO-Z weight equations.  Linear weights d_k are the
+ *     printed ones (they are a choice, not fixed by a definition, because
+ *     w_1 and w_3 coincide).  Characteristic variables use the Euler
+ *     eigenvectors (Sec. 3.1, last paragraph); the right state is the mirror
+ *     image of the left one.
+ *   - Kinetic part (Sec. 2.1): Maxwellian moments and every product term are
+ *     handled by a generic polynomial-in-(u, v, xi^2) algebra with exact
+ *     Gaussian / half-Gaussian moments; micro-slopes are found by solving
+ *     the moment systems numerically.  The interface distribution is the
+ *     simplified third-order form of Sec. 2.1 (equation for f at x_{i+1/2}).
+ *   - MSMD time stepping (Sec. 2.2): the two-stage fourth-order update of the
+ *     cell averages and of the interface distribution, whose face values
+ *     give the new cell-averaged slopes through the Gauss formula (Sec. 3.1).
+ *
+ * Readings where the paper is silent or garbled (listed with reasons in the
+ * design notes of the repository):
+ *   A1  time coefficients: polynomial part of f(t) by its exact Taylor
+ *       coefficients at t = 0; the exp(-t/tau_n) part by the two-point fit of
+ *       its time integrals over [0, dt/2] and [0, dt].
+ *   A2  physical tau (mu/p, 0 for Euler) multiplies the Navier-Stokes terms;
+ *       the numerical tau_n of Sec. 4 sits in the exponentials.
+ *   A3  abar_xx, abar_xt, abar_tt are exact second Taylor coefficients of
+ *       the Maxwellian divided by g0 (they include the products abar^2,
+ *       abar*Abar, Abar^2).
+ *   A4  slopes of the WENO states: the WENO weights applied to the
+ *       derivatives of the candidate polynomials at the interface.
+ *   A5  WENO-Z exponent 1, epsilon = 1e-6 (Tables 3-4 single this value out).
+ *   A20 the equilibrium state's value at the interface is the kinetic
+ *       average of the two WENO-Z states, int psi [g_l H(u) + g_r (1-H(u))];
+ *       its derivatives come from the linear compact reconstruction (with
+ *       the linear reconstruction both states equal the linear value).
+ *   A6  characteristic frame at the mean of the two interface cells.
+ *   A8  2-D: the tangential linear 5th-order reconstruction serves the
+ *       equilibrium state (values and derivatives) and the derivatives of
+ *       the non-equilibrium states; the VALUES of the non-equilibrium
+ *       states at the Gauss points come from a 5th-order WENO-Z in the
+ *       tangential direction (three quadratic candidates, linear weights
+ *       reproducing the quartic at the point, the centre point's negative
+ *       linear weights split into two positive groups as in Shi, Hu and Shu,
+ *       J. Comput. Phys. 175 (2002), theta = 3).
+ *   A21 positivity fallback: a face-row WENO-Z state that is not physical
+ *       is replaced by the adjacent cell average; a Gauss-point state that is
+ *       not physical is replaced by its face-row line value.
+ *   G1  the missing operator before the x^4 term of w_6 is "+" (only
+ *       consequence here: none, w_6 is built from its conditions).
+ *   G2  beta uses the exact integral (a4 coefficient 87617/80640).
+ *   G4  Maxwellian exponent is -lambda(...).
+ */
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENONPHYS -4
+
+/* ------------------------------------------------------------------ */
+/* small dense linear algebra                                           */
+/* ------------------------------------------------------------------ */
+
+/* Solve A x = b in place (A row-major n x n, destroyed; b becomes x).
+   Gaussian elimination with partial pivoting. */
+static int solve_dense(int n, double *A, double *b)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        double best = fabs(A[k * n + k]);
+        for (int r = k + 1; r < n; ++r)
+            if (fabs(A[r * n + k]) > best) { best = fabs(A[r * n + k]); piv = r; }
+        if (!(best > 0.0)) return -1;
+        if (piv != k) {
+            for (int c = 0; c < n; ++c) { double t = A[k * n + c]; A[k * n + c] = A[piv * n + c]; A[piv * n + c] = t; }
+            double t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int r = k + 1; r < n; ++r) {
+            double f = A[r * n + k] / A[k * n + k];
+            if (f == 0.0) continue;
+            for (int c = k; c < n; ++c) A[r * n + c] -= f * A[k * n + c];
+            b[r] -= f * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        for (int c = k + 1; c < n; ++c) s -= A[k * n + c] * b[c];
+        b[k] = s / A[k * n + k];
+    }
+    return 0;
+}
+
+/* integer power of a double (exact for the small arguments used here) */
+static double ipow(double a, int m)
+{
+    double r = 1.0;
+    for (int i = 0; i < m; ++i) r *= a;
+    return r;
+}
+
+/* In a coordinate s measured in cell widths, the cell [a, a+1]:
+   average of s^m, and the cell-width-scaled average of d(s^m)/ds. */
+static double cell_avg_mono(double a, int m) { return (ipow(a + 1.0, m + 1) - ipow(a, m + 1)) / (double)(m + 1); }
+static double cell_dif_mono(double a, int m) { return m == 0 ? 0.0 : ipow(a + 1.0, m) - ipow(a, m); }
+
+/* ------------------------------------------------------------------ */
+/* Linear compact reconstruction (Sec. 3.1)                             */
+/* ------------------------------------------------------------------ */
+/* Stencil S_{i+1/2} = {I_{i-1}, I_i, I_{i+1}, I_{i+2}}; data per cell: the
+   average W_k and D_k = dx * W'_k.  Coordinate s = (x - x_{i+1/2}) / dx, so
+   I_{i-1+q} = [q-2, q-1].  lin_map[o][r][c]: r = 0 value at the interface,
+   r = 1 dx * P_x, r = 2 dx^2 * P_xx; c = 0..3 -> W_{i-1..i+2},
+   c = 4..7 -> D_{i-1..i+2}. o = 0 for P^5 (6th order), 1 for P^7. */
+static double lin_map[2][3][8];
+
+/* P^7: eight exact conditions, eq. (recons-8th). */
+static int build_p7(double out[3][8])
+{
+    for (int c = 0; c < 8; ++c) {
+        double A[64], b[8];
+        for (int q = 0; q < 4; ++q) {
+            double a = (double)(q - 2);
+            for (int m = 0; m < 8; ++m) {
+                A[q * 8 + m] = cell_avg_mono(a, m);
+                A[(4 + q) * 8 + m] = cell_dif_mono(a, m);
+            }
+        }
+        for (int r = 0; r < 8; ++r) b[r] = (r == c) ? 1.0 : 0.0;
+        if (solve_dense(8, A, b)) return -1;
+        out[0][c] = b[0];
+        out[1][c] = b[1];
+        out[2][c] = 2.0 * b[2];
+    }
+    return 0;
+}
+
+/* P^5: exact on I_i, I_{i+1} (eq. recons-6th-1), least squares with unit
+   weights on the average and on the dx-scaled slope residuals of I_{i-1},
+   I_{i+2} (eq. recons-6th-2).  Solved through the KKT system
+   [B^T B  C^T; C  0] [c; mu] = [B^T r; e]. */
+static int build_p5(double out[3][8])
+{
+    for (int col = 0; col < 8; ++col) {
+        double rhs_in[8];
+        for (int r = 0; r < 8; ++r) rhs_in[r] = (r == col) ? 1.0 : 0.0;
+        double Cm[4][6], Bm[4][6], e[4], rr[4];
+        int ce = 0, cb = 0;
+        for (int q = 0; q < 4; ++q) {
+            double a = (double)(q - 2);
+            int exact = (q == 1 || q == 2);
+            double rowa[6], rowd[6];
+            for (int m = 0; m < 6; ++m) { rowa[m] = cell_avg_mono(a, m); rowd[m] = cell_dif_mono(a, m); }
+            if (exact) {
+                memcpy(Cm[ce], rowa, sizeof rowa); e[ce++] = rhs_in[q];
+                memcpy(Cm[ce], rowd, sizeof rowd); e[ce++] = rhs_in[4 + q];
+            } else {
+                memcpy(Bm[cb], rowa, sizeof rowa); rr[cb++] = rhs_in[q];
+                memcpy(Bm[cb], rowd, sizeof rowd); rr[cb++] = rhs_in[4 + q];
+            }
+        }
+        double K[100], b[10];
+        memset(K, 0, sizeof K);
+        memset(b, 0, sizeof b);
+        for (int i = 0; i < 6; ++i) {
+            for (int j = 0; j < 6; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < 4; ++k) s += Bm[k][i] * Bm[k][j];
+                K[i * 10 + j] = s;
+            }
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += Bm[k][i] * rr[k];
+            b[i] = s;
+            for (int k = 0; k < 4; ++k) { K[i * 10 + 6 + k] = Cm[k][i]; K[(6 + k) * 10 + i] = Cm[k][i]; }
+        }
+        for (int k = 0; k < 4; ++k) b[6 + k] = e[k];
+        if (solve_dense(10, K, b)) return -1;
+        out[0][col] = b[0];
+        out[1][col] = b[1];
+        out[2][col] = 2.0 * b[2];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Compact WENO-Z candidates (Sec. 3.3 and the Appendix)                */
+/* ------------------------------------------------------------------ */
+/* Coordinate t = (x - x_i) / dx, origin at the centre of I_i; the left
+   interface value is taken at t = 1/2.  Cell I_{i+o} = [o - 1/2, o + 1/2].
+   A condition is (o, kind): kind 0 = cell average, kind 1 = dx * slope. */
+typedef struct { int n; int off[5]; int kind[5]; } substencil_t;
+
+/* S_0..S_6 and the cubic S~_1 (index 7) used only for beta_1. */
+static const substencil_t SUB[8] = {
+    {3, {-1, 0, -1}, {0, 0, 1}},                    /* S0 {W_{i-1}, W_i, W'_{i-1}} */
+    {3, {-1, 0, 1}, {0, 0, 0}},                     /* S1 {W_{i-1}, W_i, W_{i+1}} */
+    {4, {0, 1, 2, 2}, {0, 0, 0, 1}},                /* S2 {W_i, W_{i+1}, W_{i+2}, W'_{i+2}} */
+    {3, {-1, 0, 1}, {0, 0, 0}},                     /* S3 {W_{i-1}, W_i, W_{i+1}} */
+    {3, {0, 1, 2}, {0, 0, 0}},                      /* S4 {W_i, W_{i+1}, W_{i+2}} */
+    {5, {-1, 0, 1, -1, 0}, {0, 0, 0, 1, 1}},        /* S5 {W_{i-1}, W_i, W_{i+1}, W'_{i-1}, W'_i} */
+    {5, {0, 1, 2, 1, 2}, {0, 0, 0, 1, 1}},          /* S6 {W_i, W_{i+1}, W_{i+2}, W'_{i+1}, W'_{i+2}} */
+    {4, {-1, 0, 1, -1}, {0, 0, 0, 1}},              /* S~1 {W_{i-1}, W_i, W_{i+1}, W'_{i-1}} */
+};
+
+/* cand_map[k][m][c]: coefficient of t^m of w_k as a linear map of the eight
+   stencil data (c = 0..3 W_{i-1..i+2}, 4..7 D_{i-1..i+2}). */
+static double cand_map[8][5][8];
+
+static int build_candidates(void)
+{
+    memset(cand_map, 0, sizeof cand_map);
+    for (int k = 0; k < 8; ++k) {
+        int n = SUB[k].n;
+        for (int j = 0; j < n; ++j) {
+            double A[25], b[5];
+            for (int r = 0; r < n; ++r) {
+                double a = (double)SUB[k].off[r] - 0.5;
+                for (int m = 0; m < n; ++m)
+                    A[r * n + m] = SUB[k].kind[r] ? cell_dif_mono(a, m) : cell_avg_mono(a, m);
+                b[r] = (r == j) ? 1.0 : 0.0;
+            }
+            if (solve_dense(n, A, b)) return -1;
+            int col = SUB[k].off[j] + 1 + (SUB[k].kind[j] ? 4 : 0);
+            for (int m = 0; m < n; ++m) cand_map[k][m][col] += b[m];
+        }
+    }
+    return 0;
+}
+
+/* Printed linear weights d^6_k, d^8_k (Sec. 3.3). */
+static const double D6[7] = {33.0 / 700, 11.0 / 140, 22.0 / 175, 11.0 / 100, 11.0 / 100, 37.0 / 140, 37.0 / 140};
+static const double D8[7] = {3.0 / 98, 5.0 / 98, 4.0 / 49, 7.0 / 98, 7.0 / 98, 17.0 / 49, 17.0 / 49};
+static double weno_eps = 1e-6;
+
+/* Smoothness indicator, eq. (smooth-indicator): sum over q = 1..deg of
+   dx^(2q-1) * integral over I_i of (d^q w / dx^q)^2, which in the unit
+   coordinate t equals sum_q integral_{-1/2}^{1/2} (d^q w / dt^q)^2 dt. */
+static double beta_of(const double *b, int deg)
+{
+    double beta = 0.0;
+    double d[5];
+    for (int m = 0; m <= deg; ++m) d[m] = b[m];
+    int cur = deg;
+    for (int q = 1; q <= deg; ++q) {
+        for (int m = 0; m < cur; ++m) d[m] = (double)(m + 1) * d[m + 1];
+        cur -= 1;
+        /* integral of (sum_m d_m t^m)^2 over [-1/2, 1/2] */
+        for (int m1 = 0; m1 <= cur; ++m1)
+            for (int m2 = 0; m2 <= cur; ++m2) {
+                int p = m1 + m2;
+                if (p % 2) continue;
+                beta += d[m1] * d[m2] * 2.0 * ipow(0.5, p + 1) / (double)(p + 1);
+            }
+    }
+    return beta;
+}
+
+/* Left interface state of one scalar field from its stencil data.
+   Outputs: value, dx * derivative (reading A4), and optionally the
+   nonlinear weights delta[7] and indicators beta[7]. */
+static void weno_left(int order, const double *Wk, const double *Dk,
+                      double *val, double *der, double *delta_out, double *beta_out)
+{
+    double in[8];
+    for (int q = 0; q < 4; ++q) { in[q] = Wk[q]; in[4 + q] = Dk[q]; }
+    double coef[8][5];
+    for (int k = 0; k < 8; ++k)
+        for (int m = 0; m < 5; ++m) {
+            double s = 0.0;
+            for (int c = 0; c < 8; ++c) s += cand_map[k][m][c] * in[c];
+            coef[k][m] = s;
+        }
+    double w[7], wd[7], beta[7];
+    for (int k = 0; k < 7; ++k) {
+        int deg = SUB[k].n - 1;
+        double v = 0.0, dv = 0.0;
+        for (int m = 0; m <= deg; ++m) {
+            v += coef[k][m] * ipow(0.5, m);
+            if (m > 0) dv += (double)m * coef[k][m] * ipow(0.5, m - 1);
+        }
+        w[k] = v;
+        wd[k] = dv;
+        beta[k] = beta_of(coef[k], deg);
+    }
+    beta[1] = beta_of(coef[7], 3); /* beta_1 from the cubic w~_1 */
+    const double *d = (order == 8) ? D8 : D6;
+    double Z = fabs(3.0 * (beta[0] - beta[4]) + (beta[4] - beta[3]));
+    double alpha[7], asum = 0.0;
+    for (int k = 0; k < 7; ++k) { alpha[k] = d[k] * (1.0 + Z / (beta[k] + weno_eps)); asum += alpha[k]; }
+    double v = 0.0, dv = 0.0;
+    for (int k = 0; k < 7; ++k) {
+        double delta = alpha[k] / asum;
+        v += delta * w[k];
+        dv += delta * wd[k];
+        if (delta_out) delta_out[k] = delta;
+        if (beta_out) beta_out[k] = beta[k];
+    }
+    *val = v;
+    *der = dv;
+}
+
+/* Right state at x_{i+1/2} by mirror symmetry: reflect x -> -x, so the
+   stencil order reverses and every slope changes sign. */
+static void weno_right(int order, const double *Wk, const double *Dk, double *val, double *der)
+{
+    double Wm[4], Dm[4];
+    for (int q = 0; q < 4; ++q) { Wm[q] = Wk[3 - q]; Dm[q] = -Dk[3 - q]; }
+    double d;
+    weno_left(order, Wm, Dm, val, &d, NULL, NULL);
+    *der = -d;
+}
+
+/* ------------------------------------------------------------------ */
+/* Euler eigenvectors for the characteristic reconstruction              */
+/* ------------------------------------------------------------------ */
+/* Right eigenvectors of dF/dW in the normal ("x") direction, columns. */
+static int euler_R(int dim, double gamma, const double *W, double *R)
+{
+    int nv = dim + 2;
+    double rho = W[0], U = W[1] / rho, V = (dim == 2) ? W[2] / rho : 0.0;
+    double E = W[nv - 1];
+    double p = (gamma - 1.0) * (E - 0.5 * rho * (U * U + V * V));
+    if (!(rho > 0.0) || !(p > 0.0)) return ORC_ENONPHYS;
+    double c = sqrt(gamma * p / rho), H = (E + p) / rho;
+    memset(R, 0, sizeof(double) * nv * nv);
+    if (dim == 1) {
+        double cols[3][3] = {{1.0, U - c, H - U * c}, {1.0, U, 0.5 * U * U}, {1.0, U + c, H + U * c}};
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) R[r * 3 + k] = cols[k][r];
+    } else {
+        double cols[4][4] = {{1.0, U - c, V, H - U * c},
+                             {1.0, U, V, 0.5 * (U * U + V * V)},
+                             {0.0, 0.0, 1.0, V},
+                             {1.0, U + c, V, H + U * c}};
+        for (int r = 0; r < 4; ++r)
+            for (int k = 0; k < 4; ++k) R[r * 4 + k] = cols[k][r];
+    }
+    return ORC_OK;
+}
+
+static int invert(int n, const double *M, double *Minv)
+{
+    for (int c = 0; c < n; ++c) {
+        double A[16], b[4];
+        memcpy(A, M, sizeof(double) * n * n);
+        for (int r = 0; r < n; ++r) b[r] = (r == c) ? 1.0 : 0.0;
+        if (solve_dense(n, A, b)) return -1;
+        for (int r = 0; r < n; ++r) Minv[r * n + c] = b[r];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Polynomials in (u, v, xi^2) and Maxwellian moments (Sec. 2.1)         */
+/* ------------------------------------------------------------------ */
+#define PU 11
+#define PV 9
+#define PX 5
+typedef struct {
+    int du, dv, dx; /* extents in use (max degree + 1) */
+    double c[PU][PV][PX];
+} poly_t;
+
+static void poly_zero(poly_t *p) { memset(p, 0, sizeof *p); p->du = p->dv = p->dx = 1; }
+
+static void poly_set(poly_t *p, int a, int b, int x, double val)
+{
+    if (a >= PU || b >= PV || x >= PX) { fprintf(stderr, "oracle poly overflow\n"); abort(); }
+    p->c[a][b][x] += val;
+    if (a + 1 > p->du) p->du = a + 1;
+    if (b + 1 > p->dv) p->dv = b + 1;
+    if (x + 1 > p->dx) p->dx = x + 1;
+}
+
+/* a[0] + a[1] u (+ a[2] v) + a[nv-1] * (u^2 + v^2 + xi^2) / 2 */
+static void poly_lin(poly_t *p, int dim, const double *a)
+{
+    int nv = dim + 2;
+    poly_zero(p);
+    poly_set(p, 0, 0, 0, a[0]);
+    poly_set(p, 1, 0, 0, a[1]);
+    if (dim == 2) poly_set(p, 0, 1, 0, a[2]);
+    poly_set(p, 2, 0, 0, 0.5 * a[nv - 1]);
+    if (dim == 2) poly_set(p, 0, 2, 0, 0.5 * a[nv - 1]);
+    poly_set(p, 0, 0, 1, 0.5 * a[nv - 1]);
+}
+
+static void poly_mul(poly_t *r, const poly_t *p, const poly_t *q)
+{
+    poly_t t;
+    poly_zero(&t);
+    for (int a1 = 0; a1 < p->du; ++a1)
+        for (int b1 = 0; b1 < p->dv; ++b1)
+            for (int x1 = 0; x1 < p->dx; ++x1) {
+                double c1 = p->c[a1][b1][x1];
+                if (c1 == 0.0) continue;
+                for (int a2 = 0; a2 < q->du; ++a2)
+                    for (int b2 = 0; b2 < q->dv; ++b2)
+                        for (int x2 = 0; x2 < q->dx; ++x2) {
+                            double c2 = q->c[a2][b2][x2];
+                            if (c2 == 0.0) continue;
+                            poly_set(&t, a1 + a2, b1 + b2, x1 + x2, c1 * c2);
+                        }
+            }
+    *r = t;
+}
+
+/* r += s * p */
+static void poly_axpy(poly_t *r, double s, const poly_t *p)
+{
+    for (int a = 0; a < p->du; ++a)
+        for (int b = 0; b < p->dv; ++b)
+            for (int x = 0; x < p->dx; ++x)
+                if (p->c[a][b][x] != 0.0) poly_set(r, a, b, x, s * p->c[a][b][x]);
+}
+
+/* r = u^nu * v^nv2 * p */
+static void poly_shift(poly_t *r, const poly_t *p, int nu, int nv2)
+{
+    poly_t t;
+    poly_zero(&t);
+    for (int a = 0; a < p->du; ++a)
+        for (int b = 0; b < p->dv; ++b)
+            for (int x = 0; x < p->dx; ++x)
+                if (p->c[a][b][x] != 0.0) poly_set(&t, a + nu, b + nv2, x, p->c[a][b][x]);
+    *r = t;
+}
+
+/* Moments of a Maxwellian with unit density:
+   mu[n] = <u^n> over all u, mp[n] over u > 0, mn[n] over u < 0,
+   mv[n] = <v^n>, mx[m] = <(xi^2)^m>. */
+#define NM (PU + 3)
+typedef struct {
+    double rho, U, V, lam;
+    double mu[NM], mp[NM], mn[NM], mv[PV + 3], mx[PX + 2];
+} maxw_t;
+
+static int make_maxwellian(int dim, double gamma, double K, const double *W, maxw_t *m)
+{
+    int nv = dim + 2;
+    double rho = W[0];
+    if (!(rho > 0.0)) return ORC_ENONPHYS;
+    double U = W[1] / rho, V = (dim == 2) ? W[2] / rho : 0.0;
+    double p = (gamma - 1.0) * (W[nv - 1] - 0.5 * rho * (U * U + V * V));
+    if (!(p > 0.0)) return ORC_ENONPHYS;
+    double lam = rho / (2.0 * p);
+    m->rho = rho; m->U = U; m->V = V; m->lam = lam;
+    double h = 1.0 / (2.0 * lam);
+    m->mu[0] = 1.0; m->mu[1] = U;
+    m->mp[0] = 0.5 * erfc(-sqrt(lam) * U);
+    m->mn[0] = 0.5 * erfc(sqrt(lam) * U);
+    double tail = 0.5 * exp(-lam * U * U) / sqrt(M_PI * lam);
+    m->mp[1] = U * m->mp[0] + tail;
+    m->mn[1] = U * m->mn[0] - tail;
+    for (int n = 0; n + 2 < NM; ++n) {
+        m->mu[n + 2] = U * m->mu[n + 1] + (n + 1) * h * m->mu[n];
+        m->mp[n + 2] = U * m->mp[n + 1] + (n + 1) * h * m->mp[n];
+        m->mn[n + 2] = U * m->mn[n + 1] + (n + 1) * h * m->mn[n];
+    }
+    m->mv[0] = 1.0; m->mv[1] = V;
+    for (int n = 0; n + 2 < PV + 3; ++n) m->mv[n + 2] = V * m->mv[n + 1] + (n + 1) * h * m->mv[n];
+    if (dim == 1) for (int n = 1; n < PV + 3; ++n) m->mv[n] = 0.0;
+    m->mx[0] = 1.0;
+    for (int k = 1; k < PX + 2; ++k) m->mx[k] = m->mx[k - 1] * (K + 2.0 * (k - 1)) * h;
+    return ORC_OK;
+}
+
+/* <P> for the Maxwellian m with unit density; half: 0 all u, +1 u > 0, -1 u < 0 */
+static double moment(const poly_t *P, const maxw_t *m, int half)
+{
+    const double *mu = half > 0 ? m->mp : (half < 0 ? m->mn : m->mu);
+    double s = 0.0;
+    for (int a = 0; a < P->du; ++a)
+        for (int b = 0; b < P->dv; ++b)
+            for (int x = 0; x < P->dx; ++x) {
+                double c = P->c[a][b][x];
+                if (c != 0.0) s += c * mu[a] * m->mv[b] * m->mx[x];
+            }
+    return s;
+}
+
+/* out[k] = rho * < P * psi_k >, psi = (1, u, [v], (u^2 + v^2 + xi^2)/2) */
+static void psi_moments(int dim, const poly_t *P, const maxw_t *m, int half, double *out)
+{
+    int nv = dim + 2;
+    poly_t t, psi;
+    for (int k = 0; k < nv; ++k) {
+        double e[4] = {0, 0, 0, 0};
+        e[k] = 1.0;
+        poly_lin(&psi, dim, e);
+        poly_mul(&t, P, &psi);
+        out[k] = m->rho * moment(&t, m, half);
+    }
+}
+
+/* Solve <a psi> = b for the micro-coefficients a (linear in psi):
+   matrix entries rho * <psi_k psi_j>, solved numerically. */
+static int micro_solve(int dim, const maxw_t *m, const double *b, double *a)
+{
+    int nv = dim + 2;
+    double A[16], x[4];
+    poly_t pj;
+    for (int j = 0; j < nv; ++j) {
+        double e[4] = {0, 0, 0, 0};
+        e[j] = 1.0;
+        poly_lin(&pj, dim, e);
+        double col[4];
+        psi_moments(dim, &pj, m, 0, col);
+        for (int k = 0; k < nv; ++k) A[k * nv + j] = col[k];
+    }
+    for (int k = 0; k < nv; ++k) x[k] = b[k];
+    if (solve_dense(nv, A, x)) return ORC_ENONPHYS;
+    for (int k = 0; k < nv; ++k) a[k] = x[k];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Interface distribution and its moments (Sec. 2.1, 2.2, 4)             */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    /* equilibrium (linear reconstruction) data at the point, normal = x */
+    double W0[4], W0x[4], W0y[4], W0xx[4], W0xy[4], W0yy[4];
+    /* non-equilibrium (WENO-Z) left/right states and their derivatives */
+    double Wl[4], Wlx[4], Wly[4], Wr[4], Wrx[4], Wry[4];
+} gp_in_t;
+
+typedef struct {
+    double FL[4];  /* flux giving L(W^n) */
+    double FdL[4]; /* flux giving dL/dt(W^n) */
+    double S0[4], S1[4], S2[4]; /* interface state: f^n, f_t^n, f_tt^n moments */
+} gp_out_t;
+
+typedef struct { double gamma, K, mu, dt; int dim; } kin_par_t;
+
+/* time-fit coefficients of the e^{-t/tau_n} part (reading A1) */
+static void exp_fit(double tau_n, double dt, double *ke, double *kte, double *kde, double *kdte)
+{
+    /* time integrals of e^{-t/tau} and t e^{-t/tau} over [0, d] */
+    double d1 = 0.5 * dt, d2 = dt;
+    double Ie1 = tau_n * (1.0 - exp(-d1 / tau_n));
+    double Ie2 = tau_n * (1.0 - exp(-d2 / tau_n));
+    double It1 = tau_n * tau_n * (1.0 - exp(-d1 / tau_n)) - tau_n * d1 * exp(-d1 / tau_n);
+    double It2 = tau_n * tau_n * (1.0 - exp(-d2 / tau_n)) - tau_n * d2 * exp(-d2 / tau_n);
+    /* F(t) ~ a + b t with int_0^d (a + b t) dt matching at d = dt/2 and dt */
+    *ke = (4.0 * Ie1 - Ie2) / dt;
+    *kde = 4.0 * (Ie2 - 2.0 * Ie1) / (dt * dt);
+    *kte = (4.0 * It1 - It2) / dt;
+    *kdte = 4.0 * (It2 - 2.0 * It1) / (dt * dt);
+}
+
+/* rho > 0 and p > 0 */
+static int physical(int dim, double gamma, const double *W)
+{
+    int nv = dim + 2;
+    double rho = W[0];
+    if (!(rho > 0.0)) return 0;
+    double U = W[1] / rho, V = dim == 2 ? W[2] / rho : 0.0;
+    double p = (gamma - 1.0) * (W[nv - 1] - 0.5 * rho * (U * U + V * V));
+    return p > 0.0;
+}
+
+/* Equilibrium value at the interface from the non-equilibrium states
+   (reading A20): W0 = int psi [g_l H(u) + g_r (1 - H(u))] dXi. */
+static int kinetic_average(int dim, double gamma, double K, const double *Wl, const double *Wr, double *W0)
+{
+    int nv = dim + 2;
+    maxw_t gl, gr;
+    int st;
+    if ((st = make_maxwellian(dim, gamma, K, Wl, &gl))) return st;
+    if ((st = make_maxwellian(dim, gamma, K, Wr, &gr))) return st;
+    poly_t one;
+    double e1[4] = {1, 0, 0, 0}, a[4], b[4];
+    poly_lin(&one, dim, e1);
+    psi_moments(dim, &one, &gl, +1, a);
+    psi_moments(dim, &one, &gr, -1, b);
+    for (int k = 0; k < nv; ++k) W0[k] = a[k] + b[k];
+    return ORC_OK;
+}
+
+static int gks_point(const kin_par_t *kp, const gp_in_t *in, gp_out_t *out)
+{
+    int dim = kp->dim, nv = dim + 2;
+    maxw_t g0, gl, gr;
+    int st;
+    if ((st = make_maxwellian(dim, kp->gamma, kp->K, in->W0, &g0))) return st;
+    if ((st = make_maxwellian(dim, kp->gamma, kp->K, in->Wl, &gl))) return st;
+    if ((st = make_maxwellian(dim, kp->gamma, kp->K, in->Wr, &gr))) return st;
+
+    /* collision times (Sec. 4, readings A2, A10) */
+    double p0 = g0.rho / (2.0 * g0.lam), pl = gl.rho / (2.0 * gl.lam), pr = gr.rho / (2.0 * gr.lam);
+    double jump = fabs((pl - pr) / (pl + pr)) * kp->dt;
+    double tau = (kp->mu > 0.0) ? kp->mu / p0 : 0.0;
+    double tau_n = (kp->mu > 0.0) ? kp->mu / p0 + jump : 0.01 * kp->dt + jump;
+
+    /* spatial micro-slopes of g0: <abar_1 psi> = W_x, <abar_2 psi> = W_y */
+    double a1[4] = {0}, a2[4] = {0}, At[4] = {0}, rhs[4];
+    if ((st = micro_solve(dim, &g0, in->W0x, a1))) return st;
+    if (dim == 2 && (st = micro_solve(dim, &g0, in->W0y, a2))) return st;
+    poly_t A1, A2, AT, tmp, tmp2;
+    poly_lin(&A1, dim, a1);
+    poly_lin(&A2, dim, a2);
+    /* compatibility: <(abar_1 u + abar_2 v + Abar) psi> = 0 */
+    poly_shift(&tmp, &A1, 1, 0);
+    if (dim == 2) { poly_shift(&tmp2, &A2, 0, 1); poly_axpy(&tmp, 1.0, &tmp2); }
+    psi_moments(dim, &tmp, &g0, 0, rhs);
+    for (int k = 0; k < nv; ++k) rhs[k] = -rhs[k];
+    if ((st = micro_solve(dim, &g0, rhs, At))) return st;
+    poly_lin(&AT, dim, At);
+
+    /* second-order Taylor coefficients G = g_(..)/g0 (reading A3):
+       G_xx = a_xx + abar_1^2 with <G_xx psi> = W_xx, etc. */
+    poly_t Gxx, Gxy, Gyy, Gxt, Gyt, Gtt, prod, lin;
+    double c[4];
+#define SECOND(G, P1, P2, RHSVEC)                                     \
+    do {                                                              \
+        poly_mul(&prod, P1, P2);                                      \
+        double mm[4];                                                 \
+        psi_moments(dim, &prod, &g0, 0, mm);                          \
+        for (int k = 0; k < nv; ++k) rhs[k] = (RHSVEC)[k] - mm[k];    \
+        if ((st = micro_solve(dim, &g0, rhs, c))) return st;          \
+        poly_lin(&lin, dim, c);                                       \
+        G = prod;                                                     \
+        poly_axpy(&G, 1.0, &lin);                                     \
+    } while (0)
+    double zero[4] = {0, 0, 0, 0};
+    SECOND(Gxx, &A1, &A1, in->W0xx);
+    if (dim == 2) {
+        SECOND(Gxy, &A1, &A2, in->W0xy);
+        SECOND(Gyy, &A2, &A2, in->W0yy);
+    } else {
+        poly_zero(&Gxy);
+        poly_zero(&Gyy);
+    }
+    /* x-derivative of the compatibility condition:
+       <(G_xx u + G_xy v + G_xt) psi> = 0 */
+    double vt[4];
+    poly_shift(&tmp, &Gxx, 1, 0);
+    if (dim == 2) { poly_shift(&tmp2, &Gxy, 0, 1); poly_axpy(&tmp, 1.0, &tmp2); }
+    psi_moments(dim, &tmp, &g0, 0, vt);
+    for (int k = 0; k < nv; ++k) vt[k] = -vt[k];
+    SECOND(Gxt, &A1, &AT, vt);
+    if (dim == 2) {
+        poly_shift(&tmp, &Gxy, 1, 0);
+        poly_shift(&tmp2, &Gyy, 0, 1);
+        poly_axpy(&tmp, 1.0, &tmp2);
+        psi_moments(dim, &tmp, &g0, 0, vt);
+        for (int k = 0; k < nv; ++k) vt[k] = -vt[k];
+        SECOND(Gyt, &A2, &AT, vt);
+    } else {
+        poly_zero(&Gyt);
+    }
+    /* t-derivative: <(G_xt u + G_yt v + G_tt) psi> = 0 */
+    poly_shift(&tmp, &Gxt, 1, 0);
+    if (dim == 2) { poly_shift(&tmp2, &Gyt, 0, 1); poly_axpy(&tmp, 1.0, &tmp2); }
+    psi_moments(dim, &tmp, &g0, 0, vt);
+    for (int k = 0; k < nv; ++k) vt[k] = -vt[k];
+    SECOND(Gtt, &AT, &AT, vt);
+#undef SECOND
+    (void)zero;
+
+    /* micro-slopes of the non-equilibrium states */
+    double al1[4] = {0}, al2[4] = {0}, ar1[4] = {0}, ar2[4] = {0};
+    if ((st = micro_solve(dim, &gl, in->Wlx, al1))) return st;
+    if ((st = micro_solve(dim, &gr, in->Wrx, ar1))) return st;
+    if (dim == 2) {
+        if ((st = micro_solve(dim, &gl, in->Wly, al2))) return st;
+        if ((st = micro_solve(dim, &gr, in->Wry, ar2))) return st;
+    }
+    poly_t AL1, AL2, AR1, AR2;
+    poly_lin(&AL1, dim, al1);
+    poly_lin(&AL2, dim, al2);
+    poly_lin(&AR1, dim, ar1);
+    poly_lin(&AR2, dim, ar2);
+
+    /* f(t) = g0 [E0 + E1 t + E2 t^2] + e^{-t/tau_n} [X0 + X1 t]:
+       E0 = 1 - tau (abar_1 u + abar_2 v + Abar)
+       E1 = Abar - tau (G_xt u + G_yt v + G_tt)
+       E2 = G_tt / 2
+       X0 = -g0 + g_l H(u) + g_r (1 - H(u))
+       X1 = g0 (abar_1 u + abar_2 v) - g_l (a_1l u + a_2l v) H(u) - g_r (a_1r u + a_2r v)(1 - H(u)) */
+    poly_t E0, E1, one, adv0, advl, advr;
+    double e1[4] = {1, 0, 0, 0};
+    poly_lin(&one, dim, e1);
+    poly_shift(&adv0, &A1, 1, 0);
+    if (dim == 2) { poly_shift(&tmp, &A2, 0, 1); poly_axpy(&adv0, 1.0, &tmp); }
+    poly_shift(&advl, &AL1, 1, 0);
+    if (dim == 2) { poly_shift(&tmp, &AL2, 0, 1); poly_axpy(&advl, 1.0, &tmp); }
+    poly_shift(&advr, &AR1, 1, 0);
+    if (dim == 2) { poly_shift(&tmp, &AR2, 0, 1); poly_axpy(&advr, 1.0, &tmp); }
+    E0 = one;
+    poly_axpy(&E0, -tau, &adv0);
+    poly_axpy(&E0, -tau, &AT);
+    E1 = AT;
+    poly_shift(&tmp, &Gxt, 1, 0);
+    poly_axpy(&E1, -tau, &tmp);
+    if (dim == 2) { poly_shift(&tmp, &Gyt, 0, 1); poly_axpy(&E1, -tau, &tmp); }
+    poly_axpy(&E1, -tau, &Gtt);
+
+    double ke, kte, kde, kdte;
+    exp_fit(tau_n, kp->dt, &ke, &kte, &kde, &kdte);
+
+    for (int w = 0; w < 2; ++w) {
+        /* w = 0: u-weighted moments (flux); w = 1: plain moments (state) */
+        int sh = (w == 0) ? 1 : 0;
+        poly_t P;
+        double m0[4], m1[4], m2[4], xe0[4], xe1[4], xl[4], xr[4];
+        poly_shift(&P, &E0, sh, 0); psi_moments(dim, &P, &g0, 0, m0);
+        poly_shift(&P, &E1, sh, 0); psi_moments(dim, &P, &g0, 0, m1);
+        poly_shift(&P, &Gtt, sh, 0); psi_moments(dim, &P, &g0, 0, m2);
+        /* X0 */
+        poly_shift(&P, &one, sh, 0);
+        psi_moments(dim, &P, &g0, 0, xe0);
+        psi_moments(dim, &P, &gl, +1, xl);
+        psi_moments(dim, &P, &gr, -1, xr);
+        double Me[4], Mte[4];
+        for (int k = 0; k < nv; ++k) Me[k] = -xe0[k] + xl[k] + xr[k];
+        /* X1 */
+        poly_shift(&P, &adv0, sh, 0); psi_moments(dim, &P, &g0, 0, xe1);
+        poly_shift(&P, &advl, sh, 0); psi_moments(dim, &P, &gl, +1, xl);
+        poly_shift(&P, &advr, sh, 0); psi_moments(dim, &P, &gr, -1, xr);
+        for (int k = 0; k < nv; ++k) Mte[k] = xe1[k] - xl[k] - xr[k];
+        for (int k = 0; k < nv; ++k) {
+            double a = m0[k] + ke * Me[k] + kte * Mte[k];
+            double b = m1[k] + kde * Me[k] + kdte * Mte[k];
+            if (w == 0) { out->FL[k] = a; out->FdL[k] = b; }
+            else { out->S0[k] = a; out->S1[k] = b; out->S2[k] = m2[k]; }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Problem state, boundary layers, sweeps and the MSMD step              */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int dim, nv, nx, ny, gx, gy, sx, sy;
+    double dx, dy, gamma, K, mu, cfl, dt_fixed, t_end;
+    int order, recon, bc[4];
+} prob_t;
+
+#define CELL(P, i, j) (((size_t)((j) + (P)->gy) * (P)->sx + (size_t)((i) + (P)->gx)) * (P)->nv)
+
+enum { BC_PERIODIC = 0, BC_EXTRAP = 1 };
+
+/* Two ghost layers per side.  Periodic: wrap.  Extrapolated (reading A16):
+   ghost average = boundary average, ghost normal slope = 0, ghost
+   tangential slope = boundary tangential slope.  x first (interior rows),
+   then y over all columns so that corners are filled. */
+static void fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy)
+{
+    int nv = P->nv;
+    for (int j = 0; j < P->ny; ++j)
+        for (int g = 1; g <= P->gx; ++g) {
+            int dst[2] = {-g, P->nx - 1 + g};
+            for (int side = 0; side < 2; ++side) {
+                int per = P->bc[side] == BC_PERIODIC;
+                int src = per ? (side == 0 ? P->nx - g : g - 1) : (side == 0 ? 0 : P->nx - 1);
+                size_t d = CELL(P, dst[side], j), s = CELL(P, src, j);
+                for (int k = 0; k < nv; ++k) {
+                    W[d + k] = W[s + k];
+                    Wx[d + k] = per ? Wx[s + k] : 0.0;
+                    if (Wy) Wy[d + k] = Wy[s + k];
+                }
+            }
+        }
+    if (P->dim == 1) return;
+    for (int i = -P->gx; i < P->nx + P->gx; ++i)
+        for (int g = 1; g <= P->gy; ++g) {
+            int dst[2] = {-g, P->ny - 1 + g};
+            for (int side = 0; side < 2; ++side) {
+                int per = P->bc[2 + side] == BC_PERIODIC;
+                int src = per ? (side == 0 ? P->ny - g : g - 1) : (side == 0 ? 0 : P->ny - 1);
+                size_t d = CELL(P, i, dst[side]), s = CELL(P, i, src);
+                for (int k = 0; k < nv; ++k) {
+                    W[d + k] = W[s + k];
+                    Wx[d + k] = Wx[s + k];
+                    Wy[d + k] = per ? Wy[s + k] : 0.0;
+                }
+            }
+        }
+}
+
+/* Along direction dir (0 = x, 1 = y), the local frame puts the normal
+   velocity in slot 1: swap the momentum slots for y. */
+static void to_local(int dim, int dir, const double *a, double *b)
+{
+    int nv = dim + 2;
+    for (int k = 0; k < nv; ++k) b[k] = a[k];
+    if (dir == 1) { b[1] = a[2]; b[2] = a[1]; }
+}
+
+/* One face row: the face between cells c and c+1 along dir at transverse
+   index t.  Output, in the local frame: [0] W0, [1] dn W0, [2] dnn W0,
+   [3] Wl, [4] Wr, [5] dn Wl, [6] dn Wr. */
+static int face_row(const prob_t *P, const double *W, const double *Wx, const double *Wy,
+                    int dir, int c, int t, double out[7][4])
+{
+    int nv = P->nv;
+    double h = dir == 0 ? P->dx : P->dy;
+    const double *S = dir == 0 ? Wx : Wy;
+    double Wk[4][4], Dk[4][4];
+    for (int q = 0; q < 4; ++q) {
+        int ci = dir == 0 ? c - 1 + q : t, cj = dir == 0 ? t : c - 1 + q;
+        size_t o = CELL(P, ci, cj);
+        double d[4];
+        for (int k = 0; k < nv; ++k) d[k] = h * S[o + k];
+        to_local(P->dim, dir, W + o, Wk[q]);
+        to_local(P->dim, dir, d, Dk[q]);
+    }
+    const double (*L)[8] = lin_map[P->order == 8 ? 1 : 0];
+    for (int k = 0; k < nv; ++k) {
+        double r[3] = {0, 0, 0};
+        for (int row = 0; row < 3; ++row)
+            for (int q = 0; q < 4; ++q) r[row] += L[row][q] * Wk[q][k] + L[row][4 + q] * Dk[q][k];
+        out[0][k] = r[0];
+        out[1][k] = r[1] / h;
+        out[2][k] = r[2] / (h * h);
+    }
+    if (P->recon == 0) {
+        for (int k = 0; k < nv; ++k) {
+            out[3][k] = out[4][k] = out[0][k];
+            out[5][k] = out[6][k] = out[1][k];
+        }
+        return ORC_OK;
+    }
+    /* characteristic WENO-Z (reading A6: frame at the mean of I_i, I_{i+1}) */
+    double Wm[4] = {0, 0, 0, 0}, R[16], Linv[16];
+    for (int k = 0; k < nv; ++k) Wm[k] = 0.5 * (Wk[1][k] + Wk[2][k]);
+    int st = euler_R(P->dim, P->gamma, Wm, R);
+    if (st) return st;
+    if (invert(nv, R, Linv)) return ORC_ENONPHYS;
+    double Q[4][4], QD[4][4];
+    for (int q = 0; q < 4; ++q)
+        for (int a = 0; a < nv; ++a) {
+            double s = 0.0, sd = 0.0;
+            for (int k = 0; k < nv; ++k) { s += Linv[a * nv + k] * Wk[q][k]; sd += Linv[a * nv + k] * Dk[q][k]; }
+            Q[q][a] = s;
+            QD[q][a] = sd;
+        }
+    double ql[4], qr[4], qlx[4], qrx[4];
+    for (int a = 0; a < nv; ++a) {
+        double wv[4], dv[4];
+        for (int q = 0; q < 4; ++q) { wv[q] = Q[q][a]; dv[q] = QD[q][a]; }
+        weno_left(P->order, wv, dv, &ql[a], &qlx[a], NULL, NULL);
+        weno_right(P->order, wv, dv, &qr[a], &qrx[a]);
+    }
+    for (int k = 0; k < nv; ++k) {
+        double sl = 0, sr = 0, slx = 0, srx = 0;
+        for (int a = 0; a < nv; ++a) {
+            sl += R[k * nv + a] * ql[a];
+            sr += R[k * nv + a] * qr[a];
+            slx += R[k * nv + a] * qlx[a];
+            srx += R[k * nv + a] * qrx[a];
+        }
+        out[3][k] = sl;
+        out[4][k] = sr;
+        out[5][k] = slx / h;
+        out[6][k] = srx / h;
+    }
+    /* positivity fallback (reading A21) */
+    if (!physical(P->dim, P->gamma, out[3])) for (int k = 0; k < nv; ++k) out[3][k] = Wk[1][k];
+    if (!physical(P->dim, P->gamma, out[4])) for (int k = 0; k < nv; ++k) out[4][k] = Wk[2][k];
+    return ORC_OK;
+}
+
+/* Tangential linear 5th-order reconstruction (Sec. 3.1): the quartic whose
+   averages over the five rows j-2..j+2 are the given line values; value and
+   first two derivatives (per unit row width) at the three Gauss points. */
+static double tan_map[3][3][5]; /* [gauss point][derivative order][row] */
+static const double GAUSS_W[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+static int build_tangential(void)
+{
+    double gs[3] = {-sqrt(0.6), 0.0, sqrt(0.6)};
+    for (int r = 0; r < 5; ++r) {
+        double A[25], b[5];
+        for (int q = 0; q < 5; ++q) {
+            double a = (double)(q - 2) - 0.5;
+            for (int m = 0; m < 5; ++m) A[q * 5 + m] = cell_avg_mono(a, m);
+            b[q] = (q == r) ? 1.0 : 0.0;
+        }
+        if (solve_dense(5, A, b)) return -1;
+        for (int g = 0; g < 3; ++g) {
+            double eta = 0.5 * gs[g];
+            double v = 0, d1 = 0, d2 = 0;
+            for (int m = 0; m < 5; ++m) {
+                v += b[m] * ipow(eta, m);
+                if (m >= 1) d1 += m * b[m] * ipow(eta, m - 1);
+                if (m >= 2) d2 += m * (m - 1) * b[m] * ipow(eta, m - 2);
+            }
+            tan_map[g][0][r] = v;
+            tan_map[g][1][r] = d1;
+            tan_map[g][2][r] = d2;
+        }
+    }
+    return 0;
+}
+
+/* Tangential WENO-Z of the non-equilibrium states (reading A8). */
+static double tw_cand[3][3][5]; /* [gauss point][candidate][row]: candidate value at the point */
+static double tw_coef[3][3][5]; /* [candidate][power of eta][row] */
+static double tw_lin[3][3];     /* [gauss point][candidate]: linear weights */
+
+static int build_tan_weno(void)
+{
+    double gs[3] = {-sqrt(0.6), 0.0, sqrt(0.6)};
+    memset(tw_coef, 0, sizeof tw_coef);
+    for (int k = 0; k < 3; ++k)          /* candidate k uses rows j-2+k .. j+k */
+        for (int r = 0; r < 3; ++r) {
+            double A[9], b[3];
+            for (int q = 0; q < 3; ++q) {
+                double a = (double)(k - 2 + q) - 0.5;
+                for (int m = 0; m < 3; ++m) A[q * 3 + m] = cell_avg_mono(a, m);
+                b[q] = (q == r) ? 1.0 : 0.0;
+            }
+            if (solve_dense(3, A, b)) return -1;
+            for (int m = 0; m < 3; ++m) tw_coef[k][m][k + r] = b[m];
+        }
+    for (int g = 0; g < 3; ++g) {
+        double eta = 0.5 * gs[g];
+        for (int k = 0; k < 3; ++k)
+            for (int r = 0; r < 5; ++r)
+                tw_cand[g][k][r] = tw_coef[k][0][r] + tw_coef[k][1][r] * eta + tw_coef[k][2][r] * eta * eta;
+        /* sum_k d_k cand_k(eta) equals the quartic's value at eta for every
+           row data: normal equations over the five unit data vectors (the
+           system is consistent, so this is exact) */
+        double A[9] = {0}, b[3] = {0};
+        for (int r = 0; r < 5; ++r)
+            for (int k1 = 0; k1 < 3; ++k1) {
+                for (int k2 = 0; k2 < 3; ++k2) A[k1 * 3 + k2] += tw_cand[g][k1][r] * tw_cand[g][k2][r];
+                b[k1] += tw_cand[g][k1][r] * tan_map[g][0][r];
+            }
+        if (solve_dense(3, A, b)) return -1;
+        for (int k = 0; k < 3; ++k) tw_lin[g][k] = b[k];
+    }
+    return 0;
+}
+
+/* value at Gauss point g from the five row line values q[0..4] (rows j-2..j+2) */
+static double tan_weno_value(int g, const double *q)
+{
+    double cand[3], beta[3];
+    for (int k = 0; k < 3; ++k) {
+        double c[3] = {0, 0, 0};
+        cand[k] = 0.0;
+        for (int r = 0; r < 5; ++r) {
+            cand[k] += tw_cand[g][k][r] * q[r];
+            for (int m = 0; m < 3; ++m) c[m] += tw_coef[k][m][r] * q[r];
+        }
+        beta[k] = beta_of(c, 2);
+    }
+    double Z = fabs(beta[0] - beta[2]);
+    double gp[3], gm[3], sp = 0.0, sm = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double d = tw_lin[g][k];
+        gp[k] = 0.5 * (d + 3.0 * fabs(d));
+        gm[k] = gp[k] - d;
+        sp += gp[k];
+        sm += gm[k];
+    }
+    double val = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        double *gw = pass ? gm : gp, sig = pass ? sm : sp;
+        if (sig == 0.0) continue;
+        double a[3], as = 0.0, v = 0.0;
+        for (int k = 0; k < 3; ++k) { a[k] = gw[k] / sig * (1.0 + Z / (beta[k] + weno_eps)); as += a[k]; }
+        for (int k = 0; k < 3; ++k) v += a[k] / as * cand[k];
+        val += (pass ? -sig : sig) * v;
+    }
+    return val;
+}
+
+static int initialised = 0;
+static int init_tables(void)
+{
+    if (initialised) return 0;
+    if (build_p7(lin_map[1]) || build_p5(lin_map[0]) || build_candidates() || build_tangential() || build_tan_weno()) return -1;
+    initialised = 1;
+    return 0;
+}
+
+/* Per-face outputs of one stage, Gauss-averaged over the face (2-D). */
+typedef struct { double *FL, *FdL, *S0, *S1, *S2; } faces_t;
+
+/* Sweep along dir: fill the face arrays (global frame).  x faces are
+   indexed [j][i] with i = 0..nx (face i is the left face of cell i), y faces
+   [j][i] with j = 0..ny. */
+static int sweep(const prob_t *P, const double *W, const double *Wx, const double *Wy, int dir,
+                 double dt, faces_t *F)
+{
+    int nv = P->nv, dim = P->dim;
+    kin_par_t kp = {P->gamma, P->K, P->mu, dt, dim};
+    int nf = dir == 0 ? P->nx + 1 : P->ny + 1;  /* faces along dir */
+    int nt = dir == 0 ? P->ny : P->nx;          /* transverse interior count */
+    double h_t = dir == 0 ? P->dy : P->dx;
+    int status = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int f = 0; f < nf; ++f) {
+        if (status) continue;
+        int c = f - 1; /* face between cells c and c+1 */
+        for (int t = 0; t < nt; ++t) {
+            double acc[5][4];
+            memset(acc, 0, sizeof acc);
+            int st = ORC_OK;
+            if (dim == 1) {
+                double row[7][4];
+                st = face_row(P, W, Wx, Wy, dir, c, t, row);
+                if (!st) {
+                    gp_in_t in;
+                    memset(&in, 0, sizeof in);
+                    for (int k = 0; k < nv; ++k) {
+                        in.W0[k] = row[0][k]; in.W0x[k] = row[1][k]; in.W0xx[k] = row[2][k];
+                        in.Wl[k] = row[3][k]; in.Wr[k] = row[4][k];
+                        in.Wlx[k] = row[5][k]; in.Wrx[k] = row[6][k];
+                    }
+                    if (P->recon) st = kinetic_average(dim, P->gamma, P->K, in.Wl, in.Wr, in.W0);
+                    gp_out_t o;
+                    if (!st) st = gks_point(&kp, &in, &o);
+                    if (!st)
+                        for (int k = 0; k < nv; ++k) {
+                            acc[0][k] = o.FL[k]; acc[1][k] = o.FdL[k];
+                            acc[2][k] = o.S0[k]; acc[3][k] = o.S1[k]; acc[4][k] = o.S2[k];
+                        }
+                }
+            } else {
+                double rows[5][7][4];
+                for (int r = 0; r < 5 && !st; ++r) st = face_row(P, W, Wx, Wy, dir, c, t - 2 + r, rows[r]);
+                for (int g = 0; g < 3 && !st; ++g) {
+                    gp_in_t in;
+                    memset(&in, 0, sizeof in);
+                    for (int k = 0; k < nv; ++k) {
+                        double v[7] = {0}, d1[7] = {0}, d2 = 0;
+                        for (int q = 0; q < 7; ++q)
+                            for (int r = 0; r < 5; ++r) {
+                                v[q] += tan_map[g][0][r] * rows[r][q][k];
+                                d1[q] += tan_map[g][1][r] * rows[r][q][k];
+                            }
+                        for (int r = 0; r < 5; ++r) d2 += tan_map[g][2][r] * rows[r][0][k];
+                        in.W0[k] = v[0]; in.W0x[k] = v[1]; in.W0xx[k] = v[2];
+                        in.W0y[k] = d1[0] / h_t; in.W0xy[k] = d1[1] / h_t; in.W0yy[k] = d2 / (h_t * h_t);
+                        in.Wl[k] = v[3]; in.Wr[k] = v[4]; in.Wlx[k] = v[5]; in.Wrx[k] = v[6];
+                        in.Wly[k] = d1[3] / h_t; in.Wry[k] = d1[4] / h_t;
+                    }
+                    if (P->recon) {
+                        /* non-equilibrium values by tangential WENO-Z (A8), fallback (A21) */
+                        for (int side = 0; side < 2; ++side) {
+                            double *dst = side ? in.Wr : in.Wl;
+                            for (int k = 0; k < nv; ++k) {
+                                double q[5];
+                                for (int r = 0; r < 5; ++r) q[r] = rows[r][3 + side][k];
+                                dst[k] = tan_weno_value(g, q);
+                            }
+                            if (!physical(dim, P->gamma, dst))
+                                for (int k = 0; k < nv; ++k) dst[k] = rows[2][3 + side][k];
+                        }
+                    }
+                    if (P->recon) st = kinetic_average(dim, P->gamma, P->K, in.Wl, in.Wr, in.W0);
+                    gp_out_t o;
+                    if (!st) st = gks_point(&kp, &in, &o);
+                    if (!st)
+                        for (int k = 0; k < nv; ++k) {
+                            acc[0][k] += GAUSS_W[g] * o.FL[k]; acc[1][k] += GAUSS_W[g] * o.FdL[k];
+                            acc[2][k] += GAUSS_W[g] * o.S0[k]; acc[3][k] += GAUSS_W[g] * o.S1[k];
+                            acc[4][k] += GAUSS_W[g] * o.S2[k];
+                        }
+                }
+            }
+            if (st) {
+#pragma omp critical
+                status = st;
+                break;
+            }
+            size_t o = dir == 0 ? ((size_t)t * (P->nx + 1) + f) * nv : ((size_t)f * P->nx + t) * nv;
+            double *dst[5] = {F->FL, F->FdL, F->S0, F->S1, F->S2};
+            for (int q = 0; q < 5; ++q) {
+                double g[4];
+                to_local(dim, dir, acc[q], g); /* the swap is its own inverse */
+                for (int k = 0; k < nv; ++k) dst[q][o + k] = g[k];
+            }
+        }
+    }
+    return status;
+}
+
+static double max_signal(const prob_t *P, const double *W, int *bad)
+{
+    /* dt rule (reading A12): CFL * min over cells of dx/(|U|+c) [, dy/(|V|+c)] */
+    double best = 0.0;
+    int nv = P->nv;
+    for (int j = 0; j < P->ny; ++j)
+        for (int i = 0; i < P->nx; ++i) {
+            const double *w = W + CELL(P, i, j);
+            double rho = w[0], U = w[1] / rho, V = P->dim == 2 ? w[2] / rho : 0.0;
+            double p = (P->gamma - 1.0) * (w[nv - 1] - 0.5 * rho * (U * U + V * V));
+            if (!(rho > 0.0) || !(p > 0.0)) { *bad = 1; return 0.0; }
+            double c = sqrt(P->gamma * p / rho);
+            double s = (fabs(U) + c) / P->dx;
+            if (P->dim == 2) { double sy = (fabs(V) + c) / P->dy; if (sy > s) s = sy; }
+            if (s > best) best = s;
+        }
+    return best;
+}
+
+/* cell operator: Lc = -(F_{i+1/2} - F_{i-1/2})/dx - (G_{j+1/2} - G_{j-1/2})/dy */
+static void cell_operator(const prob_t *P, const double *fx, const double *fy, double *out)
+{
+    int nv = P->nv;
+    for (int j = 0; j < P->ny; ++j)
+        for (int i = 0; i < P->nx; ++i)
+            for (int k = 0; k < nv; ++k) {
+                double v = -(fx[((size_t)j * (P->nx + 1) + i + 1) * nv + k] - fx[((size_t)j * (P->nx + 1) + i) * nv + k]) / P->dx;
+                if (P->dim == 2)
+                    v -= (fy[((size_t)(j + 1) * P->nx + i) * nv + k] - fy[((size_t)j * P->nx + i) * nv + k]) / P->dy;
+                out[((size_t)j * P->nx + i) * nv + k] = v;
+            }
+}
+
+/* Gauss formula (Sec. 3.1): cell-averaged slope from interface values. */
+static void slopes_from_faces(const prob_t *P, const double *vx, const double *vy, double *Wx, double *Wy)
+{
+    int nv = P->nv;
+    for (int j = 0; j < P->ny; ++j)
+        for (int i = 0; i < P->nx; ++i)
+            for (int k = 0; k < nv; ++k) {
+                size_t o = CELL(P, i, j) + k;
+                Wx[o] = (vx[((size_t)j * (P->nx + 1) + i + 1) * nv + k] - vx[((size_t)j * (P->nx + 1) + i) * nv + k]) / P->dx;
+                if (P->dim == 2)
+                    Wy[o] = (vy[((size_t)(j + 1) * P->nx + i) * nv + k] - vy[((size_t)j * P->nx + i) * nv + k]) / P->dy;
+            }
+}
+
+static int stage(const prob_t *P, const double *W, const double *Wx, const double *Wy, double dt,
+                 faces_t *Fx, faces_t *Fy, double *L, double *dL)
+{
+    int st = sweep(P, W, Wx, Wy, 0, dt, Fx);
+    if (st) return st;
+    if (P->dim == 2 && (st = sweep(P, W, Wx, Wy, 1, dt, Fy))) return st;
+    cell_operator(P, Fx->FL, P->dim == 2 ? Fy->FL : NULL, L);
+    cell_operator(P, Fx->FdL, P->dim == 2 ? Fy->FdL : NULL, dL);
+    return ORC_OK;
+}
+
+static int faces_alloc(faces_t *F, size_t n)
+{
+    F->FL = calloc(n, sizeof(double)); F->FdL = calloc(n, sizeof(double));
+    F->S0 = calloc(n, sizeof(double)); F->S1 = calloc(n, sizeof(double)); F->S2 = calloc(n, sizeof(double));
+    return (F->FL && F->FdL && F->S0 && F->S1 && F->S2) ? 0 : -1;
+}
+static void faces_free(faces_t *F) { free(F->FL); free(F->FdL); free(F->S0); free(F->S1); free(F->S2); }
+
+/* ------------------------------------------------------------------ */
+/* Public entry points (called from Python through ctypes)              */
+/* ------------------------------------------------------------------ */
+
+/* Run a problem.  W, Wx, Wy: interior arrays [ny][nx][nv] (conservative
+   averages and cell-averaged gradients), updated in place.  Stops at t_end
+   or after max_steps steps (max_steps <= 0: no limit).  dt_fixed > 0 gives
+   a constant step (clipped to t_end); otherwise CFL.  Returns 0, or
+   ORC_ENONPHYS / ORC_EINVAL; *t and *nsteps report progress either way. */
+int orc_run(int dim, int nx, int ny, double xlo, double xhi, double ylo, double yhi,
+            double gamma, double mu, double cfl, double dt_fixed, double t_end, int max_steps,
+            int order, int recon, const int *bc,
+            double *W, double *Wx, double *Wy, double *t_io, long *nsteps_out)
+{
+    if (init_tables()) return ORC_EINVAL;
+    if ((dim != 1 && dim != 2) || nx < 4 || (dim == 2 && ny < 4) || !(gamma > 1.0) || (order != 6 && order != 8))
+        return ORC_EINVAL;
+    prob_t P;
+    memset(&P, 0, sizeof P);
+    P.dim = dim; P.nv = dim + 2; P.nx = nx; P.ny = dim == 2 ? ny : 1;
+    P.gx = 2; P.gy = dim == 2 ? 2 : 0;
+    P.sx = nx + 2 * P.gx; P.sy = P.ny + 2 * P.gy;
+    P.dx = (xhi - xlo) / nx; P.dy = dim == 2 ? (yhi - ylo) / ny : 1.0;
+    P.gamma = gamma; P.mu = mu; P.cfl = cfl; P.dt_fixed = dt_fixed; P.t_end = t_end;
+    P.K = dim == 1 ? (3.0 - gamma) / (gamma - 1.0) : (4.0 - 2.0 * gamma) / (gamma - 1.0);
+    P.order = order; P.recon = recon;
+    for (int k = 0; k < 4; ++k) P.bc[k] = bc[k];
+    int nv = P.nv;
+    size_t ncell = (size_t)P.sx * P.sy * nv, nint = (size_t)nx * P.ny * nv;
+    size_t nfx = (size_t)(nx + 1) * P.ny * nv, nfy = dim == 2 ? (size_t)nx * (P.ny + 1) * nv : 1;
+
+    double *Wn = calloc(ncell, sizeof(double)), *Wxn = calloc(ncell, sizeof(double)), *Wyn = calloc(ncell, sizeof(double));
+    double *Ws = calloc(ncell, sizeof(double)), *Wxs = calloc(ncell, sizeof(double)), *Wys = calloc(ncell, sizeof(double));
+    double *L = calloc(nint, sizeof(double)), *dL = calloc(nint, sizeof(double));
+    double *Ls = calloc(nint, sizeof(double)), *dLs = calloc(nint, sizeof(double));
+    double *vx = calloc(nfx, sizeof(double)), *vy = calloc(nfy, sizeof(double));
+    faces_t Fx, Fy, Fxs, Fys;
+    int st = ORC_OK;
+    if (!Wn || !Wxn || !Wyn || !Ws || !Wxs || !Wys || !L || !dL || !Ls || !dLs || !vx || !vy ||
+        faces_alloc(&Fx, nfx) || faces_alloc(&Fy, nfy) || faces_alloc(&Fxs, nfx) || faces_alloc(&Fys, nfy))
+        st = ORC_EINVAL;
+
+    for (int j = 0; j < P.ny && !st; ++j)
+        for (int i = 0; i < nx; ++i)
+            for (int k = 0; k < nv; ++k) {
+                size_t o = CELL(&P, i, j) + k, s = ((size_t)j * nx + i) * nv + k;
+                Wn[o] = W[s]; Wxn[o] = Wx[s];
+                if (dim == 2) Wyn[o] = Wy[s];
+            }
+
+    /* Step rule (readings A12, A13): dt = dt_fixed when given, else the CFL
+       step; a step that would reach or pass t_end (within 1e-9 dt) is
+       shortened to end exactly at t_end. */
+    double t = *t_io;
+    long n = 0;
+    for (;;) {
+        if (st || (max_steps > 0 && n >= max_steps) || !(t < t_end)) break;
+        double dt;
+        int last = 0;
+        if (dt_fixed > 0.0) {
+            dt = dt_fixed;
+        } else {
+            int bad = 0;
+            double s = max_signal(&P, Wn, &bad);
+            if (bad || !(s > 0.0)) { st = ORC_ENONPHYS; break; }
+            dt = cfl / s;
+        }
+        if (t + dt >= t_end - 1e-9 * dt) { dt = t_end - t; last = 1; }
+
+        /* stage 1 at t^n */
+        fill_ghosts(&P, Wn, Wxn, dim == 2 ? Wyn : NULL);
+        if ((st = stage(&P, Wn, Wxn, Wyn, dt, &Fx, &Fy, L, dL))) break;
+        /* W* = W^n + dt/2 L^n + dt^2/8 dL^n */
+        for (int j = 0; j < P.ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                for (int k = 0; k < nv; ++k) {
+                    size_t o = CELL(&P, i, j) + k, s = ((size_t)j * nx + i) * nv + k;
+                    Ws[o] = Wn[o] + 0.5 * dt * L[s] + 0.125 * dt * dt * dL[s];
+                }
+        /* f* = f^n + dt/2 f_t^n + dt^2/8 f_tt^n at the interfaces */
+        for (size_t q = 0; q < nfx; ++q) vx[q] = Fx.S0[q] + 0.5 * dt * Fx.S1[q] + 0.125 * dt * dt * Fx.S2[q];
+        if (dim == 2)
+            for (size_t q = 0; q < nfy; ++q) vy[q] = Fy.S0[q] + 0.5 * dt * Fy.S1[q] + 0.125 * dt * dt * Fy.S2[q];
+        slopes_from_faces(&P, vx, vy, Wxs, Wys);
+
+        /* stage 2 at t* = t^n + dt/2 */
+        fill_ghosts(&P, Ws, Wxs, dim == 2 ? Wys : NULL);
+        if ((st = stage(&P, Ws, Wxs, Wys, dt, &Fxs, &Fys, Ls, dLs))) break;
+        /* W^{n+1} = W^n + dt L^n + dt^2/6 (dL^n + 2 dL*) */
+        for (int j = 0; j < P.ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                for (int k = 0; k < nv; ++k) {
+                    size_t o = CELL(&P, i, j) + k, s = ((size_t)j * nx + i) * nv + k;
+                    Wn[o] = Wn[o] + dt * L[s] + dt * dt / 6.0 * (dL[s] + 2.0 * dLs[s]);
+                }
+        /* f^{n+1} = f^n + dt f_t^n + dt^2/6 (f_tt^n + 2 f_tt*) */
+        for (size_t q = 0; q < nfx; ++q) vx[q] = Fx.S0[q] + dt * Fx.S1[q] + dt * dt / 6.0 * (Fx.S2[q] + 2.0 * Fxs.S2[q]);
+        if (dim == 2)
+            for (size_t q = 0; q < nfy; ++q) vy[q] = Fy.S0[q] + dt * Fy.S1[q] + dt * dt / 6.0 * (Fy.S2[q] + 2.0 * Fys.S2[q]);
+        slopes_from_faces(&P, vx, vy, Wxn, Wyn);
+        t = last ? t_end : t + dt;
+        ++n;
+    }
+
+    if (Wn)
+        for (int j = 0; j < P.ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                for (int k = 0; k < nv; ++k) {
+                    size_t o = CELL(&P, i, j) + k, s = ((size_t)j * nx + i) * nv + k;
+                    W[s] = Wn[o]; Wx[s] = Wxn[o];
+                    if (dim == 2) Wy[s] = Wyn[o];
+                }
+    *t_io = t;
+    *nsteps_out = n;
+    free(Wn); free(Wxn); free(Wyn); free(Ws); free(Wxs); free(Wys);
+    free(L); free(dL); free(Ls); free(dLs); free(vx); free(vy);
+    faces_free(&Fx); faces_free(&Fy); faces_free(&Fxs); faces_free(&Fys);
+    return st;
+}
+
+/* ---- unit-level entry points used by the pin tests ---- */
+
+/* Linear reconstruction map: out[3][8] as lin_map (order 6 or 8). */
+int orc_linear_map(int order, double *out)
+{
+    if (init_tables()) return ORC_EINVAL;
+    memcpy(out, lin_map[order == 8 ? 1 : 0], sizeof(double) * 24);
+    return 0;
+}
+
+/* Candidate polynomial map of w_k (k = 0..6, 7 = w~_1): out[5][8], the
+   coefficients of t^m (t = (x - x_i)/dx) as linear maps of the stencil data. */
+int orc_candidate_map(int k, double *out)
+{
+    if (init_tables() || k < 0 || k > 7) return ORC_EINVAL;
+    memcpy(out, cand_map[k], sizeof(double) * 40);
+    return 0;
+}
+
+/* Scalar WENO-Z left/right states.  res[0] left value, res[1] dx * left
+   derivative, res[2] right value, res[3] dx * right derivative;
+   delta[7], beta[7] of the left state. */
+int orc_weno(int order, const double *Wk, const double *Dk, double *res, double *delta, double *beta)
+{
+    if (init_tables()) return ORC_EINVAL;
+    weno_left(order, Wk, Dk, &res[0], &res[1], delta, beta);
+    weno_right(order, Wk, Dk, &res[2], &res[3]);
+    return 0;
+}
+
+int orc_set_weno_eps(double eps) { weno_eps = eps; return 0; }
+
+/* Tangential map tan_map[3][3][5]. */
+int orc_tangential_map(double *out)
+{
+    if (init_tables()) return ORC_EINVAL;
+    memcpy(out, tan_map, sizeof tan_map);
+    return 0;
+}
+
+/* Euler right-eigenvector matrix (row-major nv x nv). */
+int orc_euler_R(int dim, double gamma, const double *W, double *R) { return euler_R(dim, gamma, W, R); }
+
+/* Maxwellian moments for the pins: returns rho * <u^a v^b (xi^2)^c> with
+   half = 0, +1, -1. */
+int orc_raw_moment(int dim, double gamma, const double *W, int a, int b, int c, int half, double *out)
+{
+    double K = dim == 1 ? (3.0 - gamma) / (gamma - 1.0) : (4.0 - 2.0 * gamma) / (gamma - 1.0);
+    maxw_t m;
+    int st = make_maxwellian(dim, gamma, K, W, &m);
+    if (st) return st;
+    poly_t P;
+    poly_zero(&P);
+    poly_set(&P, a, b, c, 1.0);
+    *out = m.rho * moment(&P, &m, half);
+    return 0;
+}
+
+/* <a psi> = b solve, for the pins. */
+int orc_micro_solve(int dim, double gamma, const double *W, const double *b, double *a)
+{
+    double K = dim == 1 ? (3.0 - gamma) / (gamma - 1.0) : (4.0 - 2.0 * gamma) / (gamma - 1.0);
+    maxw_t m;
+    int st = make_maxwellian(dim, gamma, K, W, &m);
+    if (st) return st;
+    return micro_solve(dim, &m, b, a);
+}
+
+/* psi-moments of a linear micro-coefficient function a: out = <a psi> */
+int orc_psi_moments_lin(int dim, double gamma, const double *W, const double *a, int half, double *out)
+{
+    double K = dim == 1 ? (3.0 - gamma) / (gamma - 1.0) : (4.0 - 2.0 * gamma) / (gamma - 1.0);
+    maxw_t m;
+    int st = make_maxwellian(dim, gamma, K, W, &m);
+    if (st) return st;
+    poly_t P;
+    poly_lin(&P, dim, a);
+    psi_moments(dim, &P, &m, half, out);
+    return 0;
+}
+
+/* The interface point evaluation.  in: 12 vectors of 4 (W0, W0x, W0y, W0xx,
+   W0xy, W0yy, Wl, Wlx, Wly, Wr, Wrx, Wry); out: 5 vectors of 4 (FL, FdL, S0,
+   S1, S2).  Local frame (normal = x). */
+int orc_gks_point(int dim, double gamma, double mu, double dt, const double *in12, double *out5)
+{
+    kin_par_t kp;
+    kp.dim = dim; kp.gamma = gamma; kp.mu = mu; kp.dt = dt;
+    kp.K = dim == 1 ? (3.0 - gamma) / (gamma - 1.0) : (4.0 - 2.0 * gamma) / (gamma - 1.0);
+    gp_in_t in;
+    double *dst[12] = {in.W0, in.W0x, in.W0y, in.W0xx, in.W0xy, in.W0yy, in.Wl, in.Wlx, in.Wly, in.Wr, in.Wrx, in.Wry};
+    for (int q = 0; q < 12; ++q) memcpy(dst[q], in12 + 4 * q, sizeof(double) * 4);
+    gp_out_t o;
+    int st = gks_point(&kp, &in, &o);
+    if (st) return st;
+    double *src[5] = {o.FL, o.FdL, o.S0, o.S1, o.S2};
+    for (int q = 0; q < 5; ++q) memcpy(out5 + 4 * q, src[q], sizeof(double) * 4);
+    return 0;
+}
+
+/* Exponential time-fit coefficients (ke, kte, kde, kdte) for the pins. */
+int orc_exp_fit(double tau_n, double dt, double *out4)
+{
+    exp_fit(tau_n, dt, &out4[0], &out4[1], &out4[2], &out4[3]);
+    return 0;
+}
+
+/* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Kinetic average of two states (equilibrium value from WENO states). */
+int orc_kinetic_average(int dim, double gamma, const double *Wl, const double *Wr, double *W0)
+{
+    double K = dim == 1 ? (3.0 - gamma) / (gamma - 1.0) : (4.0 - 2.0 * gamma) / (gamma - 1.0);
+    return kinetic_average(dim, gamma, K, Wl, Wr, W0);
+}
+
+/* Tangential WENO-Z value at Gauss point g (0..2) from five row values. */
+int orc_tangential_weno(int g, const double *q, double *out)
+{
+    if (init_tables() || g < 0 || g > 2) return ORC_EINVAL;
+    *out = tan_weno_value(g, q);
+    return 0;
+}
+
+/* Tangential linear weights tw_lin[3][3]. */
+int orc_tangential_weno_weights(double *out)
+{
+    if (init_tables()) return ORC_EINVAL;
+    memcpy(out, tw_lin, sizeof tw_lin);
+    return 0;
+}

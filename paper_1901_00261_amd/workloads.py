@@ -1,0 +1,237 @@
+"""Seeded synthetic initial data for the compact gas-kinetic scheme.
+
+This module holds no arithmetic of the scheme itself: it only turns a
+problem description (primitive fields, domain, mesh) into the scheme's input,
+the cell averages W of the conservative variables and the cell-averaged
+gradients W_x (and W_y), both exact up to quadrature (Sec. 4: the accuracy
+test advects exact cell averages; the acoustic test uses exact averages of
+values and of derivatives).  Both the HIP library's tests and the CPU oracle
+consume what it produces.
+
+Arrays are float64, conservative order (rho, rho U, [rho V], rho E), layout
+[nx, nv] in 1-D and [ny, nx, nv] in 2-D.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# 8-point Gauss-Legendre rule on [-1, 1]
+_GL_X, _GL_W = np.polynomial.legendre.leggauss(8)
+
+
+def prim_to_cons(rho, U, p, gamma, V=None):
+    """Conservative variables from primitive (pointwise)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64) * np.ones_like(rho)
+    p = np.asarray(p, dtype=np.float64) * np.ones_like(rho)
+    if V is None:
+        E = p / (gamma - 1.0) + 0.5 * rho * U * U
+        return np.stack([rho, rho * U, E], axis=-1)
+    V = np.asarray(V, dtype=np.float64) * np.ones_like(rho)
+    E = p / (gamma - 1.0) + 0.5 * rho * (U * U + V * V)
+    return np.stack([rho, rho * U, rho * V, E], axis=-1)
+
+
+@dataclass
+class Problem:
+    """A problem description consumed by the library binding and the oracle."""
+    dim: int
+    nx: int
+    ny: int
+    xlo: float
+    xhi: float
+    ylo: float
+    yhi: float
+    gamma: float
+    mu: float
+    cfl: float
+    dt_fixed: float
+    t_end: float
+    order: int
+    recon: int  # 0 linear, 1 WENO-Z
+    bc: tuple   # (xlo, xhi, ylo, yhi): 0 periodic, 1 extrapolated
+    W: np.ndarray = field(repr=False)
+    Wx: np.ndarray = field(repr=False)
+    Wy: np.ndarray | None = field(repr=False, default=None)
+    name: str = ""
+
+    def oracle_kwargs(self):
+        return dict(xlo=self.xlo, xhi=self.xhi, ylo=self.ylo, yhi=self.yhi, gamma=self.gamma,
+                    mu=self.mu, cfl=self.cfl, dt_fixed=self.dt_fixed, t_end=self.t_end,
+                    order=self.order, recon=self.recon, bc=tuple(self.bc))
+
+
+# ---------------------------------------------------------------- 1-D
+def sine_wave_1d(n, *, order=6, recon=0, gamma=1.4, cfl=0.3, dt_fixed=0.0, t_end=2.0, amp=0.2, k=math.pi):
+    """rho = 1 + amp sin(k x), U = 1, p = 1 on [0, 2], periodic (Sec. 4.1).
+    Exact cell averages and cell-averaged slopes (the conservative variables
+    are affine in rho here, so both are closed forms)."""
+    xlo, xhi = 0.0, 2.0
+    dx = (xhi - xlo) / n
+    xf = xlo + dx * np.arange(n + 1)
+    # point values at faces and exact cell averages of rho
+    rho_f = 1.0 + amp * np.sin(k * xf)
+    rho_avg = 1.0 + amp * (np.cos(k * xf[:-1]) - np.cos(k * xf[1:])) / (k * dx)
+    W = prim_to_cons(rho_avg, 1.0, 1.0, gamma)          # affine in rho: exact averages
+    Wf = prim_to_cons(rho_f, 1.0, 1.0, gamma)
+    Wx = (Wf[1:] - Wf[:-1]) / dx
+    return Problem(1, n, 1, xlo, xhi, 0.0, 1.0, gamma, 0.0, cfl, dt_fixed, t_end, order, recon,
+                   (0, 0, 0, 0), W, Wx, None, name=f"sine1d_n{n}")
+
+
+def accuracy_dt(n, order, C=0.3, L=2.0):
+    """Accuracy-sweep step dt = C dx^(r/4) on n cells of [0, L] (Sec. 4.1); the
+    last step is shortened to end at t_end."""
+    return C * (L / n) ** (order / 4.0)
+
+
+def riemann_1d(n, left, right, *, x0=0.5, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=0.14, xlo=0.0, xhi=1.0):
+    """Piecewise-constant Riemann data (rho, U, p) with the jump on the face
+    nearest x0; zero slopes; extrapolated boundaries."""
+    dx = (xhi - xlo) / n
+    jface = int(round((x0 - xlo) / dx))
+    rho = np.where(np.arange(n) < jface, left[0], right[0])
+    U = np.where(np.arange(n) < jface, left[1], right[1])
+    p = np.where(np.arange(n) < jface, left[2], right[2])
+    W = prim_to_cons(rho, U, p, gamma)
+    Wx = np.zeros_like(W)
+    return Problem(1, n, 1, xlo, xhi, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   (1, 1, 0, 0), W, Wx, None, name="riemann1d")
+
+
+def random_riemann_states(seed):
+    """(rho_L, u_L, p_L), (rho_R, u_R, p_R): rho ~ U[0.1, 1], u ~ U[-1, 1],
+    p ~ U[0.1, 1], drawn in that order from PCG64(seed)."""
+    rng = np.random.default_rng(seed)
+    rl, ul, pl, rr, ur, pr = (rng.uniform(0.1, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 1.0),
+                              rng.uniform(0.1, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 1.0))
+    return (rl, ul, pl), (rr, ur, pr)
+
+
+SOD = ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+
+
+def riemann_set_1d(count=32, n=400, base_seed=20190101, order=8, recon=1):
+    return [riemann_1d(n, *random_riemann_states(base_seed + k), order=order, recon=recon)
+            for k in range(count)]
+
+
+def batch_1d(count=256, seed=4, nmin=200, nmax=4000, t_end=0.14):
+    """Uneven batch: N ~ integer U[nmin, nmax], order 6 or 8 with p = 1/2,
+    states as random_riemann_states, jump on the face nearest 0.5."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for k in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        order = 6 if rng.uniform() < 0.5 else 8
+        l, r = random_riemann_states(int(rng.integers(0, 2**31 - 1)))
+        probs.append(riemann_1d(n, l, r, order=order, recon=1, t_end=t_end))
+    return probs
+
+
+# ---------------------------------------------------------------- 2-D
+def _cell_quadrature_2d(fn, nx, ny, xlo, xhi, ylo, yhi):
+    """Exact-to-quadrature cell averages of fn(x, y) -> [..., nv] and the
+    cell-averaged x/y derivatives through face line averages (8-point
+    Gauss-Legendre per cell and per face)."""
+    dx = (xhi - xlo) / nx
+    dy = (yhi - ylo) / ny
+    xc = xlo + dx * (np.arange(nx) + 0.5)
+    yc = ylo + dy * (np.arange(ny) + 0.5)
+    gx = 0.5 * dx * _GL_X
+    gy = 0.5 * dy * _GL_X
+    w = 0.5 * _GL_W
+    # cell averages
+    X = xc[None, :, None, None] + gx[None, None, None, :]
+    Y = yc[:, None, None, None] + gy[None, None, :, None]
+    X, Y = np.broadcast_arrays(X, Y)
+    vals = fn(X, Y)  # [ny, nx, 8, 8, nv]
+    avg = np.einsum("abijv,i,j->abv", vals, w, w)
+    # x-face line averages at x = xlo + dx*i, i = 0..nx
+    xf = xlo + dx * np.arange(nx + 1)
+    Xf = xf[None, :, None] + 0 * gy[None, None, :]
+    Yf = yc[:, None, None] + gy[None, None, :]
+    Xf, Yf = np.broadcast_arrays(Xf, Yf)
+    lx = np.einsum("abiv,i->abv", fn(Xf, Yf), w)  # [ny, nx+1, nv]
+    yf = ylo + dy * np.arange(ny + 1)
+    Yg = yf[:, None, None] + 0 * gx[None, None, :]
+    Xg = xc[None, :, None] + gx[None, None, :]
+    Xg, Yg = np.broadcast_arrays(Xg, Yg)
+    ly = np.einsum("abiv,i->abv", fn(Xg, Yg), w)  # [ny+1, nx, nv]
+    Wx = (lx[:, 1:] - lx[:, :-1]) / dx
+    Wy = (ly[1:] - ly[:-1]) / dy
+    return avg, Wx, Wy
+
+
+def isentropic_vortex_2d(n, *, ny=None, L=10.0, eps=5.0, mu=1e-4, gamma=1.4, order=8, recon=1, cfl=0.3,
+                         t_end=1e9, acoustic_amp=1e-3, nmodes=32, seed=3, periodic_images=True):
+    """Isentropic vortex of strength eps at the domain centre on the mean flow
+    (1, 1), plus a seeded random-phase acoustic perturbation
+    p' = (amp/64) sum_{k=1..nmodes} [cos(2 pi k x/L + phi_k) + cos(2 pi k y/L + chi_k)],
+    rho' = p'/gamma; periodic [0, L]^2."""
+    ny = n if ny is None else ny
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.0, 2 * math.pi, nmodes)
+    chi = rng.uniform(0.0, 2 * math.pi, nmodes)
+    kk = np.arange(1, nmodes + 1)
+    xc0 = yc0 = 0.5 * L
+
+    def fn(X, Y):
+        du = np.zeros_like(X)
+        dv = np.zeros_like(X)
+        dT = np.zeros_like(X)
+        shifts = (-L, 0.0, L) if periodic_images else (0.0,)
+        for sx in shifts:
+            for sy in shifts:
+                xr = X - xc0 - sx
+                yr = Y - yc0 - sy
+                r2 = xr * xr + yr * yr
+                e = np.exp(0.5 * (1.0 - r2))
+                du += -eps / (2 * math.pi) * e * yr
+                dv += eps / (2 * math.pi) * e * xr
+                dT += -(gamma - 1.0) * eps * eps * e * e / (8 * gamma * math.pi ** 2)
+        T = 1.0 + dT
+        rho = T ** (1.0 / (gamma - 1.0))
+        p = rho * T
+        pp = np.zeros_like(X)
+        if acoustic_amp:
+            ang_x = 2 * math.pi * X[..., None] * kk / L + phi
+            ang_y = 2 * math.pi * Y[..., None] * kk / L + chi
+            pp = acoustic_amp / 64.0 * (np.cos(ang_x) + np.cos(ang_y)).sum(-1)
+        rho = rho + pp / gamma
+        p = p + pp
+        return prim_to_cons(rho, 1.0 + du, p, gamma, V=1.0 + dv)
+
+    W, Wx, Wy = _cell_quadrature_2d(fn, n, ny, 0.0, L, 0.0, L)
+    return Problem(2, n, ny, 0.0, L, 0.0, L, gamma, mu, cfl, 0.0, t_end, order, recon,
+                   (0, 0, 0, 0), W, Wx, Wy, name=f"vortex2d_{n}x{ny}")
+
+
+def quadrant_states(seed):
+    """Four quadrant states (rho, u, v, p): rho ~ U[0.1, 1.5], u, v ~
+    U[-0.8, 0.8], p ~ U[0.03, 1.5], quadrants 1..4 = (x>, y>), (x<, y>),
+    (x<, y<), (x>, y<)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(4):
+        out.append((rng.uniform(0.1, 1.5), rng.uniform(-0.8, 0.8), rng.uniform(-0.8, 0.8), rng.uniform(0.03, 1.5)))
+    return out
+
+
+def riemann_2d(n, *, ny=None, seed=5, states=None, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=1e9, split=0.5):
+    """Four-quadrant Riemann problem on [0, 1]^2, jumps on faces, zero slopes,
+    extrapolated boundaries."""
+    ny = n if ny is None else ny
+    st = states if states is not None else quadrant_states(seed)
+    ix = np.arange(n)[None, :] >= int(round(split * n))
+    iy = np.arange(ny)[:, None] >= int(round(split * ny))
+    q = np.where(ix & iy, 0, np.where(~ix & iy, 1, np.where(~ix & ~iy, 2, 3)))
+    arr = np.array(st)
+    rho, u, v, p = (arr[q, k] for k in range(4))
+    W = prim_to_cons(rho, u, p, gamma, V=v)
+    Z = np.zeros_like(W)
+    return Problem(2, n, ny, 0.0, 1.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   (1, 1, 1, 1), W, Z, Z.copy(), name=f"riemann2d_{n}x{ny}")
