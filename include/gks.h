@@ -1,0 +1,124 @@
+/*
+ * gks.h -- C ABI of the MI355X (gfx950) library for the compact 6th/8th-order
+ * gas-kinetic scheme of Zhao, Ji, Shyy and Xu (arXiv:1901.00261).
+ *
+ * The library advances cell averages W and cell-averaged gradients W_x (and
+ * W_y) of the Euler / Navier-Stokes equations on uniform meshes with the
+ * two-stage fourth-order multi-stage multi-derivative (MSMD) time stepping
+ * (Sec. 2.2), compact linear reconstruction for the equilibrium state
+ * (Sec. 3.1), compact WENO-Z for the non-equilibrium state (Sec. 3.3) and the
+ * simplified third-order BGK interface distribution (Sec. 2.1).
+ *
+ * Conventions
+ *   - Every call returns an int status: GKS_OK (0) or a negative GKS_E*.
+ *     Errors never abort the process; gks_last_error() explains the last one.
+ *   - Host arrays are row-major [ny][nx][nv], nv = dim + 2, conservative
+ *     variables (rho, rho U, [rho V], rho E); gradients are cell-averaged
+ *     gradients (not multiplied by the cell width).  The library copies them;
+ *     the caller keeps ownership.
+ *   - A handle is not re-entrant: calls on one handle must not overlap.
+ *     Separate handles are independent.
+ *   - All device work runs on the stream given to gks_init (a hipStream_t;
+ *     NULL means the library creates its own default-priority stream).
+ */
+#ifndef GKS_H
+#define GKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GKS_OK = 0,
+    GKS_EINVAL = -1,   /* invalid argument */
+    GKS_ENOMEM = -2,   /* device allocation failed */
+    GKS_EDEVICE = -3,  /* HIP runtime error */
+    GKS_ENONPHYS = -4, /* a non-physical state (rho <= 0 or p <= 0) was met */
+    GKS_ESTATE = -5    /* handle unusable after a device fault */
+};
+enum { GKS_BC_PERIODIC = 0, GKS_BC_EXTRAP = 1 };
+enum { GKS_RECON_LINEAR = 0, GKS_RECON_WENOZ = 1 };
+enum { GKS_PREC_FP64 = 0, GKS_PREC_FP32_MIXED = 1 };
+
+/* One problem (Sec. 2 and Sec. 4 of the paper).
+   dim: 1 or 2.  nx, ny: interior cells (ny = 1 when dim == 1), at least 4.
+   gamma > 1.  mu >= 0 dynamic viscosity (0: Euler); collision times follow
+   Sec. 4 (tau = mu/p for the viscous terms, tau_n = eps dt or mu/p plus the
+   pressure-jump term in the exponentials).  cfl > 0 sets
+   dt = cfl * min over cells of dx/(|U|+c) [and dy/(|V|+c)] unless
+   dt_fixed > 0.  The last step is shortened so the problem ends exactly at
+   t_end.  order: 6 or 8.  recon: GKS_RECON_*.  bc: x-low, x-high, y-low,
+   y-high, GKS_BC_* (periodic must be paired). */
+typedef struct {
+    int32_t dim;
+    int32_t nx, ny;
+    double xlo, xhi, ylo, yhi;
+    double gamma;
+    double mu;
+    double cfl;
+    double dt_fixed;
+    double t_end;
+    int32_t order;
+    int32_t recon;
+    int32_t bc[4];
+} gks_problem;
+
+typedef struct gks_handle gks_handle;
+
+/* Create a handle holding nprob problems, all of the same dim (2-D handles
+   hold one problem).  W0[p], Wx0[p], Wy0[p] are host arrays (Wy0 may be NULL
+   when dim == 1).  precision: GKS_PREC_*.  stream: hipStream_t or NULL.
+   On success *out owns device memory until gks_free.
+   Errors: GKS_EINVAL (bad sizes/parameters, non-physical initial data),
+   GKS_ENOMEM, GKS_EDEVICE. */
+int gks_init(const gks_problem* probs, int32_t nprob, int32_t precision, const double* const* W0,
+             const double* const* Wx0, const double* const* Wy0, void* stream, gks_handle** out);
+
+/* Same as gks_init with DEVICE pointers (for example torch tensors on the
+   GPU); the library copies them device-to-device on its stream. */
+int gks_init_device(const gks_problem* probs, int32_t nprob, int32_t precision, const double* const* W0,
+                    const double* const* Wx0, const double* const* Wy0, void* stream, gks_handle** out);
+
+/* Advance every unfinished problem by up to max_steps MSMD steps, each with
+   its own dt (Sec. 2.2).  *n_active (may be NULL) receives the number of
+   problems still short of t_end.  Returns GKS_ENONPHYS if any problem met a
+   non-physical state; that problem stops and keeps the state it had at the
+   start of the failing step. */
+int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active);
+
+/* Copy problem p to host buffers (layout as in gks_init; Wy ignored when
+   dim == 1) and report its time and step count (either may be NULL).
+   Synchronises the stream. */
+int gks_state(const gks_handle* h, int32_t p, double* W, double* Wx, double* Wy, double* t, int64_t* nsteps);
+
+/* Same as gks_state into DEVICE buffers (no host synchronisation beyond the
+   stream order). */
+int gks_state_device(const gks_handle* h, int32_t p, double* W, double* Wx, double* Wy);
+
+/* Status of problem p: 0 running, 1 finished (t == t_end), GKS_ENONPHYS. */
+int gks_problem_status(const gks_handle* h, int32_t p, int32_t* status);
+
+int gks_free(gks_handle* h);
+
+/* Message of the last failure on h (or of the last failed gks_init when h is
+   NULL).  Static lifetime until the next call on the same handle. */
+const char* gks_last_error(const gks_handle* h);
+
+/* Kernel timing with HIP events on the handle's stream.  enable != 0 records
+   an event pair around every launch of the kernels of the given id from now
+   on; gks_kernel_time returns the summed time (ms) and the launch count since
+   enabling.  Ids: 0 interface (flux) kernels, 1 face-row reconstruction
+   kernels (2-D), 2 cell update kernels. */
+int gks_kernel_timing(gks_handle* h, int32_t enable);
+int gks_kernel_time(gks_handle* h, int32_t kernel_id, double* total_ms, int64_t* launches);
+
+/* Number of cells * MSMD steps the last gks_step performed (all problems). */
+int gks_cell_updates(const gks_handle* h, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GKS_H */

@@ -1,0 +1,544 @@
+// gks_api.hip -- host side of the C ABI declared in include/gks.h.
+#include "../../include/gks.h"
+#include "gks_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using gks::ProbParam;
+using gks::ProbState;
+using gks::Tile;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct EventPair {
+    hipEvent_t a, b;
+    int kind;
+};
+
+} // namespace
+
+struct gks_handle {
+    int dim = 0, nprob = 0, precision = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<ProbParam> hp;
+    ProbParam* dP = nullptr;
+    ProbState* dS = nullptr;
+    long long Ntot = 0, F = 0; // 1-D cells and faces
+    Tile* dTilesF = nullptr;
+    Tile* dTilesC = nullptr;
+    int nTilesF = 0, nTilesC = 0;
+    double *W = nullptr, *Wx = nullptr, *Wy = nullptr, *PW = nullptr;
+    double *FL = nullptr, *FdL = nullptr, *Wfs = nullptr, *Pf = nullptr;
+    double *FLy = nullptr, *FdLy = nullptr, *Wfsy = nullptr, *Pfy = nullptr;
+    double *Rx = nullptr, *Ry = nullptr;
+    double* stage = nullptr; // transpose staging
+    size_t stage_len = 0;
+    std::string err;
+    bool timing = false;
+    std::vector<EventPair> pending;
+    std::vector<EventPair> pool;
+    double tot_ms[3] = {0, 0, 0};
+    long long launches[3] = {0, 0, 0};
+    long long last_updates = 0;
+};
+
+namespace {
+
+int fail(gks_handle* h, int code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    else g_init_error = msg;
+    return code;
+}
+
+#define HIP_TRY(h, expr)                                                                          \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(h, e_ == hipErrorOutOfMemory ? GKS_ENOMEM : GKS_EDEVICE,                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                       \
+    } while (0)
+
+template <typename Ptr> hipError_t dalloc(Ptr** p, size_t n)
+{
+    return hipMalloc((void**)p, n * sizeof(Ptr));
+}
+
+void dfree(void* p)
+{
+    if (p) (void)hipFree(p);
+}
+
+// AoS [cells][nv] (with ld = nv) <-> SoA [nv][cells], nv = 3 or 4.  For
+// 1-D the SoA slots are (rho, rho U, rho E).
+__global__ void aos_to_soa(const double* __restrict__ src, double* __restrict__ dst, long long n, int nv, long long ld)
+{
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    for (int k = 0; k < nv; ++k) dst[k * ld + c] = src[c * nv + k];
+}
+__global__ void soa_to_aos(const double* __restrict__ src, double* __restrict__ dst, long long n, int nv, long long ld)
+{
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    for (int k = 0; k < nv; ++k) dst[c * nv + k] = src[k * ld + c];
+}
+
+int validate(const gks_problem* pr, int32_t nprob, int32_t precision)
+{
+    if (!pr || nprob < 1) return fail(nullptr, GKS_EINVAL, "no problems given");
+    if (precision != GKS_PREC_FP64 && precision != GKS_PREC_FP32_MIXED)
+        return fail(nullptr, GKS_EINVAL, "unknown precision");
+    const int dim = pr[0].dim;
+    if (dim != 1 && dim != 2) return fail(nullptr, GKS_EINVAL, "dim must be 1 or 2");
+    if (dim == 2 && nprob != 1) return fail(nullptr, GKS_EINVAL, "a 2-D handle holds exactly one problem");
+    for (int p = 0; p < nprob; ++p) {
+        const gks_problem& q = pr[p];
+        char buf[160];
+        auto bad = [&](const char* what) {
+            snprintf(buf, sizeof buf, "problem %d: %s", p, what);
+            return fail(nullptr, GKS_EINVAL, buf);
+        };
+        if (q.dim != dim) return bad("all problems of a handle must have the same dim");
+        if (q.nx < 4 || (dim == 2 && q.ny < 4) || (dim == 1 && q.ny != 1 && q.ny != 0)) return bad("bad nx/ny");
+        if ((long long)q.nx * (dim == 2 ? q.ny : 1) > (1ll << 31) - 1) return bad("too many cells");
+        if (!(q.xhi > q.xlo) || (dim == 2 && !(q.yhi > q.ylo))) return bad("empty domain");
+        if (!(q.gamma > 1.0) || !std::isfinite(q.gamma)) return bad("gamma must be > 1");
+        if (!(q.mu >= 0.0) || !std::isfinite(q.mu)) return bad("mu must be >= 0");
+        if (!(q.dt_fixed > 0.0) && !(q.cfl > 0.0)) return bad("need cfl > 0 or dt_fixed > 0");
+        if (!(q.t_end > 0.0)) return bad("t_end must be > 0");
+        if (q.order != 6 && q.order != 8) return bad("order must be 6 or 8");
+        if (q.recon != GKS_RECON_LINEAR && q.recon != GKS_RECON_WENOZ) return bad("unknown recon");
+        const int nb = dim == 2 ? 4 : 2;
+        for (int k = 0; k < nb; ++k)
+            if (q.bc[k] != GKS_BC_PERIODIC && q.bc[k] != GKS_BC_EXTRAP) return bad("unknown boundary condition");
+        for (int k = 0; k < nb; k += 2)
+            if ((q.bc[k] == GKS_BC_PERIODIC) != (q.bc[k + 1] == GKS_BC_PERIODIC))
+                return bad("periodic boundaries must be paired");
+    }
+    return GKS_OK;
+}
+
+void record(gks_handle* h, int kind, bool begin)
+{
+    if (!h->timing) return;
+    if (begin) {
+        EventPair e;
+        if (!h->pool.empty()) {
+            e = h->pool.back();
+            h->pool.pop_back();
+        } else {
+            (void)hipEventCreate(&e.a);
+            (void)hipEventCreate(&e.b);
+        }
+        e.kind = kind;
+        (void)hipEventRecord(e.a, h->stream);
+        h->pending.push_back(e);
+    } else {
+        (void)hipEventRecord(h->pending.back().b, h->stream);
+    }
+}
+
+void harvest(gks_handle* h)
+{
+    for (auto& e : h->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+            h->tot_ms[e.kind] += ms;
+            h->launches[e.kind] += 1;
+        }
+        h->pool.push_back(e);
+    }
+    h->pending.clear();
+}
+
+template <typename T> void launch_step_1d(gks_handle* h)
+{
+    const dim3 bf(gks::kBlock1D);
+    record(h, 0, true);
+    gks::face1d_kernel<T, 1><<<h->nTilesF, bf, 0, h->stream>>>(h->dP, h->dS, h->dTilesF, h->W, h->Wx, h->Ntot, h->F,
+                                                                h->FL, h->FdL, h->Wfs, h->Pf);
+    record(h, 0, false);
+    record(h, 2, true);
+    gks::cell1d_kernel<1><<<h->nTilesC, bf, 0, h->stream>>>(h->dP, h->dS, h->dTilesC, h->W, h->Wx, h->PW, h->Ntot, h->F,
+                                                            h->FL, h->FdL, h->Wfs);
+    record(h, 2, false);
+    record(h, 0, true);
+    gks::face1d_kernel<T, 2><<<h->nTilesF, bf, 0, h->stream>>>(h->dP, h->dS, h->dTilesF, h->W, h->Wx, h->Ntot, h->F,
+                                                                h->FL, h->FdL, h->Wfs, h->Pf);
+    record(h, 0, false);
+    record(h, 2, true);
+    gks::cell1d_kernel<2><<<h->nTilesC, bf, 0, h->stream>>>(h->dP, h->dS, h->dTilesC, h->W, h->Wx, h->PW, h->Ntot, h->F,
+                                                            h->FL, h->FdL, h->Wfs);
+    record(h, 2, false);
+    gks::finish_kernel<<<(h->nprob + 63) / 64, 64, 0, h->stream>>>(h->dP, h->dS, h->nprob, 1);
+}
+
+template <typename T> void launch_step_2d(gks_handle* h)
+{
+    const ProbParam& P = h->hp[0];
+    const int nx = P.nx, ny = P.ny;
+    const dim3 br(64, 4), bg(64, 2), bc(64, 4);
+    // x faces: rows (ny + 4) x faces (nx + 1); y faces: faces (ny + 1) x columns (nx + 4)
+    const dim3 grx((nx + 1 + 63) / 64, (ny + 4 + 3) / 4), gry((nx + 4 + 63) / 64, (ny + 1 + 3) / 4);
+    const dim3 ggx((nx + 1 + 63) / 64, (ny + 1) / 2), ggy((nx + 63) / 64, (ny + 1 + 1) / 2);
+    const dim3 gc((nx + 63) / 64, (ny + 3) / 4);
+    for (int stage = 1; stage <= 2; ++stage) {
+        record(h, 1, true);
+        gks::row2d_kernel<T, 0><<<grx, br, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
+        record(h, 1, false);
+        record(h, 0, true);
+        gks::gp2d_kernel<T, 0><<<ggx, bg, 0, h->stream>>>(h->dP, h->dS, h->Rx, stage, h->FL, h->FdL, h->Wfs, h->Pf);
+        record(h, 0, false);
+        record(h, 1, true);
+        gks::row2d_kernel<T, 1><<<gry, br, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
+        record(h, 1, false);
+        record(h, 0, true);
+        gks::gp2d_kernel<T, 1><<<ggy, bg, 0, h->stream>>>(h->dP, h->dS, h->Ry, stage, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
+        record(h, 0, false);
+        record(h, 2, true);
+        if (stage == 1)
+            gks::cell2d_kernel<1><<<gc, bc, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL,
+                                                             h->Wfs, h->FLy, h->FdLy, h->Wfsy);
+        else
+            gks::cell2d_kernel<2><<<gc, bc, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL,
+                                                             h->Wfs, h->FLy, h->FdLy, h->Wfsy);
+        record(h, 2, false);
+    }
+    gks::finish_kernel<<<1, 64, 0, h->stream>>>(h->dP, h->dS, 1, 1);
+}
+
+void release(gks_handle* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* p : {(void*)h->dP, (void*)h->dS, (void*)h->dTilesF, (void*)h->dTilesC, (void*)h->W, (void*)h->Wx,
+                    (void*)h->Wy, (void*)h->PW, (void*)h->FL, (void*)h->FdL, (void*)h->Wfs, (void*)h->Pf,
+                    (void*)h->FLy, (void*)h->FdLy, (void*)h->Wfsy, (void*)h->Pfy, (void*)h->Rx, (void*)h->Ry,
+                    (void*)h->stage})
+        dfree(p);
+    for (auto& e : h->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    for (auto& e : h->pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, const double* const* W0,
+                const double* const* Wx0, const double* const* Wy0, void* stream, gks_handle** out, bool device)
+{
+    if (!out) return fail(nullptr, GKS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st = validate(probs, nprob, precision);
+    if (st) return st;
+    const int dim = probs[0].dim;
+    for (int p = 0; p < nprob; ++p)
+        if (!W0 || !Wx0 || !W0[p] || !Wx0[p] || (dim == 2 && (!Wy0 || !Wy0[p])))
+            return fail(nullptr, GKS_EINVAL, "missing initial data array");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(nullptr, GKS_EDEVICE, "no HIP device available");
+
+    gks_handle* h = new gks_handle();
+    h->dim = dim;
+    h->nprob = nprob;
+    h->precision = precision;
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreate(&h->stream) != hipSuccess) {
+            delete h;
+            return fail(nullptr, GKS_EDEVICE, "hipStreamCreate failed");
+        }
+        h->own_stream = true;
+    }
+    auto bail = [&](int code) {
+        g_init_error = h->err;
+        release(h);
+        return code;
+    };
+#define TRY(expr)                                                                                 \
+    do {                                                                                          \
+        int s_ = (expr);                                                                          \
+        if (s_) return bail(s_);                                                                  \
+    } while (0)
+
+    // problem parameters, tiles
+    std::vector<Tile> tf, tc;
+    long long coff = 0, foff = 0;
+    for (int p = 0; p < nprob; ++p) {
+        const gks_problem& q = probs[p];
+        ProbParam P{};
+        P.nx = q.nx;
+        P.ny = dim == 2 ? q.ny : 1;
+        P.coff = coff;
+        P.foff = foff;
+        P.dx = (q.xhi - q.xlo) / q.nx;
+        P.dy = dim == 2 ? (q.yhi - q.ylo) / q.ny : 1.0;
+        P.gamma = q.gamma;
+        P.K = dim == 1 ? (3.0 - q.gamma) / (q.gamma - 1.0) : (4.0 - 2.0 * q.gamma) / (q.gamma - 1.0);
+        P.mu = q.mu;
+        P.cfl = q.cfl;
+        P.dt_fixed = q.dt_fixed;
+        P.t_end = q.t_end;
+        P.order = q.order;
+        P.recon = q.recon;
+        for (int k = 0; k < 4; ++k) P.bc[k] = (dim == 1 && k >= 2) ? 0 : q.bc[k];
+        h->hp.push_back(P);
+        if (dim == 1) {
+            for (int s = 0; s <= q.nx; s += gks::kBlock1D) tf.push_back(Tile{p, s});
+            for (int s = 0; s < q.nx; s += gks::kBlock1D) tc.push_back(Tile{p, s});
+            coff += q.nx;
+            foff += q.nx + 1;
+        }
+    }
+    h->Ntot = dim == 1 ? coff : (long long)probs[0].nx * probs[0].ny;
+    h->F = foff;
+    const int nv = dim + 2;
+    TRY(([&]() -> int { HIP_TRY(h, dalloc(&h->dP, nprob)); HIP_TRY(h, dalloc(&h->dS, nprob)); return 0; })());
+    TRY(([&]() -> int {
+        HIP_TRY(h, hipMemcpyAsync(h->dP, h->hp.data(), sizeof(ProbParam) * nprob, hipMemcpyHostToDevice, h->stream));
+        std::vector<ProbState> s0(nprob);
+        for (auto& s : s0) { s = ProbState{}; s.active = 1; }
+        HIP_TRY(h, hipMemcpyAsync(h->dS, s0.data(), sizeof(ProbState) * nprob, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return 0;
+    })());
+    const long long N = h->Ntot;
+    if (dim == 1) {
+        h->nTilesF = (int)tf.size();
+        h->nTilesC = (int)tc.size();
+        TRY(([&]() -> int {
+            HIP_TRY(h, dalloc(&h->dTilesF, tf.size()));
+            HIP_TRY(h, dalloc(&h->dTilesC, tc.size()));
+            HIP_TRY(h, hipMemcpy(h->dTilesF, tf.data(), sizeof(Tile) * tf.size(), hipMemcpyHostToDevice));
+            HIP_TRY(h, hipMemcpy(h->dTilesC, tc.data(), sizeof(Tile) * tc.size(), hipMemcpyHostToDevice));
+            HIP_TRY(h, dalloc(&h->W, 2 * 3 * N));
+            HIP_TRY(h, dalloc(&h->Wx, 2 * 3 * N));
+            HIP_TRY(h, dalloc(&h->PW, 3 * N));
+            HIP_TRY(h, dalloc(&h->FL, 3 * h->F));
+            HIP_TRY(h, dalloc(&h->FdL, 3 * h->F));
+            HIP_TRY(h, dalloc(&h->Wfs, 3 * h->F));
+            HIP_TRY(h, dalloc(&h->Pf, 3 * h->F));
+            return 0;
+        })());
+    } else {
+        const long long nx = probs[0].nx, ny = probs[0].ny;
+        TRY(([&]() -> int {
+            HIP_TRY(h, dalloc(&h->W, 2 * 4 * N));
+            HIP_TRY(h, dalloc(&h->Wx, 2 * 4 * N));
+            HIP_TRY(h, dalloc(&h->Wy, 2 * 4 * N));
+            HIP_TRY(h, dalloc(&h->PW, 4 * N));
+            const long long nfx = ny * (nx + 1), nfy = (ny + 1) * nx;
+            HIP_TRY(h, dalloc(&h->FL, 4 * nfx));
+            HIP_TRY(h, dalloc(&h->FdL, 4 * nfx));
+            HIP_TRY(h, dalloc(&h->Wfs, 4 * nfx));
+            HIP_TRY(h, dalloc(&h->Pf, 4 * nfx));
+            HIP_TRY(h, dalloc(&h->FLy, 4 * nfy));
+            HIP_TRY(h, dalloc(&h->FdLy, 4 * nfy));
+            HIP_TRY(h, dalloc(&h->Wfsy, 4 * nfy));
+            HIP_TRY(h, dalloc(&h->Pfy, 4 * nfy));
+            HIP_TRY(h, dalloc(&h->Rx, 28 * (ny + 4) * (nx + 1)));
+            HIP_TRY(h, dalloc(&h->Ry, 28 * (ny + 1) * (nx + 4)));
+            return 0;
+        })());
+    }
+    // upload: AoS -> SoA through a staging buffer
+    long long maxcells = 0;
+    for (int p = 0; p < nprob; ++p) maxcells = std::max<long long>(maxcells, (long long)h->hp[p].nx * h->hp[p].ny);
+    h->stage_len = (size_t)maxcells * nv;
+    TRY(([&]() -> int { HIP_TRY(h, dalloc(&h->stage, h->stage_len)); return 0; })());
+    const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int p = 0; p < nprob; ++p) {
+        const long long n = (long long)h->hp[p].nx * h->hp[p].ny;
+        const int nblk = (int)((n + 255) / 256);
+        const double* srcs[3] = {W0[p], Wx0[p], dim == 2 ? Wy0[p] : nullptr};
+        double* dsts[3] = {h->W, h->Wx, h->Wy};
+        for (int a = 0; a < (dim == 2 ? 3 : 2); ++a) {
+            TRY(([&]() -> int {
+                HIP_TRY(h, hipMemcpyAsync(h->stage, srcs[a], sizeof(double) * n * nv, kind, h->stream));
+                aos_to_soa<<<nblk, 256, 0, h->stream>>>(h->stage, dsts[a] + h->hp[p].coff, n, nv, N);
+                HIP_TRY(h, hipGetLastError());
+                HIP_TRY(h, hipStreamSynchronize(h->stream));
+                return 0;
+            })());
+        }
+    }
+    // first dt from the initial state
+    if (dim == 1)
+        gks::signal1d_kernel<<<h->nTilesC, gks::kBlock1D, 0, h->stream>>>(h->dP, h->dS, h->dTilesC, h->W, h->Ntot);
+    else
+        gks::signal2d_kernel<<<dim3((probs[0].nx + 63) / 64, (probs[0].ny + 3) / 4), dim3(64, 4), 0, h->stream>>>(
+            h->dP, h->dS, h->W);
+    gks::finish_kernel<<<(nprob + 63) / 64, 64, 0, h->stream>>>(h->dP, h->dS, nprob, 0);
+    std::vector<ProbState> s(nprob);
+    TRY(([&]() -> int {
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(s.data(), h->dS, sizeof(ProbState) * nprob, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return 0;
+    })());
+    for (int p = 0; p < nprob; ++p)
+        if (s[p].err) {
+            h->err = "problem " + std::to_string(p) + ": non-physical initial state";
+            return bail(GKS_EINVAL);
+        }
+#undef TRY
+    *out = h;
+    return GKS_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int gks_init(const gks_problem* probs, int32_t nprob, int32_t precision, const double* const* W0,
+             const double* const* Wx0, const double* const* Wy0, void* stream, gks_handle** out)
+{
+    return init_common(probs, nprob, precision, W0, Wx0, Wy0, stream, out, false);
+}
+
+int gks_init_device(const gks_problem* probs, int32_t nprob, int32_t precision, const double* const* W0,
+                    const double* const* Wx0, const double* const* Wy0, void* stream, gks_handle** out)
+{
+    return init_common(probs, nprob, precision, W0, Wx0, Wy0, stream, out, true);
+}
+
+int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
+{
+    if (!h) return fail(nullptr, GKS_EINVAL, "NULL handle");
+    if (max_steps < 0) return fail(h, GKS_EINVAL, "max_steps < 0");
+    std::vector<ProbState> before(h->nprob), after(h->nprob);
+    HIP_TRY(h, hipMemcpyAsync(before.data(), h->dS, sizeof(ProbState) * h->nprob, hipMemcpyDeviceToHost, h->stream));
+    for (int s = 0; s < max_steps; ++s) {
+        if (h->dim == 1) {
+            if (h->precision == GKS_PREC_FP64) launch_step_1d<double>(h);
+            else launch_step_1d<float>(h);
+        } else {
+            if (h->precision == GKS_PREC_FP64) launch_step_2d<double>(h);
+            else launch_step_2d<float>(h);
+        }
+    }
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipMemcpyAsync(after.data(), h->dS, sizeof(ProbState) * h->nprob, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    harvest(h);
+    int active = 0, bad = -1;
+    long long upd = 0;
+    for (int p = 0; p < h->nprob; ++p) {
+        active += after[p].active;
+        if (after[p].err && !before[p].err && bad < 0) bad = p;
+        upd += (after[p].nsteps - before[p].nsteps) * (long long)h->hp[p].nx * h->hp[p].ny;
+    }
+    h->last_updates = upd;
+    if (n_active) *n_active = active;
+    if (bad >= 0) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "problem %d: non-physical state at t = %.17g (step %lld)", bad, after[bad].t,
+                 after[bad].nsteps);
+        return fail(h, GKS_ENONPHYS, buf);
+    }
+    return GKS_OK;
+}
+
+static int state_common(const gks_handle* hc, int32_t p, double* W, double* Wx, double* Wy, bool device)
+{
+    gks_handle* h = const_cast<gks_handle*>(hc);
+    if (!h) return fail(nullptr, GKS_EINVAL, "NULL handle");
+    if (p < 0 || p >= h->nprob) return fail(h, GKS_EINVAL, "problem index out of range");
+    ProbState s;
+    HIP_TRY(h, hipMemcpyAsync(&s, h->dS + p, sizeof s, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const ProbParam& P = h->hp[p];
+    const long long n = (long long)P.nx * P.ny;
+    const int nv = h->dim + 2;
+    const long long N = h->Ntot;
+    const int nblk = (int)((n + 255) / 256);
+    double* srcs[3] = {h->W, h->Wx, h->Wy};
+    double* dsts[3] = {W, Wx, Wy};
+    const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int a = 0; a < (h->dim == 2 ? 3 : 2); ++a) {
+        if (!dsts[a]) continue;
+        soa_to_aos<<<nblk, 256, 0, h->stream>>>(srcs[a] + (size_t)s.cur * nv * N + P.coff, h->stage, n, nv, N);
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(dsts[a], h->stage, sizeof(double) * n * nv, kind, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    return GKS_OK;
+}
+
+int gks_state(const gks_handle* hc, int32_t p, double* W, double* Wx, double* Wy, double* t, int64_t* nsteps)
+{
+    int st = state_common(hc, p, W, Wx, Wy, false);
+    if (st) return st;
+    gks_handle* h = const_cast<gks_handle*>(hc);
+    ProbState s;
+    HIP_TRY(h, hipMemcpy(&s, h->dS + p, sizeof s, hipMemcpyDeviceToHost));
+    if (t) *t = s.t;
+    if (nsteps) *nsteps = s.nsteps;
+    return GKS_OK;
+}
+
+int gks_state_device(const gks_handle* h, int32_t p, double* W, double* Wx, double* Wy)
+{
+    return state_common(h, p, W, Wx, Wy, true);
+}
+
+int gks_problem_status(const gks_handle* hc, int32_t p, int32_t* status)
+{
+    gks_handle* h = const_cast<gks_handle*>(hc);
+    if (!h || !status) return fail(h, GKS_EINVAL, "NULL argument");
+    if (p < 0 || p >= h->nprob) return fail(h, GKS_EINVAL, "problem index out of range");
+    ProbState s;
+    HIP_TRY(h, hipMemcpyAsync(&s, h->dS + p, sizeof s, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    *status = s.err ? GKS_ENONPHYS : (s.active ? 0 : 1);
+    return GKS_OK;
+}
+
+int gks_free(gks_handle* h)
+{
+    release(h);
+    return GKS_OK;
+}
+
+const char* gks_last_error(const gks_handle* h)
+{
+    return h ? h->err.c_str() : g_init_error.c_str();
+}
+
+int gks_kernel_timing(gks_handle* h, int32_t enable)
+{
+    if (!h) return fail(nullptr, GKS_EINVAL, "NULL handle");
+    h->timing = enable != 0;
+    for (int k = 0; k < 3; ++k) { h->tot_ms[k] = 0.0; h->launches[k] = 0; }
+    return GKS_OK;
+}
+
+int gks_kernel_time(gks_handle* h, int32_t kernel_id, double* total_ms, int64_t* launches)
+{
+    if (!h || kernel_id < 0 || kernel_id > 2) return fail(h, GKS_EINVAL, "bad kernel id");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    harvest(h);
+    if (total_ms) *total_ms = h->tot_ms[kernel_id];
+    if (launches) *launches = h->launches[kernel_id];
+    return GKS_OK;
+}
+
+int gks_cell_updates(const gks_handle* h, int64_t* count)
+{
+    if (!h || !count) return GKS_EINVAL;
+    *count = h->last_updates;
+    return GKS_OK;
+}
+
+} // extern "C"

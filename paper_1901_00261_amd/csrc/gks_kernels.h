@@ -1,0 +1,657 @@
+// gks_kernels.h -- HIP kernels of the compact gas-kinetic scheme for gfx950.
+//
+// Data layout in HBM (all FP64, structure of arrays so that consecutive
+// threads touch consecutive addresses):
+//   1-D (batched): W[buf][3][Ntot], Wx[buf][3][Ntot]; problem p owns cells
+//     coff_p .. coff_p + nx_p - 1.  Two buffers: W^n and the buffer that
+//     receives W* and then W^{n+1} (the step commits by flipping `cur`, so a
+//     failing step leaves W^n untouched).
+//   2-D (one problem): W[buf][4][ny][nx], Wx, Wy alike.
+//   Face arrays: 1-D [3][F] with F = sum_p (nx_p + 1); 2-D x faces
+//     [4][ny][nx+1], y faces [4][ny+1][nx]; face-row reconstructions
+//     [28][rows][faces].
+// Ghost cells are never stored: stencil gathers map indices through the
+// boundary condition (periodic wrap; extrapolation = copy of the boundary
+// cell with the normal slope set to zero).
+#pragma once
+
+#include "gks_math.h"
+
+namespace gks {
+
+struct ProbParam {
+    int nx, ny;
+    long long coff; // first cell (1-D batching)
+    long long foff; // first face (1-D batching)
+    double dx, dy, gamma, K, mu, cfl, dt_fixed, t_end;
+    int order, recon, bc[4];
+};
+
+struct ProbState {
+    double t, dt;
+    long long nsteps;
+    unsigned long long smax; // bits of a non-negative double (max signal speed / dx)
+    int active;              // still short of t_end and no error
+    int err;                 // a non-physical state was met in this step
+    int cur;                 // buffer holding W^n
+    int last;                // this step ends at t_end
+};
+
+struct Tile {
+    int p;     // problem
+    int start; // first face / cell of the tile
+};
+
+constexpr int kBlock1D = 128;
+
+// cell index through the boundary condition; zero: the normal slope of a
+// ghost cell of an extrapolated side
+__device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi, bool& zero)
+{
+    zero = false;
+    if (c < 0) {
+        if (bc_lo == 0) return c + n;
+        zero = true;
+        return 0;
+    }
+    if (c >= n) {
+        if (bc_hi == 0) return c - n;
+        zero = true;
+        return n - 1;
+    }
+    return c;
+}
+
+__device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// block-wide maximum of a non-negative value, one atomic per block
+__device__ __forceinline__ void block_max_atomic(double v, unsigned long long* dst)
+{
+    __shared__ double red[16];
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wid = (threadIdx.x + threadIdx.y * blockDim.x) >> 6;
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x + threadIdx.y * blockDim.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < nw; ++w) m = fmax(m, red[w]);
+        if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction at one face from a 4-cell stencil (local frame, slot 1 =
+// normal velocity).  Wk/Dk: cell averages and cell-width * normal slopes of
+// cells i-1..i+2.  Output (local frame): o[0] W0, o[1] dn W0 (per unit
+// length), o[2] dnn W0, o[3] Wl, o[4] Wr, o[5] dn Wl, o[6] dn Wr.
+// Non-physical WENO states fall back to the adjacent cell average.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM, int ORDER>
+__device__ __forceinline__ bool face_recon(const double (&Wk)[4][4], const double (&Dk)[4][4], double h, double gamma,
+                                           bool weno, double (&o)[7][4])
+{
+    const double ih = 1.0 / h;
+    // offsets from the cell left of the face keep the differences exact
+    double base[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) base[k] = Wk[1][k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (DIM == 1 && k == 2) {
+#pragma unroll
+            for (int q = 0; q < 7; ++q) o[q][k] = 0.0;
+            continue;
+        }
+        T w[4], d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { w[q] = T(Wk[q][k] - base[k]); d[q] = T(Dk[q][k]); }
+        T v, vx, vxx;
+        linear_recon<T, ORDER>(w, d, v, vx, vxx);
+        o[0][k] = base[k] + double(v);
+        o[1][k] = double(vx) * ih;
+        o[2][k] = double(vxx) * ih * ih;
+    }
+    if (!weno) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            o[3][k] = o[4][k] = o[0][k];
+            o[5][k] = o[6][k] = o[1][k];
+        }
+        return true;
+    }
+    // characteristic frame at the mean of the two interface cells
+    double Wm[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wm[k] = 0.5 * (Wk[1][k] + Wk[2][k]);
+    double R[4][4], L[4][4];
+    if (!char_frame<double, DIM>(Wm, gamma, R, L)) return false;
+    double ql[4], qr[4], qlx[4], qrx[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (DIM == 1 && a == 2) { ql[a] = qr[a] = qlx[a] = qrx[a] = 0.0; continue; }
+        T w[4], d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double sw = 0.0, sd = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sw += L[a][k] * (Wk[q][k] - base[k]);
+                sd += L[a][k] * Dk[q][k];
+            }
+            w[q] = T(sw);
+            d[q] = T(sd);
+        }
+        T vl, dl, vr, dr;
+        weno_left<T, ORDER>(w, d, vl, dl);
+        weno_right<T, ORDER>(w, d, vr, dr);
+        ql[a] = double(vl); qlx[a] = double(dl); qr[a] = double(vr); qrx[a] = double(dr);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double sl = 0.0, sr = 0.0, slx = 0.0, srx = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            sl += R[k][a] * ql[a];
+            sr += R[k][a] * qr[a];
+            slx += R[k][a] * qlx[a];
+            srx += R[k][a] * qrx[a];
+        }
+        o[3][k] = base[k] + sl;
+        o[4][k] = base[k] + sr;
+        o[5][k] = slx * ih;
+        o[6][k] = srx * ih;
+    }
+    if (!physical<double>(o[3], gamma, DIM))
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[3][k] = Wk[1][k];
+    if (!physical<double>(o[4], gamma, DIM))
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[4][k] = Wk[2][k];
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// 1-D interface kernel: one thread per face.
+//   STAGE 1: writes FL, FdL, Wfs = S0 + dt/2 S1 + dt^2/8 S2 (interface value
+//            at t*), Pf = S0 + dt S1 + dt^2/6 S2 (MSMD partial)
+//   STAGE 2: writes FdL and Wfs = Pf + dt^2/3 S2* (interface value at t^{n+1})
+// ---------------------------------------------------------------------------
+template <typename T, int STAGE>
+__global__ void __launch_bounds__(kBlock1D) face1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                          const Tile* __restrict__ tiles, const double* __restrict__ W,
+                                                          const double* __restrict__ Wx, long long Ntot, long long F,
+                                                          double* __restrict__ FL, double* __restrict__ FdL,
+                                                          double* __restrict__ Wfs, double* __restrict__ Pf)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const ProbParam& P = PP[tl.p];
+    ProbState& S = PS[tl.p];
+    if (!S.active) return;
+    const int f = tl.start + threadIdx.x;
+    if (f > P.nx) return;
+    const int buf = (STAGE == 1) ? S.cur : 1 - S.cur;
+    const double dt = S.dt;
+    const double* Wb = W + (size_t)buf * 3 * Ntot + P.coff;
+    const double* Xb = Wx + (size_t)buf * 3 * Ntot + P.coff;
+    double Wk[4][4], Dk[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        bool zero;
+        const int c = map_index(f - 2 + q, P.nx, P.bc[0], P.bc[1], zero);
+        Wk[q][0] = Wb[c];
+        Wk[q][1] = Wb[Ntot + c];
+        Wk[q][2] = 0.0;
+        Wk[q][3] = Wb[2 * Ntot + c];
+        Dk[q][0] = zero ? 0.0 : P.dx * Xb[c];
+        Dk[q][1] = zero ? 0.0 : P.dx * Xb[Ntot + c];
+        Dk[q][2] = 0.0;
+        Dk[q][3] = zero ? 0.0 : P.dx * Xb[2 * Ntot + c];
+    }
+    double o[7][4];
+    bool ok = (P.order == 8) ? face_recon<T, 1, 8>(Wk, Dk, P.dx, P.gamma, P.recon != 0, o)
+                             : face_recon<T, 1, 6>(Wk, Dk, P.dx, P.gamma, P.recon != 0, o);
+    PointIn<T> in;
+    PointOut<T> out;
+    if (ok) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            in.W0[k] = T(o[0][k]); in.W0x[k] = T(o[1][k]); in.W0xx[k] = T(o[2][k]);
+            in.W0y[k] = in.W0xy[k] = in.W0yy[k] = T(0);
+            in.Wl[k] = T(o[3][k]); in.Wr[k] = T(o[4][k]);
+            in.Wlx[k] = T(o[5][k]); in.Wrx[k] = T(o[6][k]);
+            in.Wly[k] = in.Wry[k] = T(0);
+        }
+        if (P.recon) ok = kinetic_average<T, 1>(in.Wl, in.Wr, T(P.gamma), T(P.K), in.W0);
+    }
+    if (ok) {
+        const PointPar par{P.gamma, P.K, P.mu, dt};
+        ok = gks_point<T, 1>(par, in, out);
+    }
+    if (!ok) {
+        S.err = 1;
+        return;
+    }
+    const long long g = P.foff + f;
+    const int slot[3] = {0, 1, 3};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int s = slot[k];
+        if (STAGE == 1) {
+            FL[k * F + g] = double(out.FL[s]);
+            FdL[k * F + g] = double(out.FdL[s]);
+            const double s0 = double(out.S0[s]), s1 = double(out.S1[s]), s2 = double(out.S2[s]);
+            Wfs[k * F + g] = s0 + 0.5 * dt * s1 + 0.125 * dt * dt * s2;
+            Pf[k * F + g] = s0 + dt * s1 + dt * dt / 6.0 * s2;
+        } else {
+            FdL[k * F + g] = double(out.FdL[s]);
+            Wfs[k * F + g] = Pf[k * F + g] + dt * dt / 3.0 * double(out.S2[s]);
+        }
+    }
+}
+
+// 1-D cell update, one thread per cell.
+template <int STAGE>
+__global__ void __launch_bounds__(kBlock1D) cell1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                          const Tile* __restrict__ tiles, double* __restrict__ W,
+                                                          double* __restrict__ Wx, double* __restrict__ PW, long long Ntot,
+                                                          long long F, const double* __restrict__ FL,
+                                                          const double* __restrict__ FdL, const double* __restrict__ Wfs)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const ProbParam& P = PP[tl.p];
+    ProbState& S = PS[tl.p];
+    if (!S.active) return; // block-uniform
+    const int i = tl.start + threadIdx.x;
+    const bool live = i < P.nx;
+    const int cur = S.cur, nxt = 1 - cur;
+    const double dt = S.dt, idx = 1.0 / P.dx;
+    const long long c = P.coff + (live ? i : 0);
+    const long long f = P.foff + (live ? i : 0);
+    double wn[3];
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double dL = -(FdL[k * F + f + 1] - FdL[k * F + f]) * idx;
+            const double slope = (Wfs[k * F + f + 1] - Wfs[k * F + f]) * idx;
+            if (STAGE == 1) {
+                const double L = -(FL[k * F + f + 1] - FL[k * F + f]) * idx;
+                const double w = W[((size_t)cur * 3 + k) * Ntot + c];
+                W[((size_t)nxt * 3 + k) * Ntot + c] = w + 0.5 * dt * L + 0.125 * dt * dt * dL;
+                PW[k * Ntot + c] = w + dt * L + dt * dt / 6.0 * dL;
+            } else {
+                wn[k] = PW[k * Ntot + c] + dt * dt / 3.0 * dL;
+                W[((size_t)nxt * 3 + k) * Ntot + c] = wn[k];
+            }
+            Wx[((size_t)nxt * 3 + k) * Ntot + c] = slope;
+        }
+    }
+    if (STAGE == 2) {
+        double s = 0.0;
+        if (live) {
+            const double rho = wn[0], U = wn[1] / rho;
+            const double p = (P.gamma - 1.0) * (wn[2] - 0.5 * rho * U * U);
+            if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
+            else s = (fabs(U) + sqrt(P.gamma * p / rho)) * idx;
+        }
+        block_max_atomic(s, &S.smax);
+    }
+}
+
+// maximum signal speed of the current state (start of a run)
+__global__ void __launch_bounds__(kBlock1D) signal1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                            const Tile* __restrict__ tiles, const double* __restrict__ W,
+                                                            long long Ntot)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const ProbParam& P = PP[tl.p];
+    ProbState& S = PS[tl.p];
+    const int i = tl.start + threadIdx.x;
+    double s = 0.0;
+    if (i < P.nx) {
+        const long long c = P.coff + i;
+        const double* Wb = W + (size_t)S.cur * 3 * Ntot;
+        const double rho = Wb[c], U = Wb[Ntot + c] / rho;
+        const double p = (P.gamma - 1.0) * (Wb[2 * Ntot + c] - 0.5 * rho * U * U);
+        if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
+        else s = (fabs(U) + sqrt(P.gamma * p / rho)) / P.dx;
+    }
+    block_max_atomic(s, &S.smax);
+}
+
+// ---------------------------------------------------------------------------
+// Per-problem step bookkeeping (one thread per problem).
+//   commit = 1: the step just run is accepted (flip buffers, advance t) or,
+//               after an error, the problem stops with W^n kept.
+//   Then the next dt follows from the maximum signal speed of the state.
+// ---------------------------------------------------------------------------
+__global__ void finish_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob, int commit)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    const ProbParam& P = PP[p];
+    ProbState& S = PS[p];
+    if (!S.active) return;
+    if (S.err) {
+        S.active = 0;
+        return;
+    }
+    if (commit) {
+        S.cur = 1 - S.cur;
+        S.t = S.last ? P.t_end : S.t + S.dt;
+        S.nsteps += 1;
+    }
+    const double smax = bits_to_double(S.smax);
+    S.smax = 0ull;
+    if (!(S.t < P.t_end)) {
+        S.active = 0;
+        return;
+    }
+    double dt = P.dt_fixed > 0.0 ? P.dt_fixed : P.cfl / smax;
+    int last = 0;
+    if (S.t + dt >= P.t_end - 1e-9 * dt) {
+        dt = P.t_end - S.t;
+        last = 1;
+    }
+    S.dt = dt;
+    S.last = last;
+}
+
+// ---------------------------------------------------------------------------
+// 2-D.  DIR 0: x faces, DIR 1: y faces (local frame swaps slots 1 and 2).
+// Face-row kernel: one thread per (face, transverse row incl. two ghost rows
+// per side); stores the seven reconstructed vectors of face_recon.
+// Row buffer R[28][A][B], thread-x index b fastest:
+//   DIR 0: a = row + 2 (ny + 4 rows), b = face (nx + 1)
+//   DIR 1: a = face (ny + 1), b = column + 2 (nx + 4)
+// ---------------------------------------------------------------------------
+template <typename T, int DIR>
+__global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                    const double* __restrict__ W, const double* __restrict__ Wx,
+                                                    const double* __restrict__ Wy, int stage, double* __restrict__ R)
+{
+    const ProbParam& P = PP[0];
+    ProbState& S = PS[0];
+    if (!S.active) return;
+    const int nx = P.nx, ny = P.ny;
+    const int nf = DIR == 0 ? nx + 1 : ny + 1;
+    const int nt = DIR == 0 ? ny : nx;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y * blockDim.y + threadIdx.y;
+    const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
+    if (a >= A || b >= B) return;
+    const int face = DIR == 0 ? b : a;
+    const int tr = (DIR == 0 ? a : b) - 2; // transverse index, -2 .. nt+1
+    const int buf = stage == 1 ? S.cur : 1 - S.cur;
+    const size_t plane = (size_t)nx * ny;
+    const double* Wb = W + (size_t)buf * 4 * plane;
+    const double* Nb = (DIR == 0 ? Wx : Wy) + (size_t)buf * 4 * plane;
+    const double h = DIR == 0 ? P.dx : P.dy;
+    double Wk[4][4], Dk[4][4];
+    bool zt;
+    const int t = DIR == 0 ? map_index(tr, ny, P.bc[2], P.bc[3], zt) : map_index(tr, nx, P.bc[0], P.bc[1], zt);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        bool zn;
+        const int c = DIR == 0 ? map_index(face - 2 + q, nx, P.bc[0], P.bc[1], zn)
+                               : map_index(face - 2 + q, ny, P.bc[2], P.bc[3], zn);
+        const size_t cell = DIR == 0 ? (size_t)t * nx + c : (size_t)c * nx + t;
+        double w[4], d[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w[k] = Wb[k * plane + cell];
+            d[k] = zn ? 0.0 : h * Nb[k * plane + cell];
+        }
+        // local frame: normal velocity in slot 1
+        Wk[q][0] = w[0]; Wk[q][3] = w[3]; Dk[q][0] = d[0]; Dk[q][3] = d[3];
+        Wk[q][1] = DIR == 0 ? w[1] : w[2]; Wk[q][2] = DIR == 0 ? w[2] : w[1];
+        Dk[q][1] = DIR == 0 ? d[1] : d[2]; Dk[q][2] = DIR == 0 ? d[2] : d[1];
+    }
+    double o[7][4];
+    const bool ok = (P.order == 8) ? face_recon<T, 2, 8>(Wk, Dk, h, P.gamma, P.recon != 0, o)
+                                   : face_recon<T, 2, 6>(Wk, Dk, h, P.gamma, P.recon != 0, o);
+    if (!ok) {
+        S.err = 1;
+        return;
+    }
+    const size_t AB = (size_t)A * B, ab = (size_t)a * B + b;
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R[(q * 4 + k) * AB + ab] = o[q][k];
+}
+
+// Gauss-point kernel: one thread per (face, interior transverse cell); three
+// Gauss points of the 3-point rule, tangential reconstruction from the five
+// face rows, the interface distribution at each point, Gauss sums.
+// Outputs in the global frame: x faces [4][ny][nx+1], y faces [4][ny+1][nx].
+template <typename T, int G>
+__device__ __forceinline__ bool gauss_point(const double* __restrict__ R, size_t AB, size_t a0, size_t bstride,
+                                            double ht, bool weno, const PointPar& par, double gamma, PointOut<T>& out)
+{
+    // row r (0..4) of quantity q, component k: R[(q*4+k)*AB + a0 + r*bstride]
+    auto rv = [&](int q, int k, int r) { return R[(size_t)(q * 4 + k) * AB + a0 + (size_t)r * bstride]; };
+    PointIn<T> in;
+    const double iht = 1.0 / ht;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v0 = 0, v1 = 0, v2 = 0, v5 = 0, v6 = 0, d0 = 0, d1 = 0, d3 = 0, d4 = 0, dd0 = 0;
+        const double base = rv(0, k, 2);
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const double c0 = kTanLin[G][0][r], c1 = kTanLin[G][1][r], c2 = kTanLin[G][2][r];
+            const double q0 = rv(0, k, r) - base;
+            v0 += c0 * q0;
+            d0 += c1 * q0;
+            dd0 += c2 * q0;
+            const double q1 = rv(1, k, r);
+            v1 += c0 * q1;
+            d1 += c1 * q1;
+            v2 += c0 * rv(2, k, r);
+            v5 += c0 * rv(5, k, r);
+            v6 += c0 * rv(6, k, r);
+            d3 += c1 * (rv(3, k, r) - base);
+            d4 += c1 * (rv(4, k, r) - base);
+        }
+        in.W0[k] = T(base + v0);
+        in.W0x[k] = T(v1);
+        in.W0xx[k] = T(v2);
+        in.W0y[k] = T(d0 * iht);
+        in.W0xy[k] = T(d1 * iht);
+        in.W0yy[k] = T(dd0 * iht * iht);
+        in.Wlx[k] = T(v5);
+        in.Wrx[k] = T(v6);
+        in.Wly[k] = T(d3 * iht);
+        in.Wry[k] = T(d4 * iht);
+        if (!weno) {
+            in.Wl[k] = in.Wr[k] = in.W0[k];
+        } else {
+            double ql[5], qr[5];
+#pragma unroll
+            for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
+            in.Wl[k] = T(base + tan_weno<double, G>(ql));
+            in.Wr[k] = T(base + tan_weno<double, G>(qr));
+        }
+    }
+    if (weno) {
+        if (!physical<T>(in.Wl, T(gamma), 2))
+#pragma unroll
+            for (int k = 0; k < 4; ++k) in.Wl[k] = T(rv(3, k, 2));
+        if (!physical<T>(in.Wr, T(gamma), 2))
+#pragma unroll
+            for (int k = 0; k < 4; ++k) in.Wr[k] = T(rv(4, k, 2));
+        if (!kinetic_average<T, 2>(in.Wl, in.Wr, T(gamma), T(par.K), in.W0)) return false;
+    }
+    return gks_point<T, 2>(par, in, out);
+}
+
+template <typename T, int DIR>
+__global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                   const double* __restrict__ R, int stage, double* __restrict__ FL,
+                                                   double* __restrict__ FdL, double* __restrict__ Wfs,
+                                                   double* __restrict__ Pf)
+{
+    const ProbParam& P = PP[0];
+    ProbState& S = PS[0];
+    if (!S.active) return;
+    const int nx = P.nx, ny = P.ny;
+    const int nf = DIR == 0 ? nx + 1 : ny + 1;
+    const int nt = DIR == 0 ? ny : nx;
+    const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x; // DIR 0: face, DIR 1: transverse cell
+    const int a = blockIdx.y * blockDim.y + threadIdx.y; // DIR 0: transverse cell, DIR 1: face
+    const int face = DIR == 0 ? b : a, tc = DIR == 0 ? a : b;
+    if (face >= nf || tc >= nt) return;
+    const size_t AB = (size_t)A * B;
+    // row r of the stencil = transverse index tc - 2 + r, stored at (tc + r)
+    const size_t a0 = DIR == 0 ? (size_t)tc * B + face : (size_t)face * B + tc;
+    const size_t bstride = DIR == 0 ? (size_t)B : 1;
+    const double ht = DIR == 0 ? P.dy : P.dx;
+    const double dt = S.dt;
+    const PointPar par{P.gamma, P.K, P.mu, dt};
+    const bool weno = P.recon != 0;
+    double acc[5][4];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[q][k] = 0.0;
+    constexpr double wg[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    bool ok = true;
+    {
+        PointOut<T> o;
+        ok = ok && gauss_point<T, 0>(R, AB, a0, bstride, ht, weno, par, P.gamma, o);
+        if (ok)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                acc[0][k] += wg[0] * double(o.FL[k]); acc[1][k] += wg[0] * double(o.FdL[k]);
+                acc[2][k] += wg[0] * double(o.S0[k]); acc[3][k] += wg[0] * double(o.S1[k]);
+                acc[4][k] += wg[0] * double(o.S2[k]);
+            }
+    }
+    {
+        PointOut<T> o;
+        ok = ok && gauss_point<T, 1>(R, AB, a0, bstride, ht, weno, par, P.gamma, o);
+        if (ok)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                acc[0][k] += wg[1] * double(o.FL[k]); acc[1][k] += wg[1] * double(o.FdL[k]);
+                acc[2][k] += wg[1] * double(o.S0[k]); acc[3][k] += wg[1] * double(o.S1[k]);
+                acc[4][k] += wg[1] * double(o.S2[k]);
+            }
+    }
+    {
+        PointOut<T> o;
+        ok = ok && gauss_point<T, 2>(R, AB, a0, bstride, ht, weno, par, P.gamma, o);
+        if (ok)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                acc[0][k] += wg[2] * double(o.FL[k]); acc[1][k] += wg[2] * double(o.FdL[k]);
+                acc[2][k] += wg[2] * double(o.S0[k]); acc[3][k] += wg[2] * double(o.S1[k]);
+                acc[4][k] += wg[2] * double(o.S2[k]);
+            }
+    }
+    if (!ok) {
+        S.err = 1;
+        return;
+    }
+    // back to the global frame
+    const int gk[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
+    const size_t nfa = DIR == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
+    const size_t fi = DIR == 0 ? (size_t)tc * (nx + 1) + face : (size_t)face * nx + tc;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t o = (size_t)gk[k] * nfa + fi;
+        if (stage == 1) {
+            FL[o] = acc[0][k];
+            FdL[o] = acc[1][k];
+            Wfs[o] = acc[2][k] + 0.5 * dt * acc[3][k] + 0.125 * dt * dt * acc[4][k];
+            Pf[o] = acc[2][k] + dt * acc[3][k] + dt * dt / 6.0 * acc[4][k];
+        } else {
+            FdL[o] = acc[1][k];
+            Wfs[o] = Pf[o] + dt * dt / 3.0 * acc[4][k];
+        }
+    }
+}
+
+// 2-D cell update: one thread per cell.
+template <int STAGE>
+__global__ void __launch_bounds__(256) cell2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                     double* __restrict__ W, double* __restrict__ Wx,
+                                                     double* __restrict__ Wy, double* __restrict__ PW,
+                                                     const double* __restrict__ FLx, const double* __restrict__ FdLx,
+                                                     const double* __restrict__ Wfx, const double* __restrict__ FLy,
+                                                     const double* __restrict__ FdLy, const double* __restrict__ Wfy)
+{
+    const ProbParam& P = PP[0];
+    ProbState& S = PS[0];
+    if (!S.active) return;
+    const int nx = P.nx, ny = P.ny;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const bool live = i < nx && j < ny;
+    const int cur = S.cur, nxt = 1 - cur;
+    const double dt = S.dt, idx = 1.0 / P.dx, idy = 1.0 / P.dy;
+    const size_t plane = (size_t)nx * ny;
+    const size_t nfx = (size_t)ny * (nx + 1), nfy = (size_t)(ny + 1) * nx;
+    double wn[4];
+    if (live) {
+        const size_t c = (size_t)j * nx + i;
+        const size_t fx = (size_t)j * (nx + 1) + i, fy = (size_t)j * nx + i;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double dL = -(FdLx[k * nfx + fx + 1] - FdLx[k * nfx + fx]) * idx -
+                              (FdLy[k * nfy + fy + nx] - FdLy[k * nfy + fy]) * idy;
+            if (STAGE == 1) {
+                const double L = -(FLx[k * nfx + fx + 1] - FLx[k * nfx + fx]) * idx -
+                                 (FLy[k * nfy + fy + nx] - FLy[k * nfy + fy]) * idy;
+                const double w = W[((size_t)cur * 4 + k) * plane + c];
+                W[((size_t)nxt * 4 + k) * plane + c] = w + 0.5 * dt * L + 0.125 * dt * dt * dL;
+                PW[k * plane + c] = w + dt * L + dt * dt / 6.0 * dL;
+            } else {
+                wn[k] = PW[k * plane + c] + dt * dt / 3.0 * dL;
+                W[((size_t)nxt * 4 + k) * plane + c] = wn[k];
+            }
+            Wx[((size_t)nxt * 4 + k) * plane + c] = (Wfx[k * nfx + fx + 1] - Wfx[k * nfx + fx]) * idx;
+            Wy[((size_t)nxt * 4 + k) * plane + c] = (Wfy[k * nfy + fy + nx] - Wfy[k * nfy + fy]) * idy;
+        }
+    }
+    if (STAGE == 2) {
+        double s = 0.0;
+        if (live) {
+            const double rho = wn[0], U = wn[1] / rho, V = wn[2] / rho;
+            const double p = (P.gamma - 1.0) * (wn[3] - 0.5 * rho * (U * U + V * V));
+            if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
+            else {
+                const double c = sqrt(P.gamma * p / rho);
+                s = fmax((fabs(U) + c) * idx, (fabs(V) + c) * idy);
+            }
+        }
+        block_max_atomic(s, &S.smax);
+    }
+}
+
+__global__ void __launch_bounds__(256) signal2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                       const double* __restrict__ W)
+{
+    const ProbParam& P = PP[0];
+    ProbState& S = PS[0];
+    const int nx = P.nx, ny = P.ny;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const size_t plane = (size_t)nx * ny;
+    double s = 0.0;
+    if (i < nx && j < ny) {
+        const size_t c = (size_t)j * nx + i;
+        const double* Wb = W + (size_t)S.cur * 4 * plane;
+        const double rho = Wb[c], U = Wb[plane + c] / rho, V = Wb[2 * plane + c] / rho;
+        const double p = (P.gamma - 1.0) * (Wb[3 * plane + c] - 0.5 * rho * (U * U + V * V));
+        if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
+        else {
+            const double cs = sqrt(P.gamma * p / rho);
+            s = fmax((fabs(U) + cs) / P.dx, (fabs(V) + cs) / P.dy);
+        }
+    }
+    block_max_atomic(s, &S.smax);
+}
+
+} // namespace gks

@@ -1,0 +1,739 @@
+// gks_math.h -- per-interface arithmetic of the compact 6th/8th-order
+// gas-kinetic scheme (Zhao, Ji, Shyy, Xu, arXiv:1901.00261), written for
+// gfx950 VALU.  Everything here is straight-line register code, templated on
+// the arithmetic type T (double, or float in the mixed-precision path) and on
+// the dimension (1 or 2).  State vectors always have four slots
+// (rho, rho U, rho V, rho E); in 1-D slot 2 is identically zero.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <utility>
+
+#define GKS_HD __host__ __device__ __forceinline__
+
+namespace gks {
+
+// WENO-Z regularisation (reading of Sec. 3.3: 1e-6 reproduces Tables 3-4)
+constexpr double kWenoEps = 1e-6;
+
+template <typename T> GKS_HD T tabs(T x) { return x < T(0) ? -x : x; }
+
+// ---------------------------------------------------------------------------
+// Compact linear reconstruction at x_{i+1/2} (Sec. 3.1, printed formulas).
+// w[0..3] = W_{i-1..i+2} (any common offset removed), d[0..3] = dx * W'.
+// Returns the value (offset included by the caller), dx * P_x, dx^2 * P_xx.
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER>
+GKS_HD void linear_recon(const T* w, const T* d, T& v, T& vx, T& vxx)
+{
+    if constexpr (ORDER == 6) {
+        v = (w[0] + T(299) * w[1] + T(299) * w[2] + w[3] - T(3) * d[0] + T(111) * d[1] - T(111) * d[2] + T(3) * d[3]) *
+            T(1.0 / 600.0);
+        vx = (T(-3) * w[0] - T(3411) * w[1] + T(3411) * w[2] + T(3) * w[3] + T(11) * d[0] - T(941) * d[1] -
+              T(941) * d[2] + T(11) * d[3]) *
+             T(1.0 / 1560.0);
+        vxx = (-w[0] + w[1] + w[2] - w[3] + T(3) * d[0] - T(51) * d[1] + T(51) * d[2] - T(3) * d[3]) * T(1.0 / 40.0);
+    } else {
+        v = (T(25) * w[0] + T(185) * w[1] + T(185) * w[2] + T(25) * w[3] + T(6) * d[0] + T(102) * d[1] -
+             T(102) * d[2] - T(6) * d[3]) *
+            T(1.0 / 420.0);
+        vx = (T(-14) * w[0] - T(270) * w[1] + T(270) * w[2] + T(14) * w[3] - T(3) * d[0] - T(99) * d[1] -
+              T(99) * d[2] - T(3) * d[3]) *
+             T(1.0 / 108.0);
+        vxx = (T(-4) * w[0] + T(4) * w[1] + T(4) * w[2] - T(4) * w[3] - d[0] - T(9) * d[1] + T(9) * d[2] + d[3]) *
+              T(0.25);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compact WENO-Z, left state at x_{i+1/2} of one characteristic field
+// (Sec. 3.3 and Appendix).  Candidate values: eq. (sub-stencil); candidate
+// polynomial coefficients b_k = a_k dx^k: Appendix (w_6 with '+' before its
+// x^4 term); smoothness indicator: the exact integral, whose (a_4 dx^4)^2
+// coefficient is 87617/80640.  val: state; der: dx * derivative (weights
+// applied to the candidates' derivatives at the interface).
+// ---------------------------------------------------------------------------
+template <typename T>
+GKS_HD T beta4(T b1, T b2, T b3, T b4)
+{
+    return b1 * b1 + T(13.0 / 12.0) * b2 * b2 + T(1043.0 / 960.0) * b3 * b3 + T(87617.0 / 80640.0) * b4 * b4 +
+           T(1.0 / 12.0) * b1 * b3 + T(7.0 / 80.0) * b2 * b4;
+}
+template <typename T> GKS_HD T beta2(T b1, T b2) { return b1 * b1 + T(13.0 / 12.0) * b2 * b2; }
+template <typename T> GKS_HD T beta3(T b1, T b2, T b3)
+{
+    return b1 * b1 + T(13.0 / 12.0) * b2 * b2 + T(1043.0 / 960.0) * b3 * b3 + T(1.0 / 12.0) * b1 * b3;
+}
+
+template <typename T, int ORDER>
+GKS_HD void weno_left(const T* w, const T* d, T& val, T& der)
+{
+    // candidate values at x_{i+1/2}
+    const T c0 = (T(-7) * w[0] + T(13) * w[1] - T(4) * d[0]) * T(1.0 / 6.0);
+    const T c1 = (-w[0] + T(5) * w[1] + T(2) * w[2]) * T(1.0 / 6.0); // w_1 == w_3
+    const T c2 = (T(5) * w[1] + T(32) * w[2] - T(13) * w[3] + T(6) * d[3]) * T(1.0 / 24.0);
+    const T c4 = (T(2) * w[1] + T(5) * w[2] - w[3]) * T(1.0 / 6.0);
+    const T c5 = (T(10) * w[0] + T(19) * w[1] + w[2] + T(3) * d[0] + T(21) * d[1]) * T(1.0 / 30.0);
+    const T c6 = (w[1] + T(19) * w[2] + T(10) * w[3] - T(21) * d[2] - T(3) * d[3]) * T(1.0 / 30.0);
+    // Appendix polynomial coefficients (origin at x_i)
+    const T a01 = T(-2) * w[0] + T(2) * w[1] - d[0];
+    const T a02 = T(-2) * (w[0] - w[1] + d[0]);
+    const T t11 = (T(-23) * w[0] + T(20) * w[1] + T(3) * w[2] - T(10) * d[0]) * T(1.0 / 16.0);
+    const T t12 = w[0] - T(2) * w[1] + w[2];
+    const T t13 = T(1.5) * (T(3) * w[0] - T(4) * w[1] + w[2] + T(2) * d[0]);
+    const T a21 = (T(-31) * w[1] + T(60) * w[2] - T(29) * w[3] + T(14) * d[3]) * T(1.0 / 16.0);
+    const T a22 = T(0.5) * (T(5) * w[1] - T(16) * w[2] + T(11) * w[3] - T(6) * d[3]);
+    const T a23 = T(1.5) * (-w[1] + T(4) * w[2] - T(3) * w[3] + T(2) * d[3]);
+    const T a31 = T(0.5) * (w[2] - w[0]);
+    const T a32 = w[0] - T(2) * w[1] + w[2];
+    const T a41 = T(0.5) * (T(-3) * w[1] + T(4) * w[2] - w[3]);
+    const T a42 = w[1] - T(2) * w[2] + w[3];
+    const T a51 = (w[0] - w[2] + T(10) * d[1]) * T(0.125);
+    const T a52 = T(0.25) * (T(19) * w[0] - T(20) * w[1] + w[2] + T(6) * d[0] + T(12) * d[1]);
+    const T a53 = T(-3) * (w[0] - w[2] + T(2) * d[1]);
+    const T a54 = T(-6) * (T(5) * w[0] - T(4) * w[1] - w[2] + T(2) * d[0] + T(4) * d[1]);
+    const T a61 = (T(-21) * w[1] + T(8) * w[2] + T(13) * w[3] - T(22) * d[2] - T(4) * d[3]) * T(0.125);
+    const T a62 = T(0.25) * (T(25) * w[1] + T(28) * w[2] - T(53) * w[3] + T(60) * d[2] + T(18) * d[3]);
+    const T a63 = T(-3) * (T(3) * w[1] + T(8) * w[2] - T(11) * w[3] + T(10) * d[2] + T(4) * d[3]);
+    const T a64 = T(6) * (w[1] + T(4) * w[2] - T(5) * w[3] + T(4) * d[2] + T(2) * d[3]);
+
+    const T b0 = beta2(a01, a02);
+    const T b1 = beta3(t11, t12, t13); // beta_1 from the cubic w~_1
+    const T b2 = beta3(a21, a22, a23);
+    const T b3 = beta2(a31, a32);
+    const T b4 = beta2(a41, a42);
+    const T b5 = beta4(a51, a52, a53, a54);
+    const T b6 = beta4(a61, a62, a63, a64);
+    const T Z = tabs(T(3) * (b0 - b4) + (b4 - b3));
+    const T eps = T(kWenoEps);
+    T d0, d1, d2, d3, d4, d5, d6;
+    if constexpr (ORDER == 6) {
+        d0 = T(33.0 / 700.0); d1 = T(11.0 / 140.0); d2 = T(22.0 / 175.0); d3 = T(11.0 / 100.0);
+        d4 = T(11.0 / 100.0); d5 = T(37.0 / 140.0); d6 = T(37.0 / 140.0);
+    } else {
+        d0 = T(3.0 / 98.0); d1 = T(5.0 / 98.0); d2 = T(4.0 / 49.0); d3 = T(7.0 / 98.0);
+        d4 = T(7.0 / 98.0); d5 = T(17.0 / 49.0); d6 = T(17.0 / 49.0);
+    }
+    const T al0 = d0 * (T(1) + Z / (b0 + eps));
+    const T al1 = d1 * (T(1) + Z / (b1 + eps));
+    const T al2 = d2 * (T(1) + Z / (b2 + eps));
+    const T al3 = d3 * (T(1) + Z / (b3 + eps));
+    const T al4 = d4 * (T(1) + Z / (b4 + eps));
+    const T al5 = d5 * (T(1) + Z / (b5 + eps));
+    const T al6 = d6 * (T(1) + Z / (b6 + eps));
+    const T inv = T(1) / (al0 + al1 + al2 + al3 + al4 + al5 + al6);
+    val = (al0 * c0 + (al1 + al3) * c1 + al2 * c2 + al4 * c4 + al5 * c5 + al6 * c6) * inv;
+    // dx * derivative of each candidate at x = dx/2: b1 + b2/2 + b3/8 + b4/48
+    const T e0 = a01 + T(0.5) * a02;
+    const T e1 = a31 + T(0.5) * a32; // w_1 and w_3 are the same quadratic
+    const T e2 = a21 + T(0.5) * a22 + T(0.125) * a23;
+    const T e4 = a41 + T(0.5) * a42;
+    const T e5 = a51 + T(0.5) * a52 + T(0.125) * a53 + T(1.0 / 48.0) * a54;
+    const T e6 = a61 + T(0.5) * a62 + T(0.125) * a63 + T(1.0 / 48.0) * a64;
+    der = (al0 * e0 + (al1 + al3) * e1 + al2 * e2 + al4 * e4 + al5 * e5 + al6 * e6) * inv;
+}
+
+// Right state at x_{i+1/2}: the mirror image (reversed stencil, slopes
+// negated, derivative negated back).
+template <typename T, int ORDER>
+GKS_HD void weno_right(const T* w, const T* d, T& val, T& der)
+{
+    const T wm[4] = {w[3], w[2], w[1], w[0]};
+    const T dm[4] = {-d[3], -d[2], -d[1], -d[0]};
+    T dd;
+    weno_left<T, ORDER>(wm, dm, val, dd);
+    der = -dd;
+}
+
+// ---------------------------------------------------------------------------
+// Euler eigenvectors in the normal direction (slot 1 = normal velocity),
+// closed form.  R: right eigenvectors as columns, L = R^{-1}.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+GKS_HD bool char_frame(const T* W, T gamma, T R[4][4], T L[4][4])
+{
+    const T rho = W[0];
+    const T U = W[1] / rho, V = (DIM == 2) ? W[2] / rho : T(0);
+    const T q2 = U * U + V * V;
+    const T p = (gamma - T(1)) * (W[3] - T(0.5) * rho * q2);
+    if (!(rho > T(0)) || !(p > T(0))) return false;
+    const T c = sqrt(gamma * p / rho);
+    const T H = (W[3] + p) / rho;
+    const T b1 = (gamma - T(1)) / (c * c);
+    const T b2 = T(0.5) * q2 * b1;
+    const T ic = T(1) / c;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) { R[a][b] = T(0); L[a][b] = T(0); }
+    // columns: acoustic-, entropy, shear (2-D), acoustic+
+    R[0][0] = T(1); R[1][0] = U - c; R[2][0] = V; R[3][0] = H - U * c;
+    R[0][1] = T(1); R[1][1] = U;     R[2][1] = V; R[3][1] = T(0.5) * q2;
+    R[0][3] = T(1); R[1][3] = U + c; R[2][3] = V; R[3][3] = H + U * c;
+    L[0][0] = T(0.5) * (b2 + U * ic); L[0][1] = T(-0.5) * (b1 * U + ic); L[0][2] = T(-0.5) * b1 * V; L[0][3] = T(0.5) * b1;
+    L[1][0] = T(1) - b2;              L[1][1] = b1 * U;                  L[1][2] = b1 * V;              L[1][3] = -b1;
+    L[3][0] = T(0.5) * (b2 - U * ic); L[3][1] = T(-0.5) * (b1 * U - ic); L[3][2] = T(-0.5) * b1 * V; L[3][3] = T(0.5) * b1;
+    if constexpr (DIM == 2) {
+        R[2][2] = T(1); R[3][2] = V;
+        L[2][0] = -V; L[2][2] = T(1);
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Tangential reconstruction at the three Gauss points y_j + s dy/2,
+// s = -sqrt(3/5), 0, +sqrt(3/5), from the five row values j-2..j+2.
+// kTanLin[g][k][r]: k-th derivative (per unit row width) of the quartic
+// matching the five row averages; kTanCand / kTanLinW: the three quadratic
+// candidates of the 5th-order WENO-Z and their linear weights at the point.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr double kTanLin[3][3][5] = {
+    {{-0.039252347340234653, 0.31298719532417346, 0.91083333333333338, -0.21632052865750681, 0.031752347340234653},
+     {0.10539650012874084, -1.1755510018023716, 1.0069756700139283, 0.091115664864294968, -0.027936833204592497},
+     {0.14364916731037083, 0.81270166537925825, -2.2999999999999998, 1.5872983346207417, -0.24364916731037084}},
+    {{0.0046874999999999998, -0.060416666666666667, 1.1114583333333334, -0.060416666666666667, 0.0046874999999999998},
+     {0.10416666666666667, -0.70833333333333337, 0.0, 0.70833333333333337, -0.10416666666666667},
+     {-0.125, 1.5, -2.75, 1.5, -0.125}},
+    {{0.031752347340234653, -0.21632052865750681, 0.91083333333333338, 0.31298719532417346, -0.039252347340234653},
+     {0.027936833204592497, -0.091115664864294968, -1.0069756700139283, 1.1755510018023716, -0.10539650012874084},
+     {-0.24364916731037084, 1.5872983346207417, -2.2999999999999998, 0.81270166537925825, 0.14364916731037083}}};
+
+__host__ __device__ constexpr double kTanCand[3][3][3] = {
+    // [gauss point][candidate][3 rows of that candidate]
+    {{-0.16031583397703753, 0.70793000257481675, 0.45238583140222077},
+     {0.22698250064370418, 0.93333333333333335, -0.16031583397703753},
+     {1.6142808352644458, -0.84126333590815006, 0.22698250064370418}},
+    {{-0.041666666666666664, 0.083333333333333329, 0.95833333333333337},
+     {-0.041666666666666664, 1.0833333333333333, -0.041666666666666664},
+     {0.95833333333333337, 0.083333333333333329, -0.041666666666666664}},
+    {{0.22698250064370418, -0.84126333590815006, 1.6142808352644458},
+     {-0.16031583397703753, 0.93333333333333335, 0.22698250064370418},
+     {0.45238583140222077, 0.70793000257481675, -0.16031583397703753}}};
+
+__host__ __device__ constexpr double kTanLinW[3][3] = {
+    {0.24484385831693256, 0.61526717557251909, 0.13988896611054835},
+    {-0.1125, 1.2250000000000001, -0.1125},
+    {0.13988896611054835, 0.61526717557251909, 0.24484385831693256}};
+
+// 5th-order WENO-Z value at Gauss point G from rows q[0..4]; the centre
+// point's negative linear weights are split into two positive groups
+// (Shi, Hu, Shu, J. Comput. Phys. 175 (2002), theta = 3).
+template <typename T, int G>
+GKS_HD T tan_weno(const T* q)
+{
+    T cand[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        cand[k] = T(kTanCand[G][k][0]) * q[k] + T(kTanCand[G][k][1]) * q[k + 1] + T(kTanCand[G][k][2]) * q[k + 2];
+    // Jiang-Shu indicators of the three quadratics over the centre row
+    const T s0a = q[0] - T(2) * q[1] + q[2], s0b = q[0] - T(4) * q[1] + T(3) * q[2];
+    const T s1a = q[1] - T(2) * q[2] + q[3], s1b = q[1] - q[3];
+    const T s2a = q[2] - T(2) * q[3] + q[4], s2b = T(3) * q[2] - T(4) * q[3] + q[4];
+    const T be[3] = {T(13.0 / 12.0) * s0a * s0a + T(0.25) * s0b * s0b, T(13.0 / 12.0) * s1a * s1a + T(0.25) * s1b * s1b,
+                     T(13.0 / 12.0) * s2a * s2a + T(0.25) * s2b * s2b};
+    const T Z = tabs(be[0] - be[2]);
+    const T eps = T(kWenoEps);
+    T r[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r[k] = T(1) + Z / (be[k] + eps);
+    if constexpr (G != 1) {
+        T a[3], s = T(0), v = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { a[k] = T(kTanLinW[G][k]) * r[k]; s += a[k]; }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v += a[k] * cand[k];
+        return v / s;
+    } else {
+        // gamma+ = (g + 3|g|)/2, gamma- = gamma+ - g
+        constexpr double gp0 = 0.1125, gp1 = 2.45, gp2 = 0.1125, sp = 2.675;
+        constexpr double gm0 = 0.225, gm1 = 1.225, gm2 = 0.225, sm = 1.675;
+        const T ap0 = T(gp0 / sp) * r[0], ap1 = T(gp1 / sp) * r[1], ap2 = T(gp2 / sp) * r[2];
+        const T am0 = T(gm0 / sm) * r[0], am1 = T(gm1 / sm) * r[1], am2 = T(gm2 / sm) * r[2];
+        const T vp = (ap0 * cand[0] + ap1 * cand[1] + ap2 * cand[2]) / (ap0 + ap1 + ap2);
+        const T vm = (am0 * cand[0] + am1 * cand[1] + am2 * cand[2]) / (am0 + am1 + am2);
+        return T(sp) * vp - T(sm) * vm;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Maxwellian moments (Sec. 2.1).  For g = rho (lam/pi)^{(K+D)/2}
+// exp(-lam((u-U)^2 + (v-V)^2 + xi^2)) with unit density:
+//   mu[n] = <u^n> (full range, u > 0 or u < 0), mv[n] = <v^n>,
+//   mx[k] = <(xi^2)^k>.  D = DIM; K internal degrees of freedom.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM, int NU>
+struct Moments {
+    T U, V, lam;
+    T mu[NU];
+    T mv[(DIM == 2) ? 9 : 1];
+    T mx[4];
+};
+
+// half: 0 full, +1 u > 0, -1 u < 0
+template <typename T, int DIM, int NU>
+GKS_HD void make_moments(T U, T V, T lam, T K, int half, Moments<T, DIM, NU>& m)
+{
+    m.U = U; m.V = V; m.lam = lam;
+    const T h = T(0.5) / lam;
+    if (half == 0) {
+        m.mu[0] = T(1);
+        m.mu[1] = U;
+    } else {
+        const T sl = sqrt(lam);
+        const T e = exp(-lam * U * U) * T(0.5) / sqrt(T(3.14159265358979323846) * lam);
+        if (half > 0) {
+            m.mu[0] = T(0.5) * erfc(-sl * U);
+            m.mu[1] = U * m.mu[0] + e;
+        } else {
+            m.mu[0] = T(0.5) * erfc(sl * U);
+            m.mu[1] = U * m.mu[0] - e;
+        }
+    }
+#pragma unroll
+    for (int n = 2; n < NU; ++n) m.mu[n] = U * m.mu[n - 1] + T(n - 1) * h * m.mu[n - 2];
+    if constexpr (DIM == 2) {
+        m.mv[0] = T(1);
+        m.mv[1] = V;
+#pragma unroll
+        for (int n = 2; n < 9; ++n) m.mv[n] = V * m.mv[n - 1] + T(n - 1) * h * m.mv[n - 2];
+    } else {
+        m.mv[0] = T(1);
+    }
+    m.mx[0] = T(1);
+    m.mx[1] = K * h;
+    m.mx[2] = m.mx[1] * (K + T(2)) * h;
+    m.mx[3] = m.mx[2] * (K + T(4)) * h;
+}
+
+// <u^A v^B Q^C>, Q = u^2 + v^2 + xi^2 (v absent in 1-D)
+template <int A, int B, int C, typename M>
+GKS_HD auto mom(const M& m) -> typename std::remove_reference<decltype(m.U)>::type
+{
+    using T = typename std::remove_reference<decltype(m.U)>::type;
+    constexpr bool two = (sizeof(m.mv) / sizeof(m.mv[0])) > 1;
+    if constexpr (!two) {
+        static_assert(B == 0, "no v moments in 1-D");
+        if constexpr (C == 0) return m.mu[A];
+        else if constexpr (C == 1) return m.mu[A + 2] + m.mu[A] * m.mx[1];
+        else if constexpr (C == 2) return m.mu[A + 4] + T(2) * m.mu[A + 2] * m.mx[1] + m.mu[A] * m.mx[2];
+        else return m.mu[A + 6] + T(3) * m.mu[A + 4] * m.mx[1] + T(3) * m.mu[A + 2] * m.mx[2] + m.mu[A] * m.mx[3];
+    } else {
+        const T* u = m.mu;
+        const T* v = m.mv;
+        const T* x = m.mx;
+        if constexpr (C == 0) return u[A] * v[B];
+        else if constexpr (C == 1) return u[A + 2] * v[B] + u[A] * (v[B + 2] + v[B] * x[1]);
+        else if constexpr (C == 2)
+            return u[A + 4] * v[B] + u[A] * (v[B + 4] + v[B] * x[2] + T(2) * v[B + 2] * x[1]) +
+                   T(2) * u[A + 2] * (v[B + 2] + v[B] * x[1]);
+        else
+            return u[A + 6] * v[B] + u[A] * (v[B + 6] + v[B] * x[3] + T(3) * v[B + 4] * x[1] + T(3) * v[B + 2] * x[2]) +
+                   T(3) * u[A + 4] * (v[B + 2] + v[B] * x[1]) +
+                   u[A + 2] * (T(3) * v[B + 4] + T(3) * v[B] * x[2] + T(6) * v[B + 2] * x[1]);
+    }
+}
+
+// psi = (1, u, v, Q/2): slot -> (u power, v power, Q power)
+constexpr int kPu[4] = {0, 1, 0, 0};
+constexpr int kPv[4] = {0, 0, 1, 0};
+constexpr int kPq[4] = {0, 0, 0, 1};
+
+// <u^A v^B psi_K psi_P>
+template <int A, int B, int K, int P, typename M>
+GKS_HD auto s_elem(const M& m)
+{
+    using T = typename std::remove_reference<decltype(m.U)>::type;
+    constexpr int c = kPq[K] + kPq[P];
+    constexpr double sc = c == 0 ? 1.0 : (c == 1 ? 0.5 : 0.25);
+    return T(sc) * mom<A + kPu[K] + kPu[P], B + kPv[K] + kPv[P], c>(m);
+}
+// <u^A v^B psi_K psi_P psi_Q>
+template <int A, int B, int K, int P, int Q, typename M>
+GKS_HD auto t_elem(const M& m)
+{
+    using T = typename std::remove_reference<decltype(m.U)>::type;
+    constexpr int c = kPq[K] + kPq[P] + kPq[Q];
+    constexpr double sc = c == 0 ? 1.0 : (c == 1 ? 0.5 : (c == 2 ? 0.25 : 0.125));
+    return T(sc) * mom<A + kPu[K] + kPu[P] + kPu[Q], B + kPv[K] + kPv[P] + kPv[Q], c>(m);
+}
+
+template <int DIM> struct Slots;
+template <> struct Slots<1> { using seq = std::integer_sequence<int, 0, 1, 3>; };
+template <> struct Slots<2> { using seq = std::integer_sequence<int, 0, 1, 2, 3>; };
+
+// out_K = sum_P a_P <u^A v^B psi_P psi_K>  (a linear in psi)
+template <int A, int B, int K, typename M, typename T, int... P>
+GKS_HD T lin_row(const M& m, const T* a, std::integer_sequence<int, P...>)
+{
+    return ((a[P] * s_elem<A, B, K, P>(m)) + ...);
+}
+template <int A, int B, int DIM, typename M, typename T, int... K>
+GKS_HD void lin_impl(const M& m, const T* a, T* out, std::integer_sequence<int, K...>)
+{
+    ((out[K] = lin_row<A, B, K>(m, a, typename Slots<DIM>::seq{})), ...);
+}
+template <int A, int B, int DIM, typename M, typename T>
+GKS_HD void lin(const M& m, const T* a, T* out)
+{
+    lin_impl<A, B, DIM>(m, a, out, typename Slots<DIM>::seq{});
+}
+
+// out_K = sum_{P,Q} a_P b_Q <u^A v^B psi_P psi_Q psi_K>
+template <int A, int B, int K, int P, typename M, typename T, int... Q>
+GKS_HD T bil_inner(const M& m, const T* b, std::integer_sequence<int, Q...>)
+{
+    return ((b[Q] * t_elem<A, B, K, P, Q>(m)) + ...);
+}
+template <int A, int B, int K, int DIM, typename M, typename T, int... P>
+GKS_HD T bil_row(const M& m, const T* a, const T* b, std::integer_sequence<int, P...>)
+{
+    return ((a[P] * bil_inner<A, B, K, P>(m, b, typename Slots<DIM>::seq{})) + ...);
+}
+template <int A, int B, int DIM, typename M, typename T, int... K>
+GKS_HD void bil_impl(const M& m, const T* a, const T* b, T* out, std::integer_sequence<int, K...>)
+{
+    ((out[K] = bil_row<A, B, K, DIM>(m, a, b, typename Slots<DIM>::seq{})), ...);
+}
+template <int A, int B, int DIM, typename M, typename T>
+GKS_HD void bil(const M& m, const T* a, const T* b, T* out)
+{
+    bil_impl<A, B, DIM>(m, a, b, out, typename Slots<DIM>::seq{});
+}
+
+// Micro-coefficients a (linear in psi) with <a psi> = b for the Maxwellian
+// (U, V, lam) with unit density: the closed-form inverse of the moment
+// matrix (textbook gas-kinetic solve).  K: internal degrees of freedom.
+template <typename T, int DIM>
+GKS_HD void micro_solve(T U, T V, T lam, T K, const T* b, T* a)
+{
+    if constexpr (DIM == 2) {
+        const T e = U * U + V * V + (K + T(2)) / (T(2) * lam);
+        const T R4 = T(2) * b[3] - e * b[0];
+        const T R3 = b[2] - V * b[0];
+        const T R2 = b[1] - U * b[0];
+        a[3] = T(4) * lam * lam / (K + T(2)) * (R4 - T(2) * U * R2 - T(2) * V * R3);
+        a[2] = T(2) * lam * R3 - V * a[3];
+        a[1] = T(2) * lam * R2 - U * a[3];
+        a[0] = b[0] - U * a[1] - V * a[2] - T(0.5) * a[3] * e;
+    } else {
+        const T e = U * U + (K + T(1)) / (T(2) * lam);
+        const T R3 = T(2) * b[3] - e * b[0];
+        const T R2 = b[1] - U * b[0];
+        a[3] = T(4) * lam * lam / (K + T(1)) * (R3 - T(2) * U * R2);
+        a[1] = T(2) * lam * R2 - U * a[3];
+        a[2] = T(0);
+        a[0] = b[0] - U * a[1] - T(0.5) * a[3] * e;
+    }
+}
+
+// primitive variables of a conservative state; false if not physical
+template <typename T, int DIM>
+GKS_HD bool primitive(const T* W, T gamma, T& rho, T& U, T& V, T& lam, T& p)
+{
+    rho = W[0];
+    U = W[1] / rho;
+    V = (DIM == 2) ? W[2] / rho : T(0);
+    p = (gamma - T(1)) * (W[3] - T(0.5) * rho * (U * U + V * V));
+    lam = T(0.5) * rho / p;
+    return (rho > T(0)) && (p > T(0));
+}
+
+template <typename T> GKS_HD bool physical(const T* W, T gamma, int dim)
+{
+    const T rho = W[0];
+    const T U = W[1] / rho, V = dim == 2 ? W[2] / rho : T(0);
+    const T p = (gamma - T(1)) * (W[3] - T(0.5) * rho * (U * U + V * V));
+    return (rho > T(0)) && (p > T(0));
+}
+
+// ---------------------------------------------------------------------------
+// Time-fit coefficients of the e^{-t/tau_n} part (reading: its time
+// integrals over [0, dt/2] and [0, dt] are matched by a + b t), FP64.
+// ke, kte: value coefficients of the e and t*e parts; kde, kdte: slopes.
+// ---------------------------------------------------------------------------
+GKS_HD void exp_fit(double tau_n, double dt, double& ke, double& kte, double& kde, double& kdte)
+{
+    const double x1 = 0.5 * dt / tau_n, x2 = dt / tau_n;
+    const double q1 = exp(-x1), q2 = exp(-x2);
+    const double om1 = -expm1(-x1), om2 = -expm1(-x2); // 1 - e^{-x}
+    const double Ie1 = tau_n * om1, Ie2 = tau_n * om2;
+    const double It1 = tau_n * tau_n * om1 - tau_n * (0.5 * dt) * q1;
+    const double It2 = tau_n * tau_n * om2 - tau_n * dt * q2;
+    const double idt = 1.0 / dt;
+    ke = (4.0 * Ie1 - Ie2) * idt;
+    kde = 4.0 * (Ie2 - 2.0 * Ie1) * idt * idt;
+    kte = (4.0 * It1 - It2) * idt;
+    kdte = 4.0 * (It2 - 2.0 * It1) * idt * idt;
+}
+
+// ---------------------------------------------------------------------------
+// The interface point: simplified third-order distribution (Sec. 2.1)
+//   f = g0 [1 + Abar t + G_tt t^2/2] - tau g0 [(abar.u + Abar) + (G_xt u + G_yt v + G_tt) t]
+//       + e^{-t/tau_n} { -g0 [1 - abar.u t] + g_l [1 - a_l.u t] H(u) + g_r [1 - a_r.u t] (1-H(u)) }
+// G_.. are the exact second Taylor coefficients of the Maxwellian over g0.
+// Outputs: FL (flux giving L), FdL (flux giving dL/dt), S0, S1, S2 (moments
+// of f^n, f_t^n, f_tt^n).  Everything in the local frame (normal = slot 1).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PointIn {
+    T W0[4], W0x[4], W0y[4], W0xx[4], W0xy[4], W0yy[4];
+    T Wl[4], Wlx[4], Wly[4], Wr[4], Wrx[4], Wry[4];
+};
+template <typename T>
+struct PointOut {
+    T FL[4], FdL[4], S0[4], S1[4], S2[4];
+};
+
+struct PointPar {
+    double gamma, K, mu, dt;
+};
+
+// returns false for a non-physical state
+template <typename T, int DIM>
+GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, PointOut<T>& out)
+{
+    const T gamma = T(par.gamma), K = T(par.K);
+    T r0, U0, V0, l0, p0, rl, Ul, Vl, ll, pl, rr, Ur, Vr, lr, pr;
+    if (!primitive<T, DIM>(in.W0, gamma, r0, U0, V0, l0, p0)) return false;
+    if (!primitive<T, DIM>(in.Wl, gamma, rl, Ul, Vl, ll, pl)) return false;
+    if (!primitive<T, DIM>(in.Wr, gamma, rr, Ur, Vr, lr, pr)) return false;
+
+    // collision times (Sec. 4): physical tau in the Navier-Stokes terms,
+    // numerical tau_n (with the pressure-jump term) in the exponentials
+    const double jump = fabs((double(pl) - double(pr)) / (double(pl) + double(pr))) * par.dt;
+    const double tau_d = par.mu > 0.0 ? par.mu / double(p0) : 0.0;
+    const double tau_n = par.mu > 0.0 ? par.mu / double(p0) + jump : 0.01 * par.dt + jump;
+    double ke, kte, kde, kdte;
+    exp_fit(tau_n, par.dt, ke, kte, kde, kdte);
+    const T tau = T(tau_d);
+
+    // ---- equilibrium part, g0 (moments to degree 8) ----
+    Moments<T, DIM, 9> m0;
+    make_moments<T, DIM, 9>(U0, V0, l0, K, 0, m0);
+    const T ir0 = T(1) / r0;
+    T b[4], a1[4], a2[4] = {T(0), T(0), T(0), T(0)}, At[4], t1[4], t2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[k] = in.W0x[k] * ir0;
+    micro_solve<T, DIM>(U0, V0, l0, K, b, a1);
+    if constexpr (DIM == 2) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = in.W0y[k] * ir0;
+        micro_solve<T, DIM>(U0, V0, l0, K, b, a2);
+    }
+    // <A psi> = -<(a1 u + a2 v) psi>
+    T S1n[4];
+    lin<1, 0, DIM>(m0, a1, t1);
+    if constexpr (DIM == 2) {
+        lin<0, 1, DIM>(m0, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S1n[k] = -(t1[k] + t2[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S1n[k] = -t1[k];
+    }
+    micro_solve<T, DIM>(U0, V0, l0, K, S1n, At);
+
+    // second derivatives: G = a_lin + product, <G_xx psi> = W_xx, ...
+    T axx[4], axy[4] = {T(0), T(0), T(0), T(0)}, ayy[4] = {T(0), T(0), T(0), T(0)}, axt[4], ayt[4] = {T(0), T(0), T(0), T(0)};
+    bil<0, 0, DIM>(m0, a1, a1, t1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[k] = in.W0xx[k] * ir0 - t1[k];
+    micro_solve<T, DIM>(U0, V0, l0, K, b, axx);
+    if constexpr (DIM == 2) {
+        bil<0, 0, DIM>(m0, a1, a2, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = in.W0xy[k] * ir0 - t1[k];
+        micro_solve<T, DIM>(U0, V0, l0, K, b, axy);
+        bil<0, 0, DIM>(m0, a2, a2, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = in.W0yy[k] * ir0 - t1[k];
+        micro_solve<T, DIM>(U0, V0, l0, K, b, ayy);
+    }
+    // <(G_xx u + G_xy v + G_xt) psi> = 0
+    lin<1, 0, DIM>(m0, axx, t1);
+    bil<1, 0, DIM>(m0, a1, a1, t2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[k] = -(t1[k] + t2[k]);
+    if constexpr (DIM == 2) {
+        lin<0, 1, DIM>(m0, axy, t1);
+        bil<0, 1, DIM>(m0, a1, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] -= t1[k] + t2[k];
+    }
+    bil<0, 0, DIM>(m0, a1, At, t1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[k] -= t1[k];
+    micro_solve<T, DIM>(U0, V0, l0, K, b, axt);
+    if constexpr (DIM == 2) {
+        // <(G_xy u + G_yy v + G_yt) psi> = 0
+        lin<1, 0, DIM>(m0, axy, t1);
+        bil<1, 0, DIM>(m0, a1, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = -(t1[k] + t2[k]);
+        lin<0, 1, DIM>(m0, ayy, t1);
+        bil<0, 1, DIM>(m0, a2, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] -= t1[k] + t2[k];
+        bil<0, 0, DIM>(m0, a2, At, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] -= t1[k];
+        micro_solve<T, DIM>(U0, V0, l0, K, b, ayt);
+    }
+    // <G_tt psi> = -<(G_xt u + G_yt v) psi>  (this is f_tt's moment)
+    T S2n[4];
+    lin<1, 0, DIM>(m0, axt, t1);
+    bil<1, 0, DIM>(m0, a1, At, t2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) S2n[k] = -(t1[k] + t2[k]);
+    if constexpr (DIM == 2) {
+        lin<0, 1, DIM>(m0, ayt, t1);
+        bil<0, 1, DIM>(m0, a2, At, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S2n[k] -= t1[k] + t2[k];
+    }
+
+    // flux of the polynomial part: F0 = <u psi> - tau <u (a1 u + a2 v + A) psi>,
+    // F1 = <u A psi> - tau <u (G_xt u + G_yt v + G_tt) psi>
+    T F0[4], F1[4];
+    {
+        // Euler flux of W0 in closed form
+        const T E = in.W0[3];
+        F0[0] = in.W0[1];
+        F0[1] = in.W0[1] * U0 + p0;
+        F0[2] = in.W0[2] * U0;
+        F0[3] = U0 * (E + p0);
+    }
+    lin<1, 0, DIM>(m0, At, F1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) F1[k] *= r0;
+    if (par.mu > 0.0) {
+        T v[4];
+        lin<2, 0, DIM>(m0, a1, t1);
+        lin<1, 0, DIM>(m0, At, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = t1[k] + t2[k];
+        if constexpr (DIM == 2) {
+            lin<1, 1, DIM>(m0, a2, t1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] += t1[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) F0[k] -= tau * r0 * v[k];
+        // G_tt = a_tt + A^2 with <G_tt psi> = S2n
+        T att[4];
+        bil<0, 0, DIM>(m0, At, At, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = S2n[k] - t1[k];
+        micro_solve<T, DIM>(U0, V0, l0, K, b, att);
+        lin<2, 0, DIM>(m0, axt, t1);
+        bil<2, 0, DIM>(m0, a1, At, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = t1[k] + t2[k];
+        if constexpr (DIM == 2) {
+            lin<1, 1, DIM>(m0, ayt, t1);
+            bil<1, 1, DIM>(m0, a2, At, t2);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] += t1[k] + t2[k];
+        }
+        lin<1, 0, DIM>(m0, att, t1);
+        bil<1, 0, DIM>(m0, At, At, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) F1[k] -= tau * r0 * (v[k] + t1[k] + t2[k]);
+    }
+    // equilibrium contributions to the e^{-t/tau_n} moments:
+    //   X0 -> -<u psi>0 (flux), -W0 (state)
+    //   X1 ->  <u (a1 u + a2 v) psi>0, <(a1 u + a2 v) psi>0 = -S1n
+    T Me[4], Mte[4], Ne[4], Nte[4];
+    lin<2, 0, DIM>(m0, a1, t1);
+    if constexpr (DIM == 2) {
+        lin<1, 1, DIM>(m0, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t1[k] += t2[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Mte[k] = r0 * t1[k];
+        Ne[k] = -in.W0[k];
+        Nte[k] = -r0 * S1n[k];
+    }
+    // -<u psi>0 is minus the Euler flux of W0 (no tau terms here)
+    {
+        const T E = in.W0[3];
+        Me[0] = -in.W0[1];
+        Me[1] = -(in.W0[1] * U0 + p0);
+        Me[2] = -in.W0[2] * U0;
+        Me[3] = -U0 * (E + p0);
+    }
+
+    // ---- non-equilibrium states, half-range moments (degree 6) ----
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const T rs = side ? rr : rl, Us = side ? Ur : Ul, Vs = side ? Vr : Vl, ls = side ? lr : ll;
+        const T* Wn = side ? in.Wrx : in.Wlx;
+        const T* Wt = side ? in.Wry : in.Wly;
+        Moments<T, DIM, 7> mh;
+        make_moments<T, DIM, 7>(Us, Vs, ls, K, side ? -1 : +1, mh);
+        const T irs = T(1) / rs;
+        T as1[4], as2[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = Wn[k] * irs;
+        micro_solve<T, DIM>(Us, Vs, ls, K, b, as1);
+        if constexpr (DIM == 2) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b[k] = Wt[k] * irs;
+            micro_solve<T, DIM>(Us, Vs, ls, K, b, as2);
+        }
+        const T one[4] = {T(1), T(0), T(0), T(0)};
+        T h0[4], h1[4], h2[4], h3[4];
+        lin<0, 0, DIM>(mh, one, h0); // <psi>_half
+        lin<1, 0, DIM>(mh, one, h1); // <u psi>_half
+        lin<1, 0, DIM>(mh, as1, h2); // <a1 u psi>_half
+        lin<2, 0, DIM>(mh, as1, h3); // <a1 u^2 psi>_half
+        if constexpr (DIM == 2) {
+            lin<0, 1, DIM>(mh, as2, t1);
+            lin<1, 1, DIM>(mh, as2, t2);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { h2[k] += t1[k]; h3[k] += t2[k]; }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            Ne[k] += rs * h0[k];
+            Me[k] += rs * h1[k];
+            Nte[k] -= rs * h2[k];
+            Mte[k] -= rs * h3[k];
+        }
+    }
+
+    const T Ke = T(ke), Kte = T(kte), Kde = T(kde), Kdte = T(kdte);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        out.FL[k] = F0[k] + Ke * Me[k] + Kte * Mte[k];
+        out.FdL[k] = F1[k] + Kde * Me[k] + Kdte * Mte[k];
+        out.S0[k] = in.W0[k] + Ke * Ne[k] + Kte * Nte[k];
+        out.S1[k] = r0 * S1n[k] + Kde * Ne[k] + Kdte * Nte[k];
+        out.S2[k] = r0 * S2n[k];
+    }
+    return true;
+}
+
+// Kinetic average of two states: int psi [g_l H(u) + g_r (1 - H(u))]
+template <typename T, int DIM>
+GKS_HD bool kinetic_average(const T* Wl, const T* Wr, T gamma, T K, T* W0)
+{
+    T rl, Ul, Vl, ll, pl, rr, Ur, Vr, lr, pr;
+    if (!primitive<T, DIM>(Wl, gamma, rl, Ul, Vl, ll, pl)) return false;
+    if (!primitive<T, DIM>(Wr, gamma, rr, Ur, Vr, lr, pr)) return false;
+    Moments<T, DIM, 3> ml, mr;
+    make_moments<T, DIM, 3>(Ul, Vl, ll, K, +1, ml);
+    make_moments<T, DIM, 3>(Ur, Vr, lr, K, -1, mr);
+    const T one[4] = {T(1), T(0), T(0), T(0)};
+    T hl[4], hr[4];
+    lin<0, 0, DIM>(ml, one, hl);
+    lin<0, 0, DIM>(mr, one, hr);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) W0[k] = rl * hl[k] + rr * hr[k];
+    if constexpr (DIM == 1) W0[2] = T(0);
+    return true;
+}
+
+} // namespace gks

@@ -1,0 +1,140 @@
+"""Parity of the HIP library with the CPU oracle (needs an MI355X).
+
+Bar: FP64 path within a relative Linf of 1e-11 of the oracle (states) after
+the full run; gradients, which are differences of interface values divided by
+the cell width, within 1e-9 relative to their largest magnitude.  Inputs are
+seeded synthetic data from paper_1901_00261_amd.workloads.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_00261_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL_W = 1e-11
+TOL_SLOPE = 1e-9
+
+
+def gks():
+    from paper_1901_00261_amd import gks as g
+    return g
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def gpu_run(probs, precision=0, chunk=100000):
+    g = gks()
+    S = g.Solver(probs, precision)
+    while S.step(chunk) > 0:
+        pass
+    out = [S.state(p) for p in range(len(probs))]
+    S.close()
+    return out
+
+
+def oracle_run(p, **over):
+    kw = {**p.oracle_kwargs(), **over}
+    return oracle.run(p.dim, p.W, p.Wx, p.Wy, **kw)
+
+
+def check(p, got, want, tol_w=TOL_W, tol_s=TOL_SLOPE):
+    print(f"{p.name}: steps gpu {got[4]} oracle {want[4]}  W {rel(got[0], want[0]):.2e}  Wx {rel(got[1], want[1]):.2e}",
+          flush=True)
+    assert got[4] == want[4]
+    assert abs(got[3] - want[3]) <= 1e-13 * max(1.0, abs(want[3]))
+    assert rel(got[0], want[0]) <= tol_w
+    assert rel(got[1], want[1]) <= tol_s
+    if p.dim == 2:
+        assert rel(got[2], want[2]) <= tol_s
+
+
+def test_library_loads_and_reports_errors():
+    g = gks()
+    p = wl.sine_wave_1d(8)
+    p.order = 7
+    with pytest.raises(g.GksError) as e:
+        g.Solver(p)
+    assert e.value.code == g.GKS_EINVAL and "order" in str(e.value)
+
+
+def test_sine_6th_linear_full_run():
+    """1-D advection of rho = 1 + 0.2 sin(pi x), N = 80, CFL 0.3, t = 2 (Sec. 4.1)."""
+    p = wl.sine_wave_1d(80, order=6, recon=0)
+    got = gpu_run([p])[0]
+    want = oracle_run(p)
+    check(p, got, want)
+    assert got[3] == 2.0
+
+
+@pytest.mark.parametrize("order,recon,n", [(8, 0, 20), (6, 1, 20), (8, 1, 40)])
+def test_sine_accuracy_runs(order, recon, n):
+    p = wl.sine_wave_1d(n, order=order, recon=recon, dt_fixed=wl.accuracy_dt(n, order))
+    got = gpu_run([p])[0]
+    want = oracle_run(p)
+    check(p, got, want)
+
+
+def test_riemann_set_batched_and_sod():
+    """Seeded Riemann problems (N = 400, 8th-order WENO-Z, t = 0.14) and Sod,
+    all in one batched handle."""
+    probs = wl.riemann_set_1d(4, n=400) + [wl.riemann_1d(400, *wl.SOD)]
+    got = gpu_run(probs)
+    for p, g in zip(probs, got):
+        check(p, g, oracle_run(p), tol_w=1e-10, tol_s=1e-8)
+
+
+def test_uneven_batch_equals_solo_runs():
+    """A batch of uneven problems gives bit-for-bit the solo results."""
+    probs = wl.batch_1d(count=6, seed=11, nmin=30, nmax=300, t_end=0.05)
+    got = gpu_run(probs)
+    for p, g in zip(probs, got):
+        s = gpu_run([p])[0]
+        assert np.array_equal(g[0], s[0]) and np.array_equal(g[1], s[1]) and g[4] == s[4]
+
+
+def test_smallest_mesh_and_exact_end_time():
+    p = wl.sine_wave_1d(4, order=8, recon=1, t_end=0.37)
+    got = gpu_run([p])[0]
+    want = oracle_run(p)
+    check(p, got, want)
+    assert got[3] == 0.37
+
+
+def test_2d_vortex_navier_stokes_small():
+    p = wl.isentropic_vortex_2d(20, ny=16, mu=1e-3, acoustic_amp=1e-2)
+    g = gks()
+    S = g.Solver(p)
+    S.step(3)
+    got = S.state(0)
+    S.close()
+    want = oracle_run(p, max_steps=3)
+    check(p, got, want)
+
+
+@pytest.mark.parametrize("order,recon", [(6, 0), (8, 1)])
+def test_2d_vortex_euler_small(order, recon):
+    p = wl.isentropic_vortex_2d(16, ny=18, mu=0.0, order=order, recon=recon)
+    g = gks()
+    S = g.Solver(p)
+    S.step(2)
+    got = S.state(0)
+    S.close()
+    want = oracle_run(p, max_steps=2)
+    check(p, got, want)
+
+
+def test_2d_riemann_small():
+    p = wl.riemann_2d(24, ny=20, seed=5)
+    g = gks()
+    S = g.Solver(p)
+    S.step(6)
+    got = S.state(0)
+    S.close()
+    want = oracle_run(p, max_steps=6)
+    check(p, got, want, tol_w=1e-10, tol_s=1e-8)
