@@ -87,20 +87,19 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* d
 // length), o[2] dnn W0, o[3] Wl, o[4] Wr, o[5] dn Wl, o[6] dn Wr.
 // Non-physical WENO states fall back to the adjacent cell average.
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, int ORDER>
-__device__ __forceinline__ bool face_recon(const double (&Wk)[4][4], const double (&Dk)[4][4], double h, double gamma,
-                                           bool weno, double (&o)[7][4])
+template <typename T, int DIM, int ORDER, typename D = double>
+GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, bool weno, D (&o)[7][4])
 {
-    const double ih = 1.0 / h;
+    const D ih = D(1) / h;
     // offsets from the cell left of the face keep the differences exact
-    double base[4];
+    D base[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) base[k] = Wk[1][k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (DIM == 1 && k == 2) {
 #pragma unroll
-            for (int q = 0; q < 7; ++q) o[q][k] = 0.0;
+            for (int q = 0; q < 7; ++q) o[q][k] = D(0);
             continue;
         }
         T w[4], d[4];
@@ -108,9 +107,9 @@ __device__ __forceinline__ bool face_recon(const double (&Wk)[4][4], const doubl
         for (int q = 0; q < 4; ++q) { w[q] = T(Wk[q][k] - base[k]); d[q] = T(Dk[q][k]); }
         T v, vx, vxx;
         linear_recon<T, ORDER>(w, d, v, vx, vxx);
-        o[0][k] = base[k] + double(v);
-        o[1][k] = double(vx) * ih;
-        o[2][k] = double(vxx) * ih * ih;
+        o[0][k] = base[k] + D(v);
+        o[1][k] = D(vx) * ih;
+        o[2][k] = D(vxx) * ih * ih;
     }
     if (!weno) {
 #pragma unroll
@@ -121,19 +120,19 @@ __device__ __forceinline__ bool face_recon(const double (&Wk)[4][4], const doubl
         return true;
     }
     // characteristic frame at the mean of the two interface cells
-    double Wm[4];
+    D Wm[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Wm[k] = 0.5 * (Wk[1][k] + Wk[2][k]);
-    double R[4][4], L[4][4];
-    if (!char_frame<double, DIM>(Wm, gamma, R, L)) return false;
-    double ql[4], qr[4], qlx[4], qrx[4];
+    for (int k = 0; k < 4; ++k) Wm[k] = D(0.5) * (Wk[1][k] + Wk[2][k]);
+    D R[4][4], L[4][4];
+    if (!char_frame<D, DIM>(Wm, gamma, R, L)) return false;
+    D ql[4], qr[4], qlx[4], qrx[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        if (DIM == 1 && a == 2) { ql[a] = qr[a] = qlx[a] = qrx[a] = 0.0; continue; }
+        if (DIM == 1 && a == 2) { ql[a] = qr[a] = qlx[a] = qrx[a] = D(0); continue; }
         T w[4], d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            double sw = 0.0, sd = 0.0;
+            D sw = D(0), sd = D(0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 sw += L[a][k] * (Wk[q][k] - base[k]);
@@ -145,11 +144,11 @@ __device__ __forceinline__ bool face_recon(const double (&Wk)[4][4], const doubl
         T vl, dl, vr, dr;
         weno_left<T, ORDER>(w, d, vl, dl);
         weno_right<T, ORDER>(w, d, vr, dr);
-        ql[a] = double(vl); qlx[a] = double(dl); qr[a] = double(vr); qrx[a] = double(dr);
+        ql[a] = D(vl); qlx[a] = D(dl); qr[a] = D(vr); qrx[a] = D(dr);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double sl = 0.0, sr = 0.0, slx = 0.0, srx = 0.0;
+        D sl = D(0), sr = D(0), slx = D(0), srx = D(0);
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             sl += R[k][a] * ql[a];
@@ -162,10 +161,10 @@ __device__ __forceinline__ bool face_recon(const double (&Wk)[4][4], const doubl
         o[5][k] = slx * ih;
         o[6][k] = srx * ih;
     }
-    if (!physical<double>(o[3], gamma, DIM))
+    if (!physical<D>(o[3], gamma, DIM))
 #pragma unroll
         for (int k = 0; k < 4; ++k) o[3][k] = Wk[1][k];
-    if (!physical<double>(o[4], gamma, DIM))
+    if (!physical<D>(o[4], gamma, DIM))
 #pragma unroll
         for (int k = 0; k < 4; ++k) o[4][k] = Wk[2][k];
     return true;
@@ -421,30 +420,29 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
         for (int k = 0; k < 4; ++k) R[(q * 4 + k) * AB + ab] = o[q][k];
 }
 
-// Gauss-point kernel: one thread per (face, interior transverse cell); three
-// Gauss points of the 3-point rule, tangential reconstruction from the five
-// face rows, the interface distribution at each point, Gauss sums.
-// Outputs in the global frame: x faces [4][ny][nx+1], y faces [4][ny+1][nx].
-template <typename T, int G>
-__device__ __forceinline__ bool gauss_point(const double* __restrict__ R, size_t AB, size_t a0, size_t bstride,
-                                            double ht, bool weno, const PointPar& par, double gamma, PointOut<T>& out)
+// Gauss-point inputs at point G (0..2) of the 3-point rule: tangential
+// linear 5th-order reconstruction of the equilibrium rows and of the
+// derivatives of the non-equilibrium rows, tangential WENO-Z of the
+// non-equilibrium values (with the positivity fallback to the face-row line
+// value) and the equilibrium value as their kinetic average.  rv(q, k, r):
+// quantity q (face_recon order), component k, row r = 0..4 (rows j-2..j+2).
+template <typename T, int G, typename D, typename Acc>
+GKS_HD bool gp_inputs(const Acc& rv, D ht, bool weno, D gamma, D K, PointIn<T>& in)
 {
-    // row r (0..4) of quantity q, component k: R[(q*4+k)*AB + a0 + r*bstride]
-    auto rv = [&](int q, int k, int r) { return R[(size_t)(q * 4 + k) * AB + a0 + (size_t)r * bstride]; };
-    PointIn<T> in;
-    const double iht = 1.0 / ht;
+    const D iht = D(1) / ht;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double v0 = 0, v1 = 0, v2 = 0, v5 = 0, v6 = 0, d0 = 0, d1 = 0, d3 = 0, d4 = 0, dd0 = 0;
-        const double base = rv(0, k, 2);
+        D v0 = D(0), v1 = D(0), v2 = D(0), v5 = D(0), v6 = D(0), d0 = D(0), d1 = D(0), d3 = D(0), d4 = D(0),
+          dd0 = D(0);
+        const D base = rv(0, k, 2);
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
-            const double c0 = kTanLin[G][0][r], c1 = kTanLin[G][1][r], c2 = kTanLin[G][2][r];
-            const double q0 = rv(0, k, r) - base;
+            const D c0 = D(kTanLin[G][0][r]), c1 = D(kTanLin[G][1][r]), c2 = D(kTanLin[G][2][r]);
+            const D q0 = rv(0, k, r) - base;
             v0 += c0 * q0;
             d0 += c1 * q0;
             dd0 += c2 * q0;
-            const double q1 = rv(1, k, r);
+            const D q1 = rv(1, k, r);
             v1 += c0 * q1;
             d1 += c1 * q1;
             v2 += c0 * rv(2, k, r);
@@ -466,11 +464,11 @@ __device__ __forceinline__ bool gauss_point(const double* __restrict__ R, size_t
         if (!weno) {
             in.Wl[k] = in.Wr[k] = in.W0[k];
         } else {
-            double ql[5], qr[5];
+            D ql[5], qr[5];
 #pragma unroll
             for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
-            in.Wl[k] = T(base + tan_weno<double, G>(ql));
-            in.Wr[k] = T(base + tan_weno<double, G>(qr));
+            in.Wl[k] = T(base + tan_weno<D, G>(ql));
+            in.Wr[k] = T(base + tan_weno<D, G>(qr));
         }
     }
     if (weno) {
@@ -480,8 +478,18 @@ __device__ __forceinline__ bool gauss_point(const double* __restrict__ R, size_t
         if (!physical<T>(in.Wr, T(gamma), 2))
 #pragma unroll
             for (int k = 0; k < 4; ++k) in.Wr[k] = T(rv(4, k, 2));
-        if (!kinetic_average<T, 2>(in.Wl, in.Wr, T(gamma), T(par.K), in.W0)) return false;
+        if (!kinetic_average<T, 2>(in.Wl, in.Wr, T(gamma), T(K), in.W0)) return false;
     }
+    return true;
+}
+
+template <typename T, int G>
+__device__ __forceinline__ bool gauss_point(const double* __restrict__ R, size_t AB, size_t a0, size_t bstride,
+                                            double ht, bool weno, const PointPar& par, double gamma, PointOut<T>& out)
+{
+    auto rv = [&](int q, int k, int r) { return R[(size_t)(q * 4 + k) * AB + a0 + (size_t)r * bstride]; };
+    PointIn<T> in;
+    if (!gp_inputs<T, G, double>(rv, ht, weno, gamma, par.K, in)) return false;
     return gks_point<T, 2>(par, in, out);
 }
 

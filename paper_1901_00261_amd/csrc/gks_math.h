@@ -187,7 +187,7 @@ GKS_HD bool char_frame(const T* W, T gamma, T R[4][4], T L[4][4])
 // matching the five row averages; kTanCand / kTanLinW: the three quadratic
 // candidates of the 5th-order WENO-Z and their linear weights at the point.
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr double kTanLin[3][3][5] = {
+__device__ constexpr double kTanLin[3][3][5] = {
     {{-0.039252347340234653, 0.31298719532417346, 0.91083333333333338, -0.21632052865750681, 0.031752347340234653},
      {0.10539650012874084, -1.1755510018023716, 1.0069756700139283, 0.091115664864294968, -0.027936833204592497},
      {0.14364916731037083, 0.81270166537925825, -2.2999999999999998, 1.5872983346207417, -0.24364916731037084}},
@@ -198,7 +198,7 @@ __host__ __device__ constexpr double kTanLin[3][3][5] = {
      {0.027936833204592497, -0.091115664864294968, -1.0069756700139283, 1.1755510018023716, -0.10539650012874084},
      {-0.24364916731037084, 1.5872983346207417, -2.2999999999999998, 0.81270166537925825, 0.14364916731037083}}};
 
-__host__ __device__ constexpr double kTanCand[3][3][3] = {
+__device__ constexpr double kTanCand[3][3][3] = {
     // [gauss point][candidate][3 rows of that candidate]
     {{-0.16031583397703753, 0.70793000257481675, 0.45238583140222077},
      {0.22698250064370418, 0.93333333333333335, -0.16031583397703753},
@@ -210,7 +210,7 @@ __host__ __device__ constexpr double kTanCand[3][3][3] = {
      {-0.16031583397703753, 0.93333333333333335, 0.22698250064370418},
      {0.45238583140222077, 0.70793000257481675, -0.16031583397703753}}};
 
-__host__ __device__ constexpr double kTanLinW[3][3] = {
+__device__ constexpr double kTanLinW[3][3] = {
     {0.24484385831693256, 0.61526717557251909, 0.13988896611054835},
     {-0.1125, 1.2250000000000001, -0.1125},
     {0.13988896611054835, 0.61526717557251909, 0.24484385831693256}};
@@ -378,6 +378,18 @@ GKS_HD void lin(const M& m, const T* a, T* out)
     lin_impl<A, B, DIM>(m, a, out, typename Slots<DIM>::seq{});
 }
 
+// out_K = <u^A v^B psi_K>
+template <int A, int B, int DIM, typename M, typename T, int... K>
+GKS_HD void psi_impl(const M& m, T* out, std::integer_sequence<int, K...>)
+{
+    ((out[K] = s_elem<A, B, K, 0>(m)), ...);
+}
+template <int A, int B, int DIM, typename M, typename T>
+GKS_HD void psi_mom(const M& m, T* out)
+{
+    psi_impl<A, B, DIM>(m, out, typename Slots<DIM>::seq{});
+}
+
 // out_K = sum_{P,Q} a_P b_Q <u^A v^B psi_P psi_Q psi_K>
 template <int A, int B, int K, int P, typename M, typename T, int... Q>
 GKS_HD T bil_inner(const M& m, const T* b, std::integer_sequence<int, Q...>)
@@ -451,19 +463,20 @@ template <typename T> GKS_HD bool physical(const T* W, T gamma, int dim)
 // integrals over [0, dt/2] and [0, dt] are matched by a + b t), FP64.
 // ke, kte: value coefficients of the e and t*e parts; kde, kdte: slopes.
 // ---------------------------------------------------------------------------
-GKS_HD void exp_fit(double tau_n, double dt, double& ke, double& kte, double& kde, double& kdte)
+template <typename D>
+GKS_HD void exp_fit(D tau_n, D dt, D& ke, D& kte, D& kde, D& kdte)
 {
-    const double x1 = 0.5 * dt / tau_n, x2 = dt / tau_n;
-    const double q1 = exp(-x1), q2 = exp(-x2);
-    const double om1 = -expm1(-x1), om2 = -expm1(-x2); // 1 - e^{-x}
-    const double Ie1 = tau_n * om1, Ie2 = tau_n * om2;
-    const double It1 = tau_n * tau_n * om1 - tau_n * (0.5 * dt) * q1;
-    const double It2 = tau_n * tau_n * om2 - tau_n * dt * q2;
-    const double idt = 1.0 / dt;
-    ke = (4.0 * Ie1 - Ie2) * idt;
-    kde = 4.0 * (Ie2 - 2.0 * Ie1) * idt * idt;
-    kte = (4.0 * It1 - It2) * idt;
-    kdte = 4.0 * (It2 - 2.0 * It1) * idt * idt;
+    const D x1 = D(0.5) * dt / tau_n, x2 = dt / tau_n;
+    const D q1 = exp(-x1), q2 = exp(-x2);
+    const D om1 = -expm1(-x1), om2 = -expm1(-x2); // 1 - e^{-x}
+    const D Ie1 = tau_n * om1, Ie2 = tau_n * om2;
+    const D It1 = tau_n * tau_n * om1 - tau_n * (D(0.5) * dt) * q1;
+    const D It2 = tau_n * tau_n * om2 - tau_n * dt * q2;
+    const D idt = D(1) / dt;
+    ke = (D(4) * Ie1 - Ie2) * idt;
+    kde = D(4) * (Ie2 - D(2) * Ie1) * idt * idt;
+    kte = (D(4) * It1 - It2) * idt;
+    kdte = D(4) * (It2 - D(2) * It1) * idt * idt;
 }
 
 // ---------------------------------------------------------------------------
@@ -488,8 +501,9 @@ struct PointPar {
     double gamma, K, mu, dt;
 };
 
-// returns false for a non-physical state
-template <typename T, int DIM>
+// returns false for a non-physical state.  D: type of the FP64 time
+// coefficients (double; a counting type when operations are tallied).
+template <typename T, int DIM, typename D = double>
 GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, PointOut<T>& out)
 {
     const T gamma = T(par.gamma), K = T(par.K);
@@ -500,11 +514,12 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, PointOut<T>& ou
 
     // collision times (Sec. 4): physical tau in the Navier-Stokes terms,
     // numerical tau_n (with the pressure-jump term) in the exponentials
-    const double jump = fabs((double(pl) - double(pr)) / (double(pl) + double(pr))) * par.dt;
-    const double tau_d = par.mu > 0.0 ? par.mu / double(p0) : 0.0;
-    const double tau_n = par.mu > 0.0 ? par.mu / double(p0) + jump : 0.01 * par.dt + jump;
-    double ke, kte, kde, kdte;
-    exp_fit(tau_n, par.dt, ke, kte, kde, kdte);
+    const D dtd = D(par.dt);
+    const D jump = tabs((D(pl) - D(pr)) / (D(pl) + D(pr))) * dtd;
+    const D tau_d = par.mu > 0.0 ? D(par.mu) / D(p0) : D(0);
+    const D tau_n = par.mu > 0.0 ? tau_d + jump : D(0.01) * dtd + jump;
+    D ke, kte, kde, kdte;
+    exp_fit<D>(tau_n, dtd, ke, kte, kde, kdte);
     const T tau = T(tau_d);
 
     // ---- equilibrium part, g0 (moments to degree 8) ----
@@ -683,10 +698,9 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, PointOut<T>& ou
             for (int k = 0; k < 4; ++k) b[k] = Wt[k] * irs;
             micro_solve<T, DIM>(Us, Vs, ls, K, b, as2);
         }
-        const T one[4] = {T(1), T(0), T(0), T(0)};
-        T h0[4], h1[4], h2[4], h3[4];
-        lin<0, 0, DIM>(mh, one, h0); // <psi>_half
-        lin<1, 0, DIM>(mh, one, h1); // <u psi>_half
+        T h0[4] = {T(0), T(0), T(0), T(0)}, h1[4] = {T(0), T(0), T(0), T(0)}, h2[4], h3[4];
+        psi_mom<0, 0, DIM>(mh, h0); // <psi>_half
+        psi_mom<1, 0, DIM>(mh, h1); // <u psi>_half
         lin<1, 0, DIM>(mh, as1, h2); // <a1 u psi>_half
         lin<2, 0, DIM>(mh, as1, h3); // <a1 u^2 psi>_half
         if constexpr (DIM == 2) {
@@ -726,10 +740,9 @@ GKS_HD bool kinetic_average(const T* Wl, const T* Wr, T gamma, T K, T* W0)
     Moments<T, DIM, 3> ml, mr;
     make_moments<T, DIM, 3>(Ul, Vl, ll, K, +1, ml);
     make_moments<T, DIM, 3>(Ur, Vr, lr, K, -1, mr);
-    const T one[4] = {T(1), T(0), T(0), T(0)};
-    T hl[4], hr[4];
-    lin<0, 0, DIM>(ml, one, hl);
-    lin<0, 0, DIM>(mr, one, hr);
+    T hl[4] = {T(0), T(0), T(0), T(0)}, hr[4] = {T(0), T(0), T(0), T(0)};
+    psi_mom<0, 0, DIM>(ml, hl);
+    psi_mom<0, 0, DIM>(mr, hr);
 #pragma unroll
     for (int k = 0; k < 4; ++k) W0[k] = rl * hl[k] + rr * hr[k];
     if constexpr (DIM == 1) W0[2] = T(0);

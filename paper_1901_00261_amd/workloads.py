@@ -133,10 +133,10 @@ def batch_1d(count=256, seed=4, nmin=200, nmax=4000, t_end=0.14):
 
 
 # ---------------------------------------------------------------- 2-D
-def _cell_quadrature_2d(fn, nx, ny, xlo, xhi, ylo, yhi):
-    """Exact-to-quadrature cell averages of fn(x, y) -> [..., nv] and the
-    cell-averaged x/y derivatives through face line averages (8-point
-    Gauss-Legendre per cell and per face)."""
+def _cell_quadrature_2d(fn, nx, ny, xlo, xhi, ylo, yhi, chunk=128):
+    """Cell averages of fn(X, Y) -> [..., nv] and the cell-averaged x/y
+    derivatives through face line averages (8-point Gauss-Legendre per cell
+    and per face).  fn receives broadcastable coordinate arrays."""
     dx = (xhi - xlo) / nx
     dy = (yhi - ylo) / ny
     xc = xlo + dx * (np.arange(nx) + 0.5)
@@ -144,23 +144,23 @@ def _cell_quadrature_2d(fn, nx, ny, xlo, xhi, ylo, yhi):
     gx = 0.5 * dx * _GL_X
     gy = 0.5 * dy * _GL_X
     w = 0.5 * _GL_W
-    # cell averages
-    X = xc[None, :, None, None] + gx[None, None, None, :]
-    Y = yc[:, None, None, None] + gy[None, None, :, None]
-    X, Y = np.broadcast_arrays(X, Y)
-    vals = fn(X, Y)  # [ny, nx, 8, 8, nv]
-    avg = np.einsum("abijv,i,j->abv", vals, w, w)
-    # x-face line averages at x = xlo + dx*i, i = 0..nx
     xf = xlo + dx * np.arange(nx + 1)
-    Xf = xf[None, :, None] + 0 * gy[None, None, :]
-    Yf = yc[:, None, None] + gy[None, None, :]
-    Xf, Yf = np.broadcast_arrays(Xf, Yf)
-    lx = np.einsum("abiv,i->abv", fn(Xf, Yf), w)  # [ny, nx+1, nv]
     yf = ylo + dy * np.arange(ny + 1)
-    Yg = yf[:, None, None] + 0 * gx[None, None, :]
-    Xg = xc[None, :, None] + gx[None, None, :]
-    Xg, Yg = np.broadcast_arrays(Xg, Yg)
-    ly = np.einsum("abiv,i->abv", fn(Xg, Yg), w)  # [ny+1, nx, nv]
+    avg = np.empty((ny, nx, 0))
+    parts_a, parts_l = [], []
+    for j0 in range(0, ny, chunk):
+        j1 = min(ny, j0 + chunk)
+        X = (xc[:, None] + gx[None, :])[None, :, None, :]          # [1, nx, 1, 8]
+        Y = (yc[j0:j1, None] + gy[None, :])[:, None, :, None]       # [nj, 1, 8, 1]
+        parts_a.append(np.einsum("abijv,i,j->abv", fn(X, Y), w, w))
+        Xf = xf[None, :, None]                                       # [1, nx+1, 1]
+        Yf = (yc[j0:j1, None] + gy[None, :])[:, None, :]             # [nj, 1, 8]
+        parts_l.append(np.einsum("abiv,i->abv", fn(Xf, Yf), w))
+    avg = np.concatenate(parts_a, axis=0)
+    lx = np.concatenate(parts_l, axis=0)                             # [ny, nx+1, nv]
+    Xg = (xc[:, None] + gx[None, :])[None, :, :]                     # [1, nx, 8]
+    Yg = yf[:, None, None]                                           # [ny+1, 1, 1]
+    ly = np.einsum("abiv,i->abv", fn(Xg, Yg), w)                     # [ny+1, nx, nv]
     Wx = (lx[:, 1:] - lx[:, :-1]) / dx
     Wy = (ly[1:] - ly[:-1]) / dy
     return avg, Wx, Wy
@@ -180,27 +180,33 @@ def isentropic_vortex_2d(n, *, ny=None, L=10.0, eps=5.0, mu=1e-4, gamma=1.4, ord
     xc0 = yc0 = 0.5 * L
 
     def fn(X, Y):
-        du = np.zeros_like(X)
-        dv = np.zeros_like(X)
-        dT = np.zeros_like(X)
+        X, Y = np.asarray(X, dtype=np.float64), np.asarray(Y, dtype=np.float64)
+        shape = np.broadcast_shapes(X.shape, Y.shape)
+        # exp((1 - r^2)/2) = e^{1/2} e^{-x'^2/2} e^{-y'^2/2}: the sums over the
+        # periodic images factorise into 1-D sums
         shifts = (-L, 0.0, L) if periodic_images else (0.0,)
-        for sx in shifts:
-            for sy in shifts:
-                xr = X - xc0 - sx
-                yr = Y - yc0 - sy
-                r2 = xr * xr + yr * yr
-                e = np.exp(0.5 * (1.0 - r2))
-                du += -eps / (2 * math.pi) * e * yr
-                dv += eps / (2 * math.pi) * e * xr
-                dT += -(gamma - 1.0) * eps * eps * e * e / (8 * gamma * math.pi ** 2)
+        sx0 = sx1 = sx2 = 0.0
+        sy0 = sy1 = sy2 = 0.0
+        for sh in shifts:
+            xr = X - xc0 - sh
+            yr = Y - yc0 - sh
+            ex = np.exp(-0.5 * xr * xr)
+            ey = np.exp(-0.5 * yr * yr)
+            sx0, sx1, sx2 = sx0 + ex, sx1 + ex * xr, sx2 + ex * ex
+            sy0, sy1, sy2 = sy0 + ey, sy1 + ey * yr, sy2 + ey * ey
+        c = math.exp(0.5)
+        du = -eps / (2 * math.pi) * c * sx0 * sy1
+        dv = eps / (2 * math.pi) * c * sx1 * sy0
+        dT = -(gamma - 1.0) * eps * eps * math.e / (8 * gamma * math.pi ** 2) * sx2 * sy2
         T = 1.0 + dT
         rho = T ** (1.0 / (gamma - 1.0))
         p = rho * T
-        pp = np.zeros_like(X)
+        pp = np.zeros(shape)
         if acoustic_amp:
-            ang_x = 2 * math.pi * X[..., None] * kk / L + phi
-            ang_y = 2 * math.pi * Y[..., None] * kk / L + chi
-            pp = acoustic_amp / 64.0 * (np.cos(ang_x) + np.cos(ang_y)).sum(-1)
+            # separable: evaluated on the coordinate arrays, then broadcast
+            fx = np.cos(2 * math.pi * X[..., None] * kk / L + phi).sum(-1)
+            fy = np.cos(2 * math.pi * Y[..., None] * kk / L + chi).sum(-1)
+            pp = pp + acoustic_amp / 64.0 * (fx + fy)
         rho = rho + pp / gamma
         p = p + pp
         return prim_to_cons(rho, 1.0 + du, p, gamma, V=1.0 + dv)
