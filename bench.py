@@ -32,7 +32,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1024, help="cells per direction")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=192, help="oracle sample: window edge in cells, one step")
+    ap.add_argument("--cpu-window", type=int, default=400, help="oracle sample: window edge in cells, one step")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run one device-to-device copy of this many MiB (calibrates FETCH_SIZE/WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -66,6 +68,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8}))
+        return
 
     from paper_1901_00261_amd import gks
     from paper_1901_00261_amd import workloads as wl

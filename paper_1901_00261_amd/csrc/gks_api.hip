@@ -112,6 +112,9 @@ int validate(const gks_problem* pr, int32_t nprob, int32_t precision)
         if (q.dim != dim) return bad("all problems of a handle must have the same dim");
         if (q.nx < 4 || (dim == 2 && q.ny < 4) || (dim == 1 && q.ny != 1 && q.ny != 0)) return bad("bad nx/ny");
         if ((long long)q.nx * (dim == 2 ? q.ny : 1) > (1ll << 31) - 1) return bad("too many cells");
+        // 2-D face-row buffers are read through 32-bit byte offsets
+        if (dim == 2 && 28ll * (q.ny + 4) * (q.nx + 4) * 8 > 0xffffffffll)
+            return bad("2-D grid too large for one handle (at most about 4370 x 4370 cells)");
         if (!(q.xhi > q.xlo) || (dim == 2 && !(q.yhi > q.ylo))) return bad("empty domain");
         if (!(q.gamma > 1.0) || !std::isfinite(q.gamma)) return bad("gamma must be > 1");
         if (!(q.mu >= 0.0) || !std::isfinite(q.mu)) return bad("mu must be >= 0");
@@ -189,22 +192,32 @@ template <typename T> void launch_step_2d(gks_handle* h)
     const ProbParam& P = h->hp[0];
     const int nx = P.nx, ny = P.ny;
     const dim3 br(64, 4), bg(64, 2), bc(64, 4);
+    // 1-D grids of 2-D tiles; the kernels map workgroups to tiles per XCD.
     // x faces: rows (ny + 4) x faces (nx + 1); y faces: faces (ny + 1) x columns (nx + 4)
-    const dim3 grx((nx + 1 + 63) / 64, (ny + 4 + 3) / 4), gry((nx + 4 + 63) / 64, (ny + 1 + 3) / 4);
-    const dim3 ggx((nx + 1 + 63) / 64, (ny + 1) / 2), ggy((nx + 63) / 64, (ny + 1 + 1) / 2);
-    const dim3 gc((nx + 63) / 64, (ny + 3) / 4);
+    auto tiles = [](int ext_x, int ext_y, dim3 b) { return ((ext_x + b.x - 1) / b.x) * ((ext_y + b.y - 1) / b.y); };
+    const int grx = tiles(nx + 1, ny + 4, br), gry = tiles(nx + 4, ny + 1, br);
+    const int ggx = tiles(nx + 1, ny, bg), ggy = tiles(nx, ny + 1, bg);
+    const int gc = tiles(nx, ny, bc);
     for (int stage = 1; stage <= 2; ++stage) {
         record(h, 1, true);
         gks::row2d_kernel<T, 0><<<grx, br, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
         record(h, 1, false);
         record(h, 0, true);
-        gks::gp2d_kernel<T, 0><<<ggx, bg, 0, h->stream>>>(h->dP, h->dS, h->Rx, stage, h->FL, h->FdL, h->Wfs, h->Pf);
+        if (stage == 1)
+            gks::gp2d_kernel<T, 0, 1><<<ggx, bg, 0, h->stream>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
+        else
+            gks::gp2d_kernel<T, 0, 2><<<ggx, bg, 0, h->stream>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
         record(h, 0, false);
         record(h, 1, true);
         gks::row2d_kernel<T, 1><<<gry, br, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
         record(h, 1, false);
         record(h, 0, true);
-        gks::gp2d_kernel<T, 1><<<ggy, bg, 0, h->stream>>>(h->dP, h->dS, h->Ry, stage, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
+        if (stage == 1)
+            gks::gp2d_kernel<T, 1, 1><<<ggy, bg, 0, h->stream>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy,
+                                                                 h->Pfy);
+        else
+            gks::gp2d_kernel<T, 1, 2><<<ggy, bg, 0, h->stream>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy,
+                                                                 h->Pfy);
         record(h, 0, false);
         record(h, 2, true);
         if (stage == 1)

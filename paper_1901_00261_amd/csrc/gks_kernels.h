@@ -80,6 +80,24 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* d
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (bid % 8), each with
+// its own L2.  Give every XCD a contiguous range of tiles (a band of tile
+// rows) so that the stencil neighbours of a tile are cached in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb)
+{
+    const int x = bid & 7, l = bid >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + l;
+}
+
+// 2-D tile coordinates of this workgroup (grid launched 1-D, gx tiles per row)
+__device__ __forceinline__ void tile_xy(int gx, int& tx, int& ty)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    ty = t / gx;
+    tx = t - ty * gx;
+}
+
 // ---------------------------------------------------------------------------
 // Reconstruction at one face from a 4-cell stencil (local frame, slot 1 =
 // normal velocity).  Wk/Dk: cell averages and cell-width * normal slopes of
@@ -211,21 +229,22 @@ __global__ void __launch_bounds__(kBlock1D) face1d_kernel(const ProbParam* __res
     bool ok = (P.order == 8) ? face_recon<T, 1, 8>(Wk, Dk, P.dx, P.gamma, P.recon != 0, o)
                              : face_recon<T, 1, 6>(Wk, Dk, P.dx, P.gamma, P.recon != 0, o);
     PointIn<T> in;
-    PointOut<T> out;
+    PointOut<double> out;
+    NonEq<double, 1, T> ne;
     if (ok) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            in.W0[k] = T(o[0][k]); in.W0x[k] = T(o[1][k]); in.W0xx[k] = T(o[2][k]);
+            in.W0x[k] = T(o[1][k]); in.W0xx[k] = T(o[2][k]);
             in.W0y[k] = in.W0xy[k] = in.W0yy[k] = T(0);
-            in.Wl[k] = T(o[3][k]); in.Wr[k] = T(o[4][k]);
             in.Wlx[k] = T(o[5][k]); in.Wrx[k] = T(o[6][k]);
             in.Wly[k] = in.Wry[k] = T(0);
         }
-        if (P.recon) ok = kinetic_average<T, 1>(in.Wl, in.Wr, T(P.gamma), T(P.K), in.W0);
+        ok = noneq_states<double, 1, T>(o[3], o[4], P.gamma, P.K, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
     }
     if (ok) {
         const PointPar par{P.gamma, P.K, P.mu, dt};
-        ok = gks_point<T, 1>(par, in, out);
+        // equilibrium value: kinetic average of the WENO-Z states, or the linear value
+        ok = gks_point<T, 1>(par, in, P.recon ? ne.Xs : o[0], ne, out);
     }
     if (!ok) {
         S.err = 1;
@@ -237,14 +256,14 @@ __global__ void __launch_bounds__(kBlock1D) face1d_kernel(const ProbParam* __res
     for (int k = 0; k < 3; ++k) {
         const int s = slot[k];
         if (STAGE == 1) {
-            FL[k * F + g] = double(out.FL[s]);
-            FdL[k * F + g] = double(out.FdL[s]);
-            const double s0 = double(out.S0[s]), s1 = double(out.S1[s]), s2 = double(out.S2[s]);
+            FL[k * F + g] = out.FL[s];
+            FdL[k * F + g] = out.FdL[s];
+            const double s0 = out.S0[s], s1 = out.S1[s], s2 = out.S2[s];
             Wfs[k * F + g] = s0 + 0.5 * dt * s1 + 0.125 * dt * dt * s2;
             Pf[k * F + g] = s0 + dt * s1 + dt * dt / 6.0 * s2;
         } else {
-            FdL[k * F + g] = double(out.FdL[s]);
-            Wfs[k * F + g] = Pf[k * F + g] + dt * dt / 3.0 * double(out.S2[s]);
+            FdL[k * F + g] = out.FdL[s];
+            Wfs[k * F + g] = Pf[k * F + g] + dt * dt / 3.0 * out.S2[s];
         }
     }
 }
@@ -375,9 +394,11 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
     const int nx = P.nx, ny = P.ny;
     const int nf = DIR == 0 ? nx + 1 : ny + 1;
     const int nt = DIR == 0 ? ny : nx;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const int a = blockIdx.y * blockDim.y + threadIdx.y;
     const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
+    int tx, ty;
+    tile_xy((B + blockDim.x - 1) / blockDim.x, tx, ty);
+    const int b = tx * blockDim.x + threadIdx.x;
+    const int a = ty * blockDim.y + threadIdx.y;
     if (a >= A || b >= B) return;
     const int face = DIR == 0 ? b : a;
     const int tr = (DIR == 0 ? a : b) - 2; // transverse index, -2 .. nt+1
@@ -420,14 +441,14 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
         for (int k = 0; k < 4; ++k) R[(q * 4 + k) * AB + ab] = o[q][k];
 }
 
-// Gauss-point inputs at point G (0..2) of the 3-point rule: tangential
+// Gauss-point inputs at point g (0..2) of the 3-point rule: tangential
 // linear 5th-order reconstruction of the equilibrium rows and of the
 // derivatives of the non-equilibrium rows, tangential WENO-Z of the
 // non-equilibrium values (with the positivity fallback to the face-row line
-// value) and the equilibrium value as their kinetic average.  rv(q, k, r):
-// quantity q (face_recon order), component k, row r = 0..4 (rows j-2..j+2).
-template <typename T, int G, typename D, typename Acc>
-GKS_HD bool gp_inputs(const Acc& rv, D ht, bool weno, D gamma, D K, PointIn<T>& in)
+// value).  rv(q, k, r): quantity q (face_recon order), component k, row
+// r = 0..4 (rows j-2..j+2).  Values in type D: W0 (linear), Wl, Wr.
+template <typename T, typename D, typename Acc>
+GKS_HD void gp_inputs(const Acc& rv, int g, D ht, bool weno, D gamma, PointIn<T>& in, D* W0, D* Wl, D* Wr)
 {
     const D iht = D(1) / ht;
 #pragma unroll
@@ -437,7 +458,7 @@ GKS_HD bool gp_inputs(const Acc& rv, D ht, bool weno, D gamma, D K, PointIn<T>& 
         const D base = rv(0, k, 2);
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
-            const D c0 = D(kTanLin[G][0][r]), c1 = D(kTanLin[G][1][r]), c2 = D(kTanLin[G][2][r]);
+            const D c0 = D(kTanLin[g][0][r]), c1 = D(kTanLin[g][1][r]), c2 = D(kTanLin[g][2][r]);
             const D q0 = rv(0, k, r) - base;
             v0 += c0 * q0;
             d0 += c1 * q0;
@@ -451,7 +472,7 @@ GKS_HD bool gp_inputs(const Acc& rv, D ht, bool weno, D gamma, D K, PointIn<T>& 
             d3 += c1 * (rv(3, k, r) - base);
             d4 += c1 * (rv(4, k, r) - base);
         }
-        in.W0[k] = T(base + v0);
+        W0[k] = base + v0;
         in.W0x[k] = T(v1);
         in.W0xx[k] = T(v2);
         in.W0y[k] = T(d0 * iht);
@@ -462,40 +483,53 @@ GKS_HD bool gp_inputs(const Acc& rv, D ht, bool weno, D gamma, D K, PointIn<T>& 
         in.Wly[k] = T(d3 * iht);
         in.Wry[k] = T(d4 * iht);
         if (!weno) {
-            in.Wl[k] = in.Wr[k] = in.W0[k];
+            Wl[k] = Wr[k] = W0[k];
         } else {
             D ql[5], qr[5];
 #pragma unroll
             for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
-            in.Wl[k] = T(base + tan_weno<D, G>(ql));
-            in.Wr[k] = T(base + tan_weno<D, G>(qr));
+            Wl[k] = base + tan_weno<D>(ql, g);
+            Wr[k] = base + tan_weno<D>(qr, g);
         }
     }
     if (weno) {
-        if (!physical<T>(in.Wl, T(gamma), 2))
+        if (!physical<D>(Wl, gamma, 2))
 #pragma unroll
-            for (int k = 0; k < 4; ++k) in.Wl[k] = T(rv(3, k, 2));
-        if (!physical<T>(in.Wr, T(gamma), 2))
+            for (int k = 0; k < 4; ++k) Wl[k] = rv(3, k, 2);
+        if (!physical<D>(Wr, gamma, 2))
 #pragma unroll
-            for (int k = 0; k < 4; ++k) in.Wr[k] = T(rv(4, k, 2));
-        if (!kinetic_average<T, 2>(in.Wl, in.Wr, T(gamma), T(K), in.W0)) return false;
+            for (int k = 0; k < 4; ++k) Wr[k] = rv(4, k, 2);
     }
-    return true;
 }
 
-template <typename T, int G>
-__device__ __forceinline__ bool gauss_point(const double* __restrict__ R, size_t AB, size_t a0, size_t bstride,
-                                            double ht, bool weno, const PointPar& par, double gamma, PointOut<T>& out)
+// Row-buffer reads through a buffer resource: 32-bit per-lane offsets for
+// the five stencil rows, the quantity plane as a scalar offset.
+struct RowReader {
+    __amdgpu_buffer_rsrc_t rsrc;
+    unsigned voff[5];  // byte offset of row r (lane dependent)
+    unsigned plane;    // bytes between quantity planes
+    __device__ __forceinline__ double operator()(int q, int k, int r) const
+    {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff[r], (unsigned)(q * 4 + k) * plane, 0);
+        return __builtin_bit_cast(double, v);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ bool gauss_point(const RowReader& rv, int g, double ht, bool weno, const PointPar& par,
+                                            PointOut<double>& out)
 {
-    auto rv = [&](int q, int k, int r) { return R[(size_t)(q * 4 + k) * AB + a0 + (size_t)r * bstride]; };
     PointIn<T> in;
-    if (!gp_inputs<T, G, double>(rv, ht, weno, gamma, par.K, in)) return false;
-    return gks_point<T, 2>(par, in, out);
+    double W0[4], Wl[4], Wr[4];
+    gp_inputs<T, double>(rv, g, ht, weno, par.gamma, in, W0, Wl, Wr);
+    NonEq<double, 2, T> ne;
+    if (!noneq_states<double, 2, T>(Wl, Wr, par.gamma, par.K, ne, in.Wlx, in.Wly, in.Wrx, in.Wry)) return false;
+    return gks_point<T, 2>(par, in, weno ? ne.Xs : W0, ne, out);
 }
 
-template <typename T, int DIR>
+template <typename T, int DIR, int STAGE>
 __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
-                                                   const double* __restrict__ R, int stage, double* __restrict__ FL,
+                                                   const double* __restrict__ R, double* __restrict__ FL,
                                                    double* __restrict__ FdL, double* __restrict__ Wfs,
                                                    double* __restrict__ Pf)
 {
@@ -506,14 +540,24 @@ __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__
     const int nf = DIR == 0 ? nx + 1 : ny + 1;
     const int nt = DIR == 0 ? ny : nx;
     const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x; // DIR 0: face, DIR 1: transverse cell
-    const int a = blockIdx.y * blockDim.y + threadIdx.y; // DIR 0: transverse cell, DIR 1: face
+    const int bw = DIR == 0 ? nf : nt; // extent of the thread-x index
+    int tx, ty;
+    tile_xy((bw + blockDim.x - 1) / blockDim.x, tx, ty);
+    const int b = tx * blockDim.x + threadIdx.x; // DIR 0: face, DIR 1: transverse cell
+    const int a = ty * blockDim.y + threadIdx.y; // DIR 0: transverse cell, DIR 1: face
     const int face = DIR == 0 ? b : a, tc = DIR == 0 ? a : b;
     if (face >= nf || tc >= nt) return;
     const size_t AB = (size_t)A * B;
     // row r of the stencil = transverse index tc - 2 + r, stored at (tc + r)
-    const size_t a0 = DIR == 0 ? (size_t)tc * B + face : (size_t)face * B + tc;
-    const size_t bstride = DIR == 0 ? (size_t)B : 1;
+    const unsigned a0 = DIR == 0 ? (unsigned)tc * B + face : (unsigned)face * B + tc;
+    const unsigned bstride = DIR == 0 ? (unsigned)B : 1u;
+    RowReader rv;
+    // the host guarantees 28 * AB * 8 < 2^32 bytes
+    rv.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)R, (short)0, (int)(unsigned)(AB * 28 * sizeof(double)),
+                                                0x00020000);
+    rv.plane = (unsigned)(AB * sizeof(double));
+#pragma unroll
+    for (int r = 0; r < 5; ++r) rv.voff[r] = (a0 + r * bstride) * (unsigned)sizeof(double);
     const double ht = DIR == 0 ? P.dy : P.dx;
     const double dt = S.dt;
     const PointPar par{P.gamma, P.K, P.mu, dt};
@@ -523,39 +567,22 @@ __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__
     for (int q = 0; q < 5; ++q)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[q][k] = 0.0;
-    constexpr double wg[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
     bool ok = true;
-    {
-        PointOut<T> o;
-        ok = ok && gauss_point<T, 0>(R, AB, a0, bstride, ht, weno, par, P.gamma, o);
+#pragma unroll 1
+    for (int g = 0; g < 3; ++g) {
+        PointOut<double> o;
+        ok = ok && gauss_point<T>(rv, g, ht, weno, par, o);
+        const double wg = g == 1 ? 8.0 / 18.0 : 5.0 / 18.0;
         if (ok)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                acc[0][k] += wg[0] * double(o.FL[k]); acc[1][k] += wg[0] * double(o.FdL[k]);
-                acc[2][k] += wg[0] * double(o.S0[k]); acc[3][k] += wg[0] * double(o.S1[k]);
-                acc[4][k] += wg[0] * double(o.S2[k]);
-            }
-    }
-    {
-        PointOut<T> o;
-        ok = ok && gauss_point<T, 1>(R, AB, a0, bstride, ht, weno, par, P.gamma, o);
-        if (ok)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                acc[0][k] += wg[1] * double(o.FL[k]); acc[1][k] += wg[1] * double(o.FdL[k]);
-                acc[2][k] += wg[1] * double(o.S0[k]); acc[3][k] += wg[1] * double(o.S1[k]);
-                acc[4][k] += wg[1] * double(o.S2[k]);
-            }
-    }
-    {
-        PointOut<T> o;
-        ok = ok && gauss_point<T, 2>(R, AB, a0, bstride, ht, weno, par, P.gamma, o);
-        if (ok)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                acc[0][k] += wg[2] * double(o.FL[k]); acc[1][k] += wg[2] * double(o.FdL[k]);
-                acc[2][k] += wg[2] * double(o.S0[k]); acc[3][k] += wg[2] * double(o.S1[k]);
-                acc[4][k] += wg[2] * double(o.S2[k]);
+                if (STAGE == 1) {
+                    acc[0][k] += wg * o.FL[k];
+                    acc[2][k] += wg * o.S0[k];
+                    acc[3][k] += wg * o.S1[k];
+                }
+                acc[1][k] += wg * o.FdL[k];
+                acc[4][k] += wg * o.S2[k];
             }
     }
     if (!ok) {
@@ -569,7 +596,7 @@ __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const size_t o = (size_t)gk[k] * nfa + fi;
-        if (stage == 1) {
+        if (STAGE == 1) {
             FL[o] = acc[0][k];
             FdL[o] = acc[1][k];
             Wfs[o] = acc[2][k] + 0.5 * dt * acc[3][k] + 0.125 * dt * dt * acc[4][k];
@@ -594,8 +621,10 @@ __global__ void __launch_bounds__(256) cell2d_kernel(const ProbParam* __restrict
     ProbState& S = PS[0];
     if (!S.active) return;
     const int nx = P.nx, ny = P.ny;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    int tx, ty;
+    tile_xy((nx + blockDim.x - 1) / blockDim.x, tx, ty);
+    const int i = tx * blockDim.x + threadIdx.x;
+    const int j = ty * blockDim.y + threadIdx.y;
     const bool live = i < nx && j < ny;
     const int cur = S.cur, nxt = 1 - cur;
     const double dt = S.dt, idx = 1.0 / P.dx, idy = 1.0 / P.dy;

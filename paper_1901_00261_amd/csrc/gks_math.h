@@ -215,16 +215,16 @@ __device__ constexpr double kTanLinW[3][3] = {
     {-0.1125, 1.2250000000000001, -0.1125},
     {0.13988896611054835, 0.61526717557251909, 0.24484385831693256}};
 
-// 5th-order WENO-Z value at Gauss point G from rows q[0..4]; the centre
+// 5th-order WENO-Z value at Gauss point g from rows q[0..4]; the centre
 // point's negative linear weights are split into two positive groups
 // (Shi, Hu, Shu, J. Comput. Phys. 175 (2002), theta = 3).
-template <typename T, int G>
-GKS_HD T tan_weno(const T* q)
+template <typename T>
+GKS_HD T tan_weno(const T* q, int g)
 {
     T cand[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        cand[k] = T(kTanCand[G][k][0]) * q[k] + T(kTanCand[G][k][1]) * q[k + 1] + T(kTanCand[G][k][2]) * q[k + 2];
+        cand[k] = T(kTanCand[g][k][0]) * q[k] + T(kTanCand[g][k][1]) * q[k + 1] + T(kTanCand[g][k][2]) * q[k + 2];
     // Jiang-Shu indicators of the three quadratics over the centre row
     const T s0a = q[0] - T(2) * q[1] + q[2], s0b = q[0] - T(4) * q[1] + T(3) * q[2];
     const T s1a = q[1] - T(2) * q[2] + q[3], s1b = q[1] - q[3];
@@ -236,23 +236,22 @@ GKS_HD T tan_weno(const T* q)
     T r[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) r[k] = T(1) + Z / (be[k] + eps);
-    if constexpr (G != 1) {
-        T a[3], s = T(0), v = T(0);
+    if (g != 1) {
+        T a[3], sum = T(0), v = T(0);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { a[k] = T(kTanLinW[G][k]) * r[k]; s += a[k]; }
+        for (int k = 0; k < 3; ++k) { a[k] = T(kTanLinW[g][k]) * r[k]; sum += a[k]; }
 #pragma unroll
         for (int k = 0; k < 3; ++k) v += a[k] * cand[k];
-        return v / s;
-    } else {
-        // gamma+ = (g + 3|g|)/2, gamma- = gamma+ - g
-        constexpr double gp0 = 0.1125, gp1 = 2.45, gp2 = 0.1125, sp = 2.675;
-        constexpr double gm0 = 0.225, gm1 = 1.225, gm2 = 0.225, sm = 1.675;
-        const T ap0 = T(gp0 / sp) * r[0], ap1 = T(gp1 / sp) * r[1], ap2 = T(gp2 / sp) * r[2];
-        const T am0 = T(gm0 / sm) * r[0], am1 = T(gm1 / sm) * r[1], am2 = T(gm2 / sm) * r[2];
-        const T vp = (ap0 * cand[0] + ap1 * cand[1] + ap2 * cand[2]) / (ap0 + ap1 + ap2);
-        const T vm = (am0 * cand[0] + am1 * cand[1] + am2 * cand[2]) / (am0 + am1 + am2);
-        return T(sp) * vp - T(sm) * vm;
+        return v / sum;
     }
+    // gamma+ = (g + 3|g|)/2, gamma- = gamma+ - g
+    constexpr double gp0 = 0.1125, gp1 = 2.45, gp2 = 0.1125, sp = 2.675;
+    constexpr double gm0 = 0.225, gm1 = 1.225, gm2 = 0.225, sm = 1.675;
+    const T ap0 = T(gp0 / sp) * r[0], ap1 = T(gp1 / sp) * r[1], ap2 = T(gp2 / sp) * r[2];
+    const T am0 = T(gm0 / sm) * r[0], am1 = T(gm1 / sm) * r[1], am2 = T(gm2 / sm) * r[2];
+    const T vp = (ap0 * cand[0] + ap1 * cand[1] + ap2 * cand[2]) / (ap0 + ap1 + ap2);
+    const T vm = (am0 * cand[0] + am1 * cand[1] + am2 * cand[2]) / (am0 + am1 + am2);
+    return T(sp) * vp - T(sm) * vm;
 }
 
 // ---------------------------------------------------------------------------
@@ -480,272 +479,465 @@ GKS_HD void exp_fit(D tau_n, D dt, D& ke, D& kte, D& kde, D& kdte)
 }
 
 // ---------------------------------------------------------------------------
+// Central-velocity form of the equilibrium moments.  With c = u - U,
+// w = v - V and phi = (1, c, w, Q/2), Q = c^2 + w^2 + xi^2, the Maxwellian's
+// moments are closed forms in h = 1/(2 lambda) and N = K + D (isotropic
+// Gaussian with variance h per degree of freedom):
+//   <c^a w^b Q^k> = 0 for odd a or b, else
+//   h^{a/2+b/2+k} (a-1)!! (b-1)!! prod_{m<k} (N + a + b + 2m).
+// psi = M phi with M lower triangular (psi_1 = U + c, psi_2 = V + w,
+// psi_3 = E0 + U c + V w + phi_3, E0 = (U^2 + V^2)/2), so moment conditions
+// <(a.psi) psi> = b become G a^ = M^{-1} b with a^ = M^T a and the almost
+// diagonal Gram matrix G = <phi phi^T>.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Central {
+    T h[7]; // h^n
+    T N;
+    T U, V, E0;
+};
+
+constexpr double dfact(int n) { return n <= 0 ? 1.0 : double(n) * dfact(n - 2); }
+constexpr int kCc[4] = {0, 1, 0, 0};
+constexpr int kCw[4] = {0, 0, 1, 0};
+constexpr int kCq[4] = {0, 0, 0, 1};
+
+template <int A, int B> constexpr bool odd_cw() { return (A % 2) != 0 || (B % 2) != 0; }
+
+// <c^A w^B Q^Kq>, A and B even
+template <int A, int B, int Kq, typename T>
+GKS_HD T mc(const Central<T>& C)
+{
+    static_assert(!odd_cw<A, B>(), "odd central moments vanish");
+    constexpr int e = A / 2 + B / 2 + Kq;
+    constexpr double df = dfact(A - 1) * dfact(B - 1);
+    T v = T(df) * C.h[e];
+    if constexpr (Kq >= 1) v *= C.N + T(A + B);
+    if constexpr (Kq >= 2) v *= C.N + T(A + B + 2);
+    if constexpr (Kq >= 3) v *= C.N + T(A + B + 4);
+    return v;
+}
+
+// 2-tensor <c^Al w^Be phi_J phi_P> and 3-tensor <c^Al w^Be phi_J phi_P phi_R>
+template <int Al, int Be, int J, int P> constexpr bool z2() { return odd_cw<Al + kCc[J] + kCc[P], Be + kCw[J] + kCw[P]>(); }
+template <int Al, int Be, int J, int P, int R> constexpr bool z3()
+{
+    return odd_cw<Al + kCc[J] + kCc[P] + kCc[R], Be + kCw[J] + kCw[P] + kCw[R]>();
+}
+template <int Al, int Be, int J, int P, typename T>
+GKS_HD T c2(const Central<T>& C)
+{
+    constexpr int q = kCq[J] + kCq[P];
+    constexpr double sc = q == 0 ? 1.0 : (q == 1 ? 0.5 : 0.25);
+    return T(sc) * mc<Al + kCc[J] + kCc[P], Be + kCw[J] + kCw[P], q>(C);
+}
+template <int Al, int Be, int J, int P, int R, typename T>
+GKS_HD T c3(const Central<T>& C)
+{
+    constexpr int q = kCq[J] + kCq[P] + kCq[R];
+    constexpr double sc = q == 0 ? 1.0 : (q == 1 ? 0.5 : (q == 2 ? 0.25 : 0.125));
+    return T(sc) * mc<Al + kCc[J] + kCc[P] + kCc[R], Be + kCw[J] + kCw[P] + kCw[R], q>(C);
+}
+
+template <int Al, int Be, int J, int P, typename T>
+GKS_HD void c2_acc(const Central<T>& C, const T* a, T& acc)
+{
+    if constexpr (!z2<Al, Be, J, P>()) acc += a[P] * c2<Al, Be, J, P>(C);
+}
+template <int Al, int Be, int J, int P, int R, typename T>
+GKS_HD void c3_acc(const Central<T>& C, const T* a, const T* b, T& acc)
+{
+    if constexpr (!z3<Al, Be, J, P, R>()) acc += (a[P] * b[R]) * c3<Al, Be, J, P, R>(C);
+}
+template <int Al, int Be, int J, typename T, int... P>
+GKS_HD T c2_row(const Central<T>& C, const T* a, std::integer_sequence<int, P...>)
+{
+    T acc = T(0);
+    (c2_acc<Al, Be, J, P>(C, a, acc), ...);
+    return acc;
+}
+template <int Al, int Be, int J, int P, typename T, int... R>
+GKS_HD void c3_inner(const Central<T>& C, const T* a, const T* b, T& acc, std::integer_sequence<int, R...>)
+{
+    (c3_acc<Al, Be, J, P, R>(C, a, b, acc), ...);
+}
+template <int Al, int Be, int J, int DIM, typename T, int... P>
+GKS_HD T c3_row(const Central<T>& C, const T* a, const T* b, std::integer_sequence<int, P...>)
+{
+    T acc = T(0);
+    (c3_inner<Al, Be, J, P>(C, a, b, acc, typename Slots<DIM>::seq{}), ...);
+    return acc;
+}
+template <int Al, int Be, int DIM, typename T, int... J>
+GKS_HD void clin_impl(const Central<T>& C, const T* a, T* out, std::integer_sequence<int, J...>)
+{
+    ((out[J] = c2_row<Al, Be, J>(C, a, typename Slots<DIM>::seq{})), ...);
+}
+template <int Al, int Be, int DIM, typename T, int... J>
+GKS_HD void cbil_impl(const Central<T>& C, const T* a, const T* b, T* out, std::integer_sequence<int, J...>)
+{
+    ((out[J] = c3_row<Al, Be, J, DIM>(C, a, b, typename Slots<DIM>::seq{})), ...);
+}
+// out_J = <c^Al w^Be (a.phi) phi_J>
+template <int Al, int Be, int DIM, typename T>
+GKS_HD void clin(const Central<T>& C, const T* a, T* out)
+{
+    clin_impl<Al, Be, DIM>(C, a, out, typename Slots<DIM>::seq{});
+}
+// out_J = <c^Al w^Be (a.phi)(b.phi) phi_J>
+template <int Al, int Be, int DIM, typename T>
+GKS_HD void cbil(const Central<T>& C, const T* a, const T* b, T* out)
+{
+    cbil_impl<Al, Be, DIM>(C, a, b, out, typename Slots<DIM>::seq{});
+}
+
+// b^ = M^{-1} b (conservative-variable vector -> central dual basis)
+template <typename T, int DIM>
+GKS_HD void to_central(const Central<T>& C, const T* b, T s, T* o)
+{
+    o[0] = s * b[0];
+    o[1] = s * (b[1] - C.U * b[0]);
+    o[2] = DIM == 2 ? s * (b[2] - C.V * b[0]) : T(0);
+    o[3] = s * (b[3] - C.U * b[1] - (DIM == 2 ? C.V * b[2] : T(0)) + C.E0 * b[0]);
+}
+// b = M b^ (central dual -> conservative-variable vector), scaled by s
+template <typename T, int DIM>
+GKS_HD void from_central(const Central<T>& C, const T* o, T s, T* b)
+{
+    b[0] = s * o[0];
+    b[1] = s * (C.U * o[0] + o[1]);
+    b[2] = DIM == 2 ? s * (C.V * o[0] + o[2]) : T(0);
+    b[3] = s * (C.E0 * o[0] + C.U * o[1] + (DIM == 2 ? C.V * o[2] : T(0)) + o[3]);
+}
+// a^ = G^{-1} b^
+template <typename T, int DIM>
+GKS_HD void gsolve(const Central<T>& C, const T* b, T* a)
+{
+    const T ih = T(1) / C.h[1];
+    a[1] = b[1] * ih;
+    a[2] = DIM == 2 ? b[2] * ih : T(0);
+    a[0] = T(0.5) * (C.N + T(2)) * b[0] - b[3] * ih;
+    a[3] = -b[0] * ih + T(2) * b[3] * ih * ih / C.N;
+}
+
+// ---------------------------------------------------------------------------
 // The interface point: simplified third-order distribution (Sec. 2.1)
 //   f = g0 [1 + Abar t + G_tt t^2/2] - tau g0 [(abar.u + Abar) + (G_xt u + G_yt v + G_tt) t]
 //       + e^{-t/tau_n} { -g0 [1 - abar.u t] + g_l [1 - a_l.u t] H(u) + g_r [1 - a_r.u t] (1-H(u)) }
 // G_.. are the exact second Taylor coefficients of the Maxwellian over g0.
-// Outputs: FL (flux giving L), FdL (flux giving dL/dt), S0, S1, S2 (moments
-// of f^n, f_t^n, f_tt^n).  Everything in the local frame (normal = slot 1).
+// Outputs (type D, FP64): FL (flux giving L), FdL (flux giving dL/dt), S0,
+// S1, S2 (moments of f^n, f_t^n, f_tt^n).  Local frame (normal = slot 1).
+// Precision split: the O(1) quantities (equilibrium value, its Euler flux,
+// the half-range moments of the two states) are of type D; everything
+// proportional to a reconstructed derivative is of type T.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct PointIn {
-    T W0[4], W0x[4], W0y[4], W0xx[4], W0xy[4], W0yy[4];
-    T Wl[4], Wlx[4], Wly[4], Wr[4], Wrx[4], Wry[4];
+    T W0x[4], W0y[4], W0xx[4], W0xy[4], W0yy[4];
+    T Wlx[4], Wly[4], Wrx[4], Wry[4];
 };
-template <typename T>
+template <typename D>
 struct PointOut {
-    T FL[4], FdL[4], S0[4], S1[4], S2[4];
+    D FL[4], FdL[4], S0[4], S1[4], S2[4];
 };
 
 struct PointPar {
     double gamma, K, mu, dt;
 };
 
-// returns false for a non-physical state.  D: type of the FP64 time
-// coefficients (double; a counting type when operations are tallied).
-template <typename T, int DIM, typename D = double>
-GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, PointOut<T>& out)
+template <typename D, int NU, int DIM, typename T>
+GKS_HD void cast_moments(const Moments<D, DIM, NU>& a, Moments<T, DIM, NU>& b)
 {
-    const T gamma = T(par.gamma), K = T(par.K);
-    T r0, U0, V0, l0, p0, rl, Ul, Vl, ll, pl, rr, Ur, Vr, lr, pr;
-    if (!primitive<T, DIM>(in.W0, gamma, r0, U0, V0, l0, p0)) return false;
-    if (!primitive<T, DIM>(in.Wl, gamma, rl, Ul, Vl, ll, pl)) return false;
-    if (!primitive<T, DIM>(in.Wr, gamma, rr, Ur, Vr, lr, pr)) return false;
+    b.U = T(a.U); b.V = T(a.V); b.lam = T(a.lam);
+#pragma unroll
+    for (int n = 0; n < NU; ++n) b.mu[n] = T(a.mu[n]);
+#pragma unroll
+    for (int n = 0; n < (DIM == 2 ? 9 : 1); ++n) b.mv[n] = T(a.mv[n]);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) b.mx[n] = T(a.mx[n]);
+}
 
-    // collision times (Sec. 4): physical tau in the Navier-Stokes terms,
-    // numerical tau_n (with the pressure-jump term) in the exponentials
-    const D dtd = D(par.dt);
-    const D jump = tabs((D(pl) - D(pr)) / (D(pl) + D(pr))) * dtd;
-    const D tau_d = par.mu > 0.0 ? D(par.mu) / D(p0) : D(0);
-    const D tau_n = par.mu > 0.0 ? tau_d + jump : D(0.01) * dtd + jump;
-    D ke, kte, kde, kdte;
-    exp_fit<D>(tau_n, dtd, ke, kte, kde, kdte);
-    const T tau = T(tau_d);
+// The two non-equilibrium states at the point (Sec. 2.1, the g_l, g_r terms):
+//   Xs = <psi>_{l,u>0} + <psi>_{r,u<0},  Xf = <u psi>_{l,u>0} + <u psi>_{r,u<0}
+// (type D), their pressures, and (type T, only when slopes are given)
+//   Hn = <(a_l.u) psi>_{l,u>0} + <(a_r.u) psi>_{r,u<0},
+//   Hm = <u (a_l.u) psi>_{l,u>0} + <u (a_r.u) psi>_{r,u<0},
+// with a_l, a_r the micro-slopes of the states' normal (and tangential)
+// derivatives.
+template <typename D, int DIM, typename T = D>
+struct NonEq {
+    D pl, pr;
+    D Xs[4], Xf[4];
+    T Hn[4], Hm[4];
+};
 
-    // ---- equilibrium part, g0 (moments to degree 8) ----
-    Moments<T, DIM, 9> m0;
-    make_moments<T, DIM, 9>(U0, V0, l0, K, 0, m0);
-    const T ir0 = T(1) / r0;
-    T b[4], a1[4], a2[4] = {T(0), T(0), T(0), T(0)}, At[4], t1[4], t2[4];
+template <typename D, int DIM, typename T = D>
+GKS_HD bool noneq_states(const D* Wl, const D* Wr, D gamma, D K, NonEq<D, DIM, T>& ne, const T* Wlx = nullptr,
+                         const T* Wly = nullptr, const T* Wrx = nullptr, const T* Wry = nullptr)
+{
 #pragma unroll
-    for (int k = 0; k < 4; ++k) b[k] = in.W0x[k] * ir0;
-    micro_solve<T, DIM>(U0, V0, l0, K, b, a1);
-    if constexpr (DIM == 2) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] = in.W0y[k] * ir0;
-        micro_solve<T, DIM>(U0, V0, l0, K, b, a2);
-    }
-    // <A psi> = -<(a1 u + a2 v) psi>
-    T S1n[4];
-    lin<1, 0, DIM>(m0, a1, t1);
-    if constexpr (DIM == 2) {
-        lin<0, 1, DIM>(m0, a2, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) S1n[k] = -(t1[k] + t2[k]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) S1n[k] = -t1[k];
-    }
-    micro_solve<T, DIM>(U0, V0, l0, K, S1n, At);
-
-    // second derivatives: G = a_lin + product, <G_xx psi> = W_xx, ...
-    T axx[4], axy[4] = {T(0), T(0), T(0), T(0)}, ayy[4] = {T(0), T(0), T(0), T(0)}, axt[4], ayt[4] = {T(0), T(0), T(0), T(0)};
-    bil<0, 0, DIM>(m0, a1, a1, t1);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) b[k] = in.W0xx[k] * ir0 - t1[k];
-    micro_solve<T, DIM>(U0, V0, l0, K, b, axx);
-    if constexpr (DIM == 2) {
-        bil<0, 0, DIM>(m0, a1, a2, t1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] = in.W0xy[k] * ir0 - t1[k];
-        micro_solve<T, DIM>(U0, V0, l0, K, b, axy);
-        bil<0, 0, DIM>(m0, a2, a2, t1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] = in.W0yy[k] * ir0 - t1[k];
-        micro_solve<T, DIM>(U0, V0, l0, K, b, ayy);
-    }
-    // <(G_xx u + G_xy v + G_xt) psi> = 0
-    lin<1, 0, DIM>(m0, axx, t1);
-    bil<1, 0, DIM>(m0, a1, a1, t2);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) b[k] = -(t1[k] + t2[k]);
-    if constexpr (DIM == 2) {
-        lin<0, 1, DIM>(m0, axy, t1);
-        bil<0, 1, DIM>(m0, a1, a2, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] -= t1[k] + t2[k];
-    }
-    bil<0, 0, DIM>(m0, a1, At, t1);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) b[k] -= t1[k];
-    micro_solve<T, DIM>(U0, V0, l0, K, b, axt);
-    if constexpr (DIM == 2) {
-        // <(G_xy u + G_yy v + G_yt) psi> = 0
-        lin<1, 0, DIM>(m0, axy, t1);
-        bil<1, 0, DIM>(m0, a1, a2, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] = -(t1[k] + t2[k]);
-        lin<0, 1, DIM>(m0, ayy, t1);
-        bil<0, 1, DIM>(m0, a2, a2, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] -= t1[k] + t2[k];
-        bil<0, 0, DIM>(m0, a2, At, t1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] -= t1[k];
-        micro_solve<T, DIM>(U0, V0, l0, K, b, ayt);
-    }
-    // <G_tt psi> = -<(G_xt u + G_yt v) psi>  (this is f_tt's moment)
-    T S2n[4];
-    lin<1, 0, DIM>(m0, axt, t1);
-    bil<1, 0, DIM>(m0, a1, At, t2);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) S2n[k] = -(t1[k] + t2[k]);
-    if constexpr (DIM == 2) {
-        lin<0, 1, DIM>(m0, ayt, t1);
-        bil<0, 1, DIM>(m0, a2, At, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) S2n[k] -= t1[k] + t2[k];
-    }
-
-    // flux of the polynomial part: F0 = <u psi> - tau <u (a1 u + a2 v + A) psi>,
-    // F1 = <u A psi> - tau <u (G_xt u + G_yt v + G_tt) psi>
-    T F0[4], F1[4];
-    {
-        // Euler flux of W0 in closed form
-        const T E = in.W0[3];
-        F0[0] = in.W0[1];
-        F0[1] = in.W0[1] * U0 + p0;
-        F0[2] = in.W0[2] * U0;
-        F0[3] = U0 * (E + p0);
-    }
-    lin<1, 0, DIM>(m0, At, F1);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) F1[k] *= r0;
-    if (par.mu > 0.0) {
-        T v[4];
-        lin<2, 0, DIM>(m0, a1, t1);
-        lin<1, 0, DIM>(m0, At, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = t1[k] + t2[k];
-        if constexpr (DIM == 2) {
-            lin<1, 1, DIM>(m0, a2, t1);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] += t1[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) F0[k] -= tau * r0 * v[k];
-        // G_tt = a_tt + A^2 with <G_tt psi> = S2n
-        T att[4];
-        bil<0, 0, DIM>(m0, At, At, t1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] = S2n[k] - t1[k];
-        micro_solve<T, DIM>(U0, V0, l0, K, b, att);
-        lin<2, 0, DIM>(m0, axt, t1);
-        bil<2, 0, DIM>(m0, a1, At, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = t1[k] + t2[k];
-        if constexpr (DIM == 2) {
-            lin<1, 1, DIM>(m0, ayt, t1);
-            bil<1, 1, DIM>(m0, a2, At, t2);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] += t1[k] + t2[k];
-        }
-        lin<1, 0, DIM>(m0, att, t1);
-        bil<1, 0, DIM>(m0, At, At, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) F1[k] -= tau * r0 * (v[k] + t1[k] + t2[k]);
-    }
-    // equilibrium contributions to the e^{-t/tau_n} moments:
-    //   X0 -> -<u psi>0 (flux), -W0 (state)
-    //   X1 ->  <u (a1 u + a2 v) psi>0, <(a1 u + a2 v) psi>0 = -S1n
-    T Me[4], Mte[4], Ne[4], Nte[4];
-    lin<2, 0, DIM>(m0, a1, t1);
-    if constexpr (DIM == 2) {
-        lin<1, 1, DIM>(m0, a2, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) t1[k] += t2[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        Mte[k] = r0 * t1[k];
-        Ne[k] = -in.W0[k];
-        Nte[k] = -r0 * S1n[k];
-    }
-    // -<u psi>0 is minus the Euler flux of W0 (no tau terms here)
-    {
-        const T E = in.W0[3];
-        Me[0] = -in.W0[1];
-        Me[1] = -(in.W0[1] * U0 + p0);
-        Me[2] = -in.W0[2] * U0;
-        Me[3] = -U0 * (E + p0);
-    }
-
-    // ---- non-equilibrium states, half-range moments (degree 6) ----
+    for (int k = 0; k < 4; ++k) { ne.Xs[k] = D(0); ne.Xf[k] = D(0); ne.Hn[k] = T(0); ne.Hm[k] = T(0); }
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-        const T rs = side ? rr : rl, Us = side ? Ur : Ul, Vs = side ? Vr : Vl, ls = side ? lr : ll;
-        const T* Wn = side ? in.Wrx : in.Wlx;
-        const T* Wt = side ? in.Wry : in.Wly;
-        Moments<T, DIM, 7> mh;
-        make_moments<T, DIM, 7>(Us, Vs, ls, K, side ? -1 : +1, mh);
-        const T irs = T(1) / rs;
-        T as1[4], as2[4] = {T(0), T(0), T(0), T(0)};
+        D rs, Us, Vs, ls, ps;
+        if (!primitive<D, DIM>(side ? Wr : Wl, gamma, rs, Us, Vs, ls, ps)) return false;
+        if (side) ne.pr = ps;
+        else ne.pl = ps;
+        Moments<D, DIM, 7> m;
+        make_moments<D, DIM, 7>(Us, Vs, ls, K, side ? -1 : +1, m);
+        D h[4] = {D(0), D(0), D(0), D(0)};
+        psi_mom<0, 0, DIM>(m, h);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] = Wn[k] * irs;
-        micro_solve<T, DIM>(Us, Vs, ls, K, b, as1);
-        if constexpr (DIM == 2) {
+        for (int k = 0; k < 4; ++k) ne.Xs[k] += rs * h[k];
+        psi_mom<1, 0, DIM>(m, h);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) b[k] = Wt[k] * irs;
-            micro_solve<T, DIM>(Us, Vs, ls, K, b, as2);
+        for (int k = 0; k < 4; ++k) ne.Xf[k] += rs * h[k];
+        const T* Wn = side ? Wrx : Wlx;
+        if (Wn) {
+            const T* Wt = side ? Wry : Wly;
+            Moments<T, DIM, 7> mt;
+            cast_moments<D, 7, DIM, T>(m, mt);
+            const T rt = T(rs), irs = T(1) / T(rs), K_t = T(K);
+            T b[4], as1[4], as2[4] = {T(0), T(0), T(0), T(0)}, h2[4], h3[4], t1[4], t2[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b[k] = Wn[k] * irs;
+            micro_solve<T, DIM>(mt.U, mt.V, mt.lam, K_t, b, as1);
+            if constexpr (DIM == 2) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) b[k] = Wt[k] * irs;
+                micro_solve<T, DIM>(mt.U, mt.V, mt.lam, K_t, b, as2);
+            }
+            lin<1, 0, DIM>(mt, as1, h2); // <a1 u psi>_half
+            lin<2, 0, DIM>(mt, as1, h3); // <a1 u^2 psi>_half
+            if constexpr (DIM == 2) {
+                lin<0, 1, DIM>(mt, as2, t1);
+                lin<1, 1, DIM>(mt, as2, t2);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { h2[k] += t1[k]; h3[k] += t2[k]; }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { ne.Hn[k] += rt * h2[k]; ne.Hm[k] += rt * h3[k]; }
         }
-        T h0[4] = {T(0), T(0), T(0), T(0)}, h1[4] = {T(0), T(0), T(0), T(0)}, h2[4], h3[4];
-        psi_mom<0, 0, DIM>(mh, h0); // <psi>_half
-        psi_mom<1, 0, DIM>(mh, h1); // <u psi>_half
-        lin<1, 0, DIM>(mh, as1, h2); // <a1 u psi>_half
-        lin<2, 0, DIM>(mh, as1, h3); // <a1 u^2 psi>_half
-        if constexpr (DIM == 2) {
-            lin<0, 1, DIM>(mh, as2, t1);
-            lin<1, 1, DIM>(mh, as2, t2);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { h2[k] += t1[k]; h3[k] += t2[k]; }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            Ne[k] += rs * h0[k];
-            Me[k] += rs * h1[k];
-            Nte[k] -= rs * h2[k];
-            Mte[k] -= rs * h3[k];
-        }
-    }
-
-    const T Ke = T(ke), Kte = T(kte), Kde = T(kde), Kdte = T(kdte);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        out.FL[k] = F0[k] + Ke * Me[k] + Kte * Mte[k];
-        out.FdL[k] = F1[k] + Kde * Me[k] + Kdte * Mte[k];
-        out.S0[k] = in.W0[k] + Ke * Ne[k] + Kte * Nte[k];
-        out.S1[k] = r0 * S1n[k] + Kde * Ne[k] + Kdte * Nte[k];
-        out.S2[k] = r0 * S2n[k];
     }
     return true;
 }
 
 // Kinetic average of two states: int psi [g_l H(u) + g_r (1 - H(u))]
-template <typename T, int DIM>
-GKS_HD bool kinetic_average(const T* Wl, const T* Wr, T gamma, T K, T* W0)
+template <typename D, int DIM>
+GKS_HD bool kinetic_average(const D* Wl, const D* Wr, D gamma, D K, D* W0)
 {
-    T rl, Ul, Vl, ll, pl, rr, Ur, Vr, lr, pr;
-    if (!primitive<T, DIM>(Wl, gamma, rl, Ul, Vl, ll, pl)) return false;
-    if (!primitive<T, DIM>(Wr, gamma, rr, Ur, Vr, lr, pr)) return false;
-    Moments<T, DIM, 3> ml, mr;
-    make_moments<T, DIM, 3>(Ul, Vl, ll, K, +1, ml);
-    make_moments<T, DIM, 3>(Ur, Vr, lr, K, -1, mr);
-    T hl[4] = {T(0), T(0), T(0), T(0)}, hr[4] = {T(0), T(0), T(0), T(0)};
-    psi_mom<0, 0, DIM>(ml, hl);
-    psi_mom<0, 0, DIM>(mr, hr);
+    NonEq<D, DIM> ne;
+    if (!noneq_states<D, DIM>(Wl, Wr, gamma, K, ne)) return false;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) W0[k] = rl * hl[k] + rr * hr[k];
-    if constexpr (DIM == 1) W0[2] = T(0);
+    for (int k = 0; k < 4; ++k) W0[k] = ne.Xs[k];
+    return true;
+}
+
+// W0d: equilibrium state (type D); ne: the two non-equilibrium states.
+// Returns false for a non-physical equilibrium state.
+template <typename T, int DIM, typename D = double>
+GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, const NonEq<D, DIM, T>& ne,
+                      PointOut<D>& out)
+{
+    const D gammad = D(par.gamma);
+    D r0d, U0d, V0d, l0d, p0d;
+    if (!primitive<D, DIM>(W0d, gammad, r0d, U0d, V0d, l0d, p0d)) return false;
+
+    // collision times (Sec. 4): physical tau in the Navier-Stokes terms,
+    // numerical tau_n (with the pressure-jump term) in the exponentials
+    const D dtd = D(par.dt);
+    const D jump = tabs((ne.pl - ne.pr) / (ne.pl + ne.pr)) * dtd;
+    const D tau_d = par.mu > 0.0 ? D(par.mu) / p0d : D(0);
+    const D tau_n = par.mu > 0.0 ? tau_d + jump : D(0.01) * dtd + jump;
+    D ke, kte, kde, kdte;
+    exp_fit<D>(tau_n, dtd, ke, kte, kde, kdte);
+
+    // ---- equilibrium part in central velocities (type T) ----
+    Central<T> C;
+    const T r0 = T(r0d), ir0 = T(1) / T(r0d);
+    C.U = T(U0d);
+    C.V = T(V0d);
+    C.E0 = T(0.5) * (C.U * C.U + C.V * C.V);
+    C.N = T(par.K) + T(DIM);
+    C.h[0] = T(1);
+    C.h[1] = T(p0d / r0d);
+#pragma unroll
+    for (int n = 2; n < 7; ++n) C.h[n] = C.h[n - 1] * C.h[1];
+    const T U = C.U, V = C.V;
+    T bx[4], by[4] = {T(0), T(0), T(0), T(0)}, bxx[4], bxy[4] = {T(0), T(0), T(0), T(0)},
+             byy[4] = {T(0), T(0), T(0), T(0)};
+    to_central<T, DIM>(C, in.W0x, ir0, bx);
+    to_central<T, DIM>(C, in.W0xx, ir0, bxx);
+    if constexpr (DIM == 2) {
+        to_central<T, DIM>(C, in.W0y, ir0, by);
+        to_central<T, DIM>(C, in.W0xy, ir0, bxy);
+        to_central<T, DIM>(C, in.W0yy, ir0, byy);
+    }
+    T a1[4], a2[4] = {T(0), T(0), T(0), T(0)}, At[4], t1[4], t2[4];
+    gsolve<T, DIM>(C, bx, a1);
+    if constexpr (DIM == 2) gsolve<T, DIM>(C, by, a2);
+    // compatibility: G Abar = -(U b_x + <c a1 phi> + V b_y + <w a2 phi>)
+    T S1c[4];
+    clin<1, 0, DIM>(C, a1, t1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) S1c[k] = -(U * bx[k] + t1[k]);
+    if constexpr (DIM == 2) {
+        clin<0, 1, DIM>(C, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S1c[k] -= V * by[k] + t2[k];
+    }
+    gsolve<T, DIM>(C, S1c, At);
+    // second-order coefficients: <G_xx phi> = b_xx etc.
+    T axx[4], axy[4] = {T(0), T(0), T(0), T(0)}, ayy[4] = {T(0), T(0), T(0), T(0)};
+    cbil<0, 0, DIM>(C, a1, a1, t1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t1[k] = bxx[k] - t1[k];
+    gsolve<T, DIM>(C, t1, axx);
+    if constexpr (DIM == 2) {
+        cbil<0, 0, DIM>(C, a1, a2, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t1[k] = bxy[k] - t1[k];
+        gsolve<T, DIM>(C, t1, axy);
+        cbil<0, 0, DIM>(C, a2, a2, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t1[k] = byy[k] - t1[k];
+        gsolve<T, DIM>(C, t1, ayy);
+    }
+    // <G_xt phi> = -<(U + c) G_xx phi> - <(V + w) G_xy phi>  (= Pxt), same for yt
+    T Pxt[4], Pyt[4] = {T(0), T(0), T(0), T(0)};
+    clin<1, 0, DIM>(C, axx, t1);
+    cbil<1, 0, DIM>(C, a1, a1, t2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Pxt[k] = -(U * bxx[k] + t1[k] + t2[k]);
+    if constexpr (DIM == 2) {
+        clin<0, 1, DIM>(C, axy, t1);
+        cbil<0, 1, DIM>(C, a1, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Pxt[k] -= V * bxy[k] + t1[k] + t2[k];
+        clin<1, 0, DIM>(C, axy, t1);
+        cbil<1, 0, DIM>(C, a1, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Pyt[k] = -(U * bxy[k] + t1[k] + t2[k]);
+        clin<0, 1, DIM>(C, ayy, t1);
+        cbil<0, 1, DIM>(C, a2, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Pyt[k] -= V * byy[k] + t1[k] + t2[k];
+    }
+    T axt[4], ayt[4] = {T(0), T(0), T(0), T(0)};
+    cbil<0, 0, DIM>(C, a1, At, t1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t1[k] = Pxt[k] - t1[k];
+    gsolve<T, DIM>(C, t1, axt);
+    if constexpr (DIM == 2) {
+        cbil<0, 0, DIM>(C, a2, At, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t1[k] = Pyt[k] - t1[k];
+        gsolve<T, DIM>(C, t1, ayt);
+    }
+    // <G_tt phi> = -<(U + c) G_xt phi> - <(V + w) G_yt phi>
+    T S2c[4], cx[4], cy[4] = {T(0), T(0), T(0), T(0)};
+    clin<1, 0, DIM>(C, axt, t1);
+    cbil<1, 0, DIM>(C, a1, At, t2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { cx[k] = t1[k] + t2[k]; S2c[k] = -(U * Pxt[k] + cx[k]); } // cx = <c G_xt phi>
+    if constexpr (DIM == 2) {
+        clin<0, 1, DIM>(C, ayt, t1);
+        cbil<0, 1, DIM>(C, a2, At, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { cy[k] = t1[k] + t2[k]; S2c[k] -= V * Pyt[k] + cy[k]; } // cy = <w G_yt phi>
+    }
+    // <u Abar psi>: central U <Abar phi> + <c Abar phi>
+    T F1c[4], Mc[4];
+    clin<1, 0, DIM>(C, At, t1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) F1c[k] = U * S1c[k] + t1[k];
+    // <u (a1 u + a2 v) psi>0 (initial-layer slope term of g0)
+    clin<1, 0, DIM>(C, a1, t1);
+    clin<2, 0, DIM>(C, a1, t2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Mc[k] = U * U * bx[k] + T(2) * U * t1[k] + t2[k];
+    if constexpr (DIM == 2) {
+        T t3[4];
+        clin<0, 1, DIM>(C, a2, t3);
+        clin<1, 0, DIM>(C, a2, t1);
+        clin<1, 1, DIM>(C, a2, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Mc[k] += U * V * by[k] + U * t3[k] + V * t1[k] + t2[k];
+    }
+    T F0t[4] = {T(0), T(0), T(0), T(0)}, F1t[4] = {T(0), T(0), T(0), T(0)};
+    if (par.mu > 0.0) {
+        // <u (a1 u + a2 v + Abar) psi> = Mc + U <Abar phi> + <c Abar phi>
+        clin<1, 0, DIM>(C, At, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) F0t[k] = Mc[k] + U * S1c[k] + t1[k];
+        // <u (G_xt u + G_yt v + G_tt) psi>
+        T att[4];
+        cbil<0, 0, DIM>(C, At, At, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t1[k] = S2c[k] - t1[k];
+        gsolve<T, DIM>(C, t1, att);
+        clin<2, 0, DIM>(C, axt, t1);
+        cbil<2, 0, DIM>(C, a1, At, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) F1t[k] = U * U * Pxt[k] + T(2) * U * cx[k] + t1[k] + t2[k];
+        clin<1, 0, DIM>(C, att, t1);
+        cbil<1, 0, DIM>(C, At, At, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) F1t[k] += U * S2c[k] + t1[k] + t2[k];
+        if constexpr (DIM == 2) {
+            T t3[4];
+            clin<1, 0, DIM>(C, ayt, t1);
+            cbil<1, 0, DIM>(C, a2, At, t2);
+            clin<1, 1, DIM>(C, ayt, t3);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) F1t[k] += U * V * Pyt[k] + U * cy[k] + V * (t1[k] + t2[k]) + t3[k];
+            cbil<1, 1, DIM>(C, a2, At, t3);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) F1t[k] += t3[k];
+        }
+    }
+    // back to conservative components, times rho0
+    T F1[4], S1n[4], S2n[4], Mte[4], Nte[4];
+    from_central<T, DIM>(C, F1c, r0, F1);
+    from_central<T, DIM>(C, S1c, r0, S1n);
+    from_central<T, DIM>(C, S2c, r0, S2n);
+    from_central<T, DIM>(C, Mc, r0, Mte);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Nte[k] = -S1n[k];
+    if (par.mu > 0.0) {
+        from_central<T, DIM>(C, F0t, r0, t1);
+        from_central<T, DIM>(C, F1t, r0, t2);
+        const T tau = T(tau_d);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { F0t[k] = tau * t1[k]; F1[k] -= tau * t2[k]; }
+    }
+
+    // ---- non-equilibrium slope terms (computed with the states) ----
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Nte[k] -= ne.Hn[k];
+        Mte[k] -= ne.Hm[k];
+    }
+
+    // ---- equilibrium flux (type D) and the e^{-t/tau_n} value parts ----
+    D F0[4];
+    F0[0] = W0d[1];
+    F0[1] = W0d[1] * U0d + p0d;
+    F0[2] = W0d[2] * U0d;
+    F0[3] = U0d * (W0d[3] + p0d);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const D Me = ne.Xf[k] - F0[k];
+        const D Ne = ne.Xs[k] - W0d[k];
+        out.FL[k] = F0[k] - D(F0t[k]) + ke * Me + kte * D(Mte[k]);
+        out.FdL[k] = D(F1[k]) + kde * Me + kdte * D(Mte[k]);
+        out.S0[k] = W0d[k] + ke * Ne + kte * D(Nte[k]);
+        out.S1[k] = D(S1n[k]) + kde * Ne + kdte * D(Nte[k]);
+        out.S2[k] = D(S2n[k]);
+    }
+    if constexpr (DIM == 1) {
+        out.FL[2] = out.FdL[2] = out.S0[2] = out.S1[2] = out.S2[2] = D(0);
+    }
     return true;
 }
 

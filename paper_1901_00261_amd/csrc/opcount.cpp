@@ -34,6 +34,7 @@ inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
 inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
 inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
 inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
+inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
 inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
 inline Cnt sqrt(Cnt a) { ++cnt::trans; return Cnt(std::sqrt(a.v)); }
@@ -89,14 +90,18 @@ int main()
         const gks::PointPar par{gamma, K2, ns ? 1e-4 : 0.0, 1e-3};
         Tally a = snap();
         bool ok = true;
-        gks::PointIn<Cnt> in;
-        gks::PointOut<Cnt> out;
-        ok = ok && gks::gp_inputs<Cnt, 0, Cnt>(rv, Cnt(0.01), true, Cnt(gamma), Cnt(K2), in) &&
-             gks::gks_point<Cnt, 2, Cnt>(par, in, out);
-        ok = ok && gks::gp_inputs<Cnt, 1, Cnt>(rv, Cnt(0.01), true, Cnt(gamma), Cnt(K2), in) &&
-             gks::gks_point<Cnt, 2, Cnt>(par, in, out);
-        ok = ok && gks::gp_inputs<Cnt, 2, Cnt>(rv, Cnt(0.01), true, Cnt(gamma), Cnt(K2), in) &&
-             gks::gks_point<Cnt, 2, Cnt>(par, in, out);
+        auto one = [&](int G) {
+            gks::PointIn<Cnt> in;
+            gks::PointOut<Cnt> out;
+            Cnt W0[4], Wl[4], Wr[4];
+            gks::gp_inputs<Cnt, Cnt>(rv, G, Cnt(0.01), true, Cnt(gamma), in, W0, Wl, Wr);
+            gks::NonEq<Cnt, 2> ne;
+            ok = ok && gks::noneq_states<Cnt, 2>(Wl, Wr, Cnt(gamma), Cnt(K2), ne, in.Wlx, in.Wly, in.Wrx, in.Wry) &&
+                 gks::gks_point<Cnt, 2, Cnt>(par, in, ne.Xs, ne, out);
+        };
+        one(0);
+        one(1);
+        one(2);
         if (!ok) {
             fprintf(stderr, "opcount: unexpected non-physical sample\n");
             return 1;
@@ -119,14 +124,15 @@ int main()
         gks::PointIn<Cnt> in;
         gks::PointOut<Cnt> out;
         for (int k = 0; k < 4; ++k) {
-            in.W0[k] = o[0][k]; in.W0x[k] = o[1][k]; in.W0xx[k] = o[2][k];
+            in.W0x[k] = o[1][k]; in.W0xx[k] = o[2][k];
             in.W0y[k] = in.W0xy[k] = in.W0yy[k] = 0.0;
-            in.Wl[k] = o[3][k]; in.Wr[k] = o[4][k]; in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
+            in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
             in.Wly[k] = in.Wry[k] = 0.0;
         }
-        ok = ok && gks::kinetic_average<Cnt, 1>(in.Wl, in.Wr, Cnt(gamma), Cnt(K1), in.W0);
+        gks::NonEq<Cnt, 1> ne;
+        ok = ok && gks::noneq_states<Cnt, 1>(o[3], o[4], Cnt(gamma), Cnt(K1), ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
         const gks::PointPar par{gamma, K1, 0.0, 1e-3};
-        ok = ok && gks::gks_point<Cnt, 1, Cnt>(par, in, out);
+        ok = ok && gks::gks_point<Cnt, 1, Cnt>(par, in, ne.Xs, ne, out);
         if (!ok) {
             fprintf(stderr, "opcount: unexpected non-physical sample\n");
             return 1;
