@@ -101,60 +101,59 @@ __device__ __forceinline__ void tile_xy(int gx, int& tx, int& ty)
 // ---------------------------------------------------------------------------
 // Reconstruction at one face from a 4-cell stencil (local frame, slot 1 =
 // normal velocity).  Wk/Dk: cell averages and cell-width * normal slopes of
-// cells i-1..i+2.  Output (local frame): o[0] W0, o[1] dn W0 (per unit
-// length), o[2] dnn W0, o[3] Wl, o[4] Wr, o[5] dn Wl, o[6] dn Wr.
+// cells i-1..i+2.  emit(q, k, value) receives, in the local frame: q = 0 W0,
+// 1 dn W0 (per unit length), 2 dnn W0, 3 Wl, 4 Wr, 5 dn Wl, 6 dn Wr.
 // Non-physical WENO states fall back to the adjacent cell average.
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, int ORDER, typename D = double>
-GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, bool weno, D (&o)[7][4])
+template <typename T, int DIM, int ORDER, typename D = double, typename Emit>
+GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, bool weno, Emit&& emit)
 {
     const D ih = D(1) / h;
     // offsets from the cell left of the face keep the differences exact
-    D base[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) base[k] = Wk[1][k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (DIM == 1 && k == 2) {
 #pragma unroll
-            for (int q = 0; q < 7; ++q) o[q][k] = D(0);
+            for (int q = 0; q < 7; ++q) emit(q, k, D(0));
             continue;
         }
+        const D base = Wk[1][k];
         T w[4], d[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { w[q] = T(Wk[q][k] - base[k]); d[q] = T(Dk[q][k]); }
+        for (int q = 0; q < 4; ++q) { w[q] = T(Wk[q][k] - base); d[q] = T(Dk[q][k]); }
         T v, vx, vxx;
         linear_recon<T, ORDER>(w, d, v, vx, vxx);
-        o[0][k] = base[k] + D(v);
-        o[1][k] = D(vx) * ih;
-        o[2][k] = D(vxx) * ih * ih;
-    }
-    if (!weno) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            o[3][k] = o[4][k] = o[0][k];
-            o[5][k] = o[6][k] = o[1][k];
+        emit(0, k, base + D(v));
+        emit(1, k, D(vx) * ih);
+        emit(2, k, D(vxx) * ih * ih);
+        if (!weno) {
+            emit(3, k, base + D(v));
+            emit(4, k, base + D(v));
+            emit(5, k, D(vx) * ih);
+            emit(6, k, D(vx) * ih);
         }
-        return true;
     }
+    if (!weno) return true;
     // characteristic frame at the mean of the two interface cells
     D Wm[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) Wm[k] = D(0.5) * (Wk[1][k] + Wk[2][k]);
-    D R[4][4], L[4][4];
-    if (!char_frame<D, DIM>(Wm, gamma, R, L)) return false;
+    CharFrame<D, DIM> fr;
+    if (!fr.init(Wm, gamma)) return false;
     D ql[4], qr[4], qlx[4], qrx[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         if (DIM == 1 && a == 2) { ql[a] = qr[a] = qlx[a] = qrx[a] = D(0); continue; }
+        D l[4];
+        fr.left(a, l);
         T w[4], d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             D sw = D(0), sd = D(0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                sw += L[a][k] * (Wk[q][k] - base[k]);
-                sd += L[a][k] * Dk[q][k];
+                sw += l[k] * (Wk[q][k] - Wk[1][k]);
+                sd += l[k] * Dk[q][k];
             }
             w[q] = T(sw);
             d[q] = T(sd);
@@ -164,27 +163,24 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
         weno_right<T, ORDER>(w, d, vr, dr);
         ql[a] = D(vl); qlx[a] = D(dl); qr[a] = D(vr); qrx[a] = D(dr);
     }
+    D Wl[4], Wr[4], Wlx[4], Wrx[4];
+    fr.right(ql, Wl);
+    fr.right(qr, Wr);
+    fr.right(qlx, Wlx);
+    fr.right(qrx, Wrx);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        D sl = D(0), sr = D(0), slx = D(0), srx = D(0);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            sl += R[k][a] * ql[a];
-            sr += R[k][a] * qr[a];
-            slx += R[k][a] * qlx[a];
-            srx += R[k][a] * qrx[a];
-        }
-        o[3][k] = base[k] + sl;
-        o[4][k] = base[k] + sr;
-        o[5][k] = slx * ih;
-        o[6][k] = srx * ih;
+        Wl[k] += Wk[1][k];
+        Wr[k] += Wk[1][k];
     }
-    if (!physical<D>(o[3], gamma, DIM))
+    const bool okl = physical<D>(Wl, gamma, DIM), okr = physical<D>(Wr, gamma, DIM);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[3][k] = Wk[1][k];
-    if (!physical<D>(o[4], gamma, DIM))
-#pragma unroll
-        for (int k = 0; k < 4; ++k) o[4][k] = Wk[2][k];
+    for (int k = 0; k < 4; ++k) {
+        emit(3, k, okl ? Wl[k] : Wk[1][k]);
+        emit(4, k, okr ? Wr[k] : Wk[2][k]);
+        emit(5, k, Wlx[k] * ih);
+        emit(6, k, Wrx[k] * ih);
+    }
     return true;
 }
 
@@ -226,8 +222,9 @@ __global__ void __launch_bounds__(kBlock1D) face1d_kernel(const ProbParam* __res
         Dk[q][3] = zero ? 0.0 : P.dx * Xb[2 * Ntot + c];
     }
     double o[7][4];
-    bool ok = (P.order == 8) ? face_recon<T, 1, 8>(Wk, Dk, P.dx, P.gamma, P.recon != 0, o)
-                             : face_recon<T, 1, 6>(Wk, Dk, P.dx, P.gamma, P.recon != 0, o);
+    auto put = [&](int q, int k, double v) { o[q][k] = v; };
+    bool ok = (P.order == 8) ? face_recon<T, 1, 8>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
+                             : face_recon<T, 1, 6>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put);
     PointIn<T> in;
     PointOut<double> out;
     NonEq<double, 1, T> ne;
@@ -427,18 +424,11 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
         Wk[q][1] = DIR == 0 ? w[1] : w[2]; Wk[q][2] = DIR == 0 ? w[2] : w[1];
         Dk[q][1] = DIR == 0 ? d[1] : d[2]; Dk[q][2] = DIR == 0 ? d[2] : d[1];
     }
-    double o[7][4];
-    const bool ok = (P.order == 8) ? face_recon<T, 2, 8>(Wk, Dk, h, P.gamma, P.recon != 0, o)
-                                   : face_recon<T, 2, 6>(Wk, Dk, h, P.gamma, P.recon != 0, o);
-    if (!ok) {
-        S.err = 1;
-        return;
-    }
     const size_t AB = (size_t)A * B, ab = (size_t)a * B + b;
-#pragma unroll
-    for (int q = 0; q < 7; ++q)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) R[(q * 4 + k) * AB + ab] = o[q][k];
+    auto put = [&](int q, int k, double v) { R[(q * 4 + k) * AB + ab] = v; };
+    const bool ok = (P.order == 8) ? face_recon<T, 2, 8>(Wk, Dk, h, P.gamma, P.recon != 0, put)
+                                   : face_recon<T, 2, 6>(Wk, Dk, h, P.gamma, P.recon != 0, put);
+    if (!ok) S.err = 1;
 }
 
 // Gauss-point inputs at point g (0..2) of the 3-point rule: tangential

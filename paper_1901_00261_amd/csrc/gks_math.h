@@ -180,6 +180,44 @@ GKS_HD bool char_frame(const T* W, T gamma, T R[4][4], T L[4][4])
     return true;
 }
 
+// The same eigenvectors from six scalars, entries rebuilt on demand (keeps
+// two 4x4 matrices out of the registers while the WENO-Z runs).
+template <typename T, int DIM>
+struct CharFrame {
+    T U, V, c, H, b1, b2, ic;
+    GKS_HD bool init(const T* W, T gamma)
+    {
+        const T rho = W[0];
+        U = W[1] / rho;
+        V = (DIM == 2) ? W[2] / rho : T(0);
+        const T q2 = U * U + V * V;
+        const T p = (gamma - T(1)) * (W[3] - T(0.5) * rho * q2);
+        if (!(rho > T(0)) || !(p > T(0))) return false;
+        c = sqrt(gamma * p / rho);
+        H = (W[3] + p) / rho;
+        b1 = (gamma - T(1)) / (c * c);
+        b2 = T(0.5) * q2 * b1;
+        ic = T(1) / c;
+        return true;
+    }
+    // row a of L = R^{-1}
+    GKS_HD void left(int a, T* l) const
+    {
+        if (a == 0) { l[0] = T(0.5) * (b2 + U * ic); l[1] = T(-0.5) * (b1 * U + ic); l[2] = T(-0.5) * b1 * V; l[3] = T(0.5) * b1; }
+        else if (a == 1) { l[0] = T(1) - b2; l[1] = b1 * U; l[2] = b1 * V; l[3] = -b1; }
+        else if (a == 2) { l[0] = -V; l[1] = T(0); l[2] = T(1); l[3] = T(0); }
+        else { l[0] = T(0.5) * (b2 - U * ic); l[1] = T(-0.5) * (b1 * U - ic); l[2] = T(-0.5) * b1 * V; l[3] = T(0.5) * b1; }
+    }
+    // sum_a R[k][a] q[a]
+    GKS_HD void right(const T* q, T* out) const
+    {
+        out[0] = q[0] + q[1] + q[3];
+        out[1] = (U - c) * q[0] + U * q[1] + (U + c) * q[3];
+        out[2] = DIM == 2 ? V * (q[0] + q[1] + q[3]) + q[2] : T(0);
+        out[3] = (H - U * c) * q[0] + T(0.5) * (U * U + V * V) * q[1] + (DIM == 2 ? V * q[2] : T(0)) + (H + U * c) * q[3];
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Tangential reconstruction at the three Gauss points y_j + s dy/2,
 // s = -sqrt(3/5), 0, +sqrt(3/5), from the five row values j-2..j+2.

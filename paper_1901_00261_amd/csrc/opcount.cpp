@@ -71,7 +71,7 @@ int main()
             for (int k = 0; k < 4; ++k) Dk[q][k] = 0.01 * (k + 1) * (q + 1);
         }
         Tally a = snap();
-        gks::face_recon<Cnt, 2, 8, Cnt>(Wk, Dk, Cnt(0.01), Cnt(gamma), true, o);
+        gks::face_recon<Cnt, 2, 8, Cnt>(Wk, Dk, Cnt(0.01), Cnt(gamma), true, [&](int q, int k, Cnt v) { o[q][k] = v; });
         emit("face_row_2d", diff(a, snap()), true);
     }
     // ---- 2-D Gauss point (NS: mu > 0; and Euler), WENO-Z, averaged over the 3 points
@@ -120,7 +120,7 @@ int main()
             for (int k = 0; k < 4; ++k) Dk[q][k] = k == 2 ? 0.0 : 0.01 * (k + 1) * (q + 1);
         }
         Tally a = snap();
-        bool ok = gks::face_recon<Cnt, 1, 8, Cnt>(Wk, Dk, Cnt(0.01), Cnt(gamma), true, o);
+        bool ok = gks::face_recon<Cnt, 1, 8, Cnt>(Wk, Dk, Cnt(0.01), Cnt(gamma), true, [&](int q, int k, Cnt v) { o[q][k] = v; });
         gks::PointIn<Cnt> in;
         gks::PointOut<Cnt> out;
         for (int k = 0; k < 4; ++k) {

@@ -1,0 +1,94 @@
+"""FP32-mixed path (GKS_PREC_FP32_MIXED) against the FP64 oracle (needs a GPU).
+
+The mixed path computes the equilibrium value, its Euler flux, the
+half-range moments of the WENO-Z states, the time coefficients and every
+MSMD accumulation in FP64; only terms proportional to a reconstructed
+derivative (micro-slopes, Taylor coefficients, WENO-Z weights and
+candidates, tangential reconstruction of derivatives) are FP32, with unit
+roundoff u = 6e-8.  Those terms enter the face values multiplied by dt or
+dt^2 and the fluxes as corrections, so after n steps the state deviates by
+about n * u * dt * |dL/dt| ~ 1e-9..1e-8 and the gradients (differences of
+face values over dx) by about u relative.  Bars used here: 2e-7 relative
+Linf on states and 2e-5 relative on gradients for smooth problems; for
+shocks, where FP32 WENO-Z weights can switch differently, the relative L1
+of the states is held to 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_00261_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+MIXED = 1
+
+
+def gks():
+    from paper_1901_00261_amd import gks as g
+    return g
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rel_l1(a, b):
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def run(probs, precision, steps=None):
+    g = gks()
+    S = g.Solver(probs, precision)
+    if steps is None:
+        while S.step(100000) > 0:
+            pass
+    else:
+        S.step(steps)
+    out = [S.state(p) for p in range(len(probs))]
+    S.close()
+    return out
+
+
+def test_mixed_sine_full_run():
+    p = wl.sine_wave_1d(80, order=6, recon=0)
+    got = run([p], MIXED)[0]
+    want = oracle.run(1, p.W, p.Wx, **p.oracle_kwargs())
+    print("mixed sine W", rel(got[0], want[0]), "Wx", rel(got[1], want[1]))
+    assert got[4] == want[4]
+    assert rel(got[0], want[0]) < 2e-7 and rel(got[1], want[1]) < 2e-5
+
+
+def test_mixed_keeps_order_to_fp32_floor():
+    """T17: on the Sec. 4.1 accuracy test the mixed path's errors follow the
+    FP64 ones while they are above the FP32 floor (here 1e-8 in L1)."""
+    for order in (6, 8):
+        for n in (5, 10, 20):
+            p = wl.sine_wave_1d(n, order=order, recon=1, dt_fixed=wl.accuracy_dt(n, order))
+            got = run([p], MIXED)[0]
+            e_mixed = np.abs(got[0][:, 0] - p.W[:, 0]).mean()
+            want = oracle.run(1, p.W, p.Wx, **p.oracle_kwargs())
+            e64 = np.abs(want[0][:, 0] - p.W[:, 0]).mean()
+            print(f"order {order} N {n}: L1 fp64 {e64:.3e} mixed {e_mixed:.3e}")
+            assert abs(e_mixed - e64) <= 1e-3 * e64 + 1e-8
+
+
+def test_mixed_2d_vortex_small():
+    p = wl.isentropic_vortex_2d(20, ny=16, mu=1e-3, acoustic_amp=1e-2)
+    got = run([p], MIXED, steps=3)[0]
+    want = oracle.run(2, p.W, p.Wx, p.Wy, **{**p.oracle_kwargs(), "max_steps": 3})
+    print("mixed vortex W", rel(got[0], want[0]), "Wx", rel(got[1], want[1]), "Wy", rel(got[2], want[2]))
+    assert rel(got[0], want[0]) < 2e-7
+    assert rel(got[1], want[1]) < 2e-5 and rel(got[2], want[2]) < 2e-5
+
+
+def test_mixed_riemann_set():
+    probs = wl.riemann_set_1d(3, n=400) + [wl.riemann_1d(400, *wl.SOD)]
+    got = run(probs, MIXED)
+    for p, g in zip(probs, got):
+        want = oracle.run(1, p.W, p.Wx, **p.oracle_kwargs())
+        print(p.name, "rel L1", rel_l1(g[0], want[0]))
+        assert g[4] == want[4]
+        assert rel_l1(g[0], want[0]) < 1e-5
