@@ -109,13 +109,27 @@ const char* gks_last_error(const gks_handle* h);
 /* Kernel timing with HIP events on the handle's stream.  enable != 0 records
    an event pair around every launch of the kernels of the given id from now
    on; gks_kernel_time returns the summed time (ms) and the launch count since
-   enabling.  Ids: 0 interface (flux) kernels, 1 face-row reconstruction
-   kernels (2-D), 2 cell update kernels. */
+   enabling.  Ids: 0 interface (flux) kernels (1-D: the pair of fused stage
+   kernels, interface and cell update, counts as one launch), 1 face-row
+   reconstruction kernels (2-D), 2 cell update kernels (2-D).  Steps are not
+   replayed from a graph while timing is on. */
 int gks_kernel_timing(gks_handle* h, int32_t enable);
 int gks_kernel_time(gks_handle* h, int32_t kernel_id, double* total_ms, int64_t* launches);
 
 /* Number of cells * MSMD steps the last gks_step performed (all problems). */
 int gks_cell_updates(const gks_handle* h, int64_t* count);
+
+/* Launch configuration of the handle (text, valid until the next call on
+   h).  A batched 1-D handle runs one kernel per MSMD stage over work items
+   of BLK-1 cells (BLK = 64, 128 or 256 threads), with GMUL persistent
+   workgroups per compute unit or, for GMUL = 0, one workgroup per item.
+   The first gks_step of a 1-D handle autotunes (BLK, GMUL) by timing a few
+   steps from the initial state, which is restored afterwards; every
+   configuration performs the same arithmetic, so results do not depend on
+   the choice.  Environment: GKS_TUNE="BLK:GMUL" forces a configuration,
+   GKS_TUNE_CACHE=<file> caches tuning results by problem-set signature,
+   GKS_GRAPH=0 disables the hipGraph replay of steps (enabled by default). */
+const char* gks_launch_config(const gks_handle* h);
 
 #ifdef __cplusplus
 }

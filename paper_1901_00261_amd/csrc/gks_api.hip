@@ -34,9 +34,8 @@ struct gks_handle {
     ProbParam* dP = nullptr;
     ProbState* dS = nullptr;
     long long Ntot = 0, F = 0; // 1-D cells and faces
-    Tile* dTilesF = nullptr;
-    Tile* dTilesC = nullptr;
-    int nTilesF = 0, nTilesC = 0;
+    Tile* dTilesC = nullptr; // 1-D cell tiles of kBlock1D (signal-speed kernel)
+    int nTilesC = 0;
     double *W = nullptr, *Wx = nullptr, *Wy = nullptr, *PW = nullptr;
     double *FL = nullptr, *FdL = nullptr, *Wfs = nullptr, *Pf = nullptr;
     double *FLy = nullptr, *FdLy = nullptr, *Wfsy = nullptr, *Pfy = nullptr;
@@ -50,6 +49,21 @@ struct gks_handle {
     double tot_ms[3] = {0, 0, 0};
     long long launches[3] = {0, 0, 0};
     long long last_updates = 0;
+    // batched 1-D: work items per tile size, device work counters
+    unsigned* ctr = nullptr;
+    Tile* dItems[3] = {nullptr, nullptr, nullptr}; // tile sizes 64, 128, 256 (BLK - 1 cells each)
+    int nItems[3] = {0, 0, 0};
+    int ncu = 256;
+    // launch configuration (autotuned): threads per tile, workgroups per CU
+    // (0: one workgroup per work item)
+    bool tuned = false;
+    int blk = 128, gmul = 2;
+    std::string tune_note, cfg_text;
+    // step graph
+    bool use_graph = true;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -132,9 +146,9 @@ int validate(const gks_problem* pr, int32_t nprob, int32_t precision)
     return GKS_OK;
 }
 
-void record(gks_handle* h, int kind, bool begin)
+void record(gks_handle* h, hipStream_t st, int kind, bool begin)
 {
-    if (!h->timing) return;
+    if (!h->timing || st != h->stream) return;
     if (begin) {
         EventPair e;
         if (!h->pool.empty()) {
@@ -165,29 +179,28 @@ void harvest(gks_handle* h)
     h->pending.clear();
 }
 
-template <typename T> void launch_step_1d(gks_handle* h)
+template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
 {
-    const dim3 bf(gks::kBlock1D);
-    record(h, 0, true);
-    gks::face1d_kernel<T, 1><<<h->nTilesF, bf, 0, h->stream>>>(h->dP, h->dS, h->dTilesF, h->W, h->Wx, h->Ntot, h->F,
-                                                                h->FL, h->FdL, h->Wfs, h->Pf);
-    record(h, 0, false);
-    record(h, 2, true);
-    gks::cell1d_kernel<1><<<h->nTilesC, bf, 0, h->stream>>>(h->dP, h->dS, h->dTilesC, h->W, h->Wx, h->PW, h->Ntot, h->F,
-                                                            h->FL, h->FdL, h->Wfs);
-    record(h, 2, false);
-    record(h, 0, true);
-    gks::face1d_kernel<T, 2><<<h->nTilesF, bf, 0, h->stream>>>(h->dP, h->dS, h->dTilesF, h->W, h->Wx, h->Ntot, h->F,
-                                                                h->FL, h->FdL, h->Wfs, h->Pf);
-    record(h, 0, false);
-    record(h, 2, true);
-    gks::cell1d_kernel<2><<<h->nTilesC, bf, 0, h->stream>>>(h->dP, h->dS, h->dTilesC, h->W, h->Wx, h->PW, h->Ntot, h->F,
-                                                            h->FL, h->FdL, h->Wfs);
-    record(h, 2, false);
-    gks::finish_kernel<<<(h->nprob + 63) / 64, 64, 0, h->stream>>>(h->dP, h->dS, h->nprob, 1);
+    const int b = h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2);
+    const Tile* it = h->dItems[b];
+    const int n = h->nItems[b];
+    const int G = h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu);
+    record(h, st, 0, true);
+    if (h->blk == 64) {
+        gks::stage1d_kernel<T, 1, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+    } else if (h->blk == 128) {
+        gks::stage1d_kernel<T, 1, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+    } else {
+        gks::stage1d_kernel<T, 1, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+    }
+    record(h, st, 0, false);
+    gks::finish_kernel<<<(h->nprob + 63) / 64, 64, 0, st>>>(h->dP, h->dS, h->nprob, 1, h->ctr);
 }
 
-template <typename T> void launch_step_2d(gks_handle* h)
+template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
 {
     const ProbParam& P = h->hp[0];
     const int nx = P.nx, ny = P.ny;
@@ -199,47 +212,202 @@ template <typename T> void launch_step_2d(gks_handle* h)
     const int ggx = tiles(nx + 1, ny, bg), ggy = tiles(nx, ny + 1, bg);
     const int gc = tiles(nx, ny, bc);
     for (int stage = 1; stage <= 2; ++stage) {
-        record(h, 1, true);
-        gks::row2d_kernel<T, 0><<<grx, br, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
-        record(h, 1, false);
-        record(h, 0, true);
+        record(h, st, 1, true);
+        gks::row2d_kernel<T, 0><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
+        record(h, st, 1, false);
+        record(h, st, 0, true);
         if (stage == 1)
-            gks::gp2d_kernel<T, 0, 1><<<ggx, bg, 0, h->stream>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
+            gks::gp2d_kernel<T, 0, 1><<<ggx, bg, 0, st>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
         else
-            gks::gp2d_kernel<T, 0, 2><<<ggx, bg, 0, h->stream>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
-        record(h, 0, false);
-        record(h, 1, true);
-        gks::row2d_kernel<T, 1><<<gry, br, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
-        record(h, 1, false);
-        record(h, 0, true);
+            gks::gp2d_kernel<T, 0, 2><<<ggx, bg, 0, st>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
+        record(h, st, 0, false);
+        record(h, st, 1, true);
+        gks::row2d_kernel<T, 1><<<gry, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
+        record(h, st, 1, false);
+        record(h, st, 0, true);
         if (stage == 1)
-            gks::gp2d_kernel<T, 1, 1><<<ggy, bg, 0, h->stream>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy,
-                                                                 h->Pfy);
+            gks::gp2d_kernel<T, 1, 1><<<ggy, bg, 0, st>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
         else
-            gks::gp2d_kernel<T, 1, 2><<<ggy, bg, 0, h->stream>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy,
-                                                                 h->Pfy);
-        record(h, 0, false);
-        record(h, 2, true);
+            gks::gp2d_kernel<T, 1, 2><<<ggy, bg, 0, st>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
+        record(h, st, 0, false);
+        record(h, st, 2, true);
         if (stage == 1)
-            gks::cell2d_kernel<1><<<gc, bc, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL,
-                                                             h->Wfs, h->FLy, h->FdLy, h->Wfsy);
+            gks::cell2d_kernel<1><<<gc, bc, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL, h->Wfs,
+                                                      h->FLy, h->FdLy, h->Wfsy);
         else
-            gks::cell2d_kernel<2><<<gc, bc, 0, h->stream>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL,
-                                                             h->Wfs, h->FLy, h->FdLy, h->Wfsy);
-        record(h, 2, false);
+            gks::cell2d_kernel<2><<<gc, bc, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL, h->Wfs,
+                                                      h->FLy, h->FdLy, h->Wfsy);
+        record(h, st, 2, false);
     }
-    gks::finish_kernel<<<1, 64, 0, h->stream>>>(h->dP, h->dS, 1, 1);
+    gks::finish_kernel<<<1, 64, 0, st>>>(h->dP, h->dS, 1, 1, nullptr);
+}
+
+void launch_step(gks_handle* h, hipStream_t st)
+{
+    if (h->dim == 1) {
+        if (h->precision == GKS_PREC_FP64) launch_step_1d<double>(h, st);
+        else launch_step_1d<float>(h, st);
+    } else {
+        if (h->precision == GKS_PREC_FP64) launch_step_2d<double>(h, st);
+        else launch_step_2d<float>(h, st);
+    }
+}
+
+void drop_graph(gks_handle* h)
+{
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+}
+
+// capture one MSMD step (kernel nodes only) on the private capture stream
+int build_graph(gks_handle* h)
+{
+    drop_graph(h);
+    HIP_TRY(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    launch_step(h, h->cap);
+    HIP_TRY(h, hipStreamEndCapture(h->cap, &h->graph));
+    HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    return GKS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner for the batched 1-D path: tile size (64, 128, 256 threads) and
+// grid size (1, 2, 4 persistent workgroups per CU, or one workgroup per work
+// item); each candidate runs 1 + 2 steps (the last two timed) from the same
+// saved state, which is restored afterwards.  All candidates run the same
+// per-face and per-cell arithmetic, so the choice does not change results.
+// GKS_TUNE="BLK:GMUL" forces a configuration; GKS_TUNE_CACHE names a text
+// file of "signature blk gmul" lines read before and appended after tuning.
+// ---------------------------------------------------------------------------
+std::string tune_signature(const gks_handle* h)
+{
+    int maxnx = 0;
+    for (const auto& P : h->hp) maxnx = std::max(maxnx, P.nx);
+    char buf[160];
+    snprintf(buf, sizeof buf, "dim1:np%d:N%lld:max%d:prec%d:cu%d", h->nprob, h->Ntot, maxnx, h->precision, h->ncu);
+    return buf;
+}
+
+bool parse_forced(const char* s, int& blk, int& gmul)
+{
+    int b = 0, g = -1;
+    char tail = 0;
+    if (sscanf(s, "%d:%d%c", &b, &g, &tail) == 2 && (b == 64 || b == 128 || b == 256) && g >= 0 && g <= 16) {
+        blk = b;
+        gmul = g;
+        return true;
+    }
+    return false;
+}
+
+int autotune(gks_handle* h)
+{
+    h->tuned = true;
+    if (const char* f = getenv("GKS_TUNE")) {
+        if (!parse_forced(f, h->blk, h->gmul)) {
+            h->tuned = false;
+            return fail(h, GKS_EINVAL, std::string("bad GKS_TUNE (want BLK:GMUL, BLK 64/128/256, GMUL 0..16): ") + f);
+        }
+        h->tune_note = std::string("forced ") + f;
+        return GKS_OK;
+    }
+    const std::string sig = tune_signature(h);
+    const char* cache = getenv("GKS_TUNE_CACHE");
+    if (cache) {
+        if (FILE* fp = fopen(cache, "r")) {
+            char line[256];
+            while (fgets(line, sizeof line, fp)) {
+                char key[200];
+                int b, g;
+                if (sscanf(line, "%199s %d %d", key, &b, &g) == 3 && sig == key && (b == 64 || b == 128 || b == 256) &&
+                    g >= 0 && g <= 16) {
+                    h->blk = b; h->gmul = g;
+                    h->tune_note = "cache " + sig;
+                }
+            }
+            fclose(fp);
+            if (!h->tune_note.empty()) return GKS_OK;
+        }
+    }
+    // save state (both buffers) and bookkeeping
+    const size_t nW = (size_t)2 * 3 * h->Ntot;
+    double *sW = nullptr, *sX = nullptr;
+    std::vector<ProbState> s0(h->nprob);
+    HIP_TRY(h, dalloc(&sW, nW));
+    HIP_TRY(h, dalloc(&sX, nW));
+    HIP_TRY(h, hipMemcpyAsync(sW, h->W, nW * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(sX, h->Wx, nW * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(s0.data(), h->dS, sizeof(ProbState) * h->nprob, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    struct Cand { int blk, gmul; };
+    std::vector<Cand> cands;
+    for (int b : {64, 128, 256})
+        for (int g : {0, 1, 2, 4}) cands.push_back({b, g});
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    float best = 1e30f;
+    Cand bc = cands[0];
+    const bool was_timing = h->timing;
+    h->timing = false;
+    int st = GKS_OK;
+    for (const Cand& c : cands) {
+        h->blk = c.blk; h->gmul = c.gmul;
+        launch_step(h, h->stream);
+        (void)hipEventRecord(e0, h->stream);
+        launch_step(h, h->stream);
+        launch_step(h, h->stream);
+        (void)hipEventRecord(e1, h->stream);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(h, GKS_EDEVICE, "autotune: timing failed");
+            break;
+        }
+        if (ms < best) { best = ms; bc = c; }
+        // restore
+        if (hipMemcpyAsync(h->W, sW, nW * sizeof(double), hipMemcpyDeviceToDevice, h->stream) != hipSuccess ||
+            hipMemcpyAsync(h->Wx, sX, nW * sizeof(double), hipMemcpyDeviceToDevice, h->stream) != hipSuccess ||
+            hipMemcpyAsync(h->dS, s0.data(), sizeof(ProbState) * h->nprob, hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess) {
+            st = fail(h, GKS_EDEVICE, "autotune: state restore failed");
+            break;
+        }
+    }
+    h->timing = was_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dfree(sW);
+    dfree(sX);
+    if (st) return st;
+    h->blk = bc.blk; h->gmul = bc.gmul;
+    char note[200];
+    snprintf(note, sizeof note, "tuned %s: blk %d gmul %d (%.3f ms for 2 steps)", sig.c_str(), bc.blk, bc.gmul, best);
+    h->tune_note = note;
+    if (cache) {
+        if (FILE* fp = fopen(cache, "a")) {
+            fprintf(fp, "%s %d %d\n", sig.c_str(), bc.blk, bc.gmul);
+            fclose(fp);
+        }
+    }
+    return GKS_OK;
 }
 
 void release(gks_handle* h)
 {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (void* p : {(void*)h->dP, (void*)h->dS, (void*)h->dTilesF, (void*)h->dTilesC, (void*)h->W, (void*)h->Wx,
+    for (void* p : {(void*)h->dP, (void*)h->dS, (void*)h->dTilesC, (void*)h->W, (void*)h->Wx,
                     (void*)h->Wy, (void*)h->PW, (void*)h->FL, (void*)h->FdL, (void*)h->Wfs, (void*)h->Pf,
                     (void*)h->FLy, (void*)h->FdLy, (void*)h->Wfsy, (void*)h->Pfy, (void*)h->Rx, (void*)h->Ry,
                     (void*)h->stage})
         dfree(p);
+    drop_graph(h);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    dfree(h->ctr);
+    for (int b = 0; b < 3; ++b) dfree(h->dItems[b]);
     for (auto& e : h->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto& e : h->pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -286,7 +454,7 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     } while (0)
 
     // problem parameters, tiles
-    std::vector<Tile> tf, tc;
+    std::vector<Tile> tc;
     long long coff = 0, foff = 0;
     for (int p = 0; p < nprob; ++p) {
         const gks_problem& q = probs[p];
@@ -308,7 +476,6 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
         for (int k = 0; k < 4; ++k) P.bc[k] = (dim == 1 && k >= 2) ? 0 : q.bc[k];
         h->hp.push_back(P);
         if (dim == 1) {
-            for (int s = 0; s <= q.nx; s += gks::kBlock1D) tf.push_back(Tile{p, s});
             for (int s = 0; s < q.nx; s += gks::kBlock1D) tc.push_back(Tile{p, s});
             coff += q.nx;
             foff += q.nx + 1;
@@ -327,20 +494,43 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
         return 0;
     })());
     const long long N = h->Ntot;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            h->ncu = ncu;
+    }
+    if (const char* g = getenv("GKS_GRAPH")) h->use_graph = atoi(g) != 0;
+    TRY(([&]() -> int {
+        HIP_TRY(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIP_TRY(h, dalloc(&h->ctr, 2));
+        HIP_TRY(h, hipMemset(h->ctr, 0, 2 * sizeof(unsigned)));
+        return 0;
+    })());
     if (dim == 1) {
-        h->nTilesF = (int)tf.size();
+        const int blks[3] = {64, 128, 256};
+        for (int b = 0; b < 3; ++b) {
+            std::vector<Tile> items;
+            for (int p = 0; p < nprob; ++p)
+                for (int s = 0; s < probs[p].nx; s += blks[b] - 1) items.push_back(Tile{p, s});
+            h->nItems[b] = (int)items.size();
+            TRY(([&]() -> int {
+                HIP_TRY(h, dalloc(&h->dItems[b], items.size()));
+                HIP_TRY(h, hipMemcpy(h->dItems[b], items.data(), sizeof(Tile) * items.size(), hipMemcpyHostToDevice));
+                return 0;
+            })());
+        }
+    } else {
+        h->tuned = true;
+    }
+    if (dim == 1) {
         h->nTilesC = (int)tc.size();
         TRY(([&]() -> int {
-            HIP_TRY(h, dalloc(&h->dTilesF, tf.size()));
             HIP_TRY(h, dalloc(&h->dTilesC, tc.size()));
-            HIP_TRY(h, hipMemcpy(h->dTilesF, tf.data(), sizeof(Tile) * tf.size(), hipMemcpyHostToDevice));
             HIP_TRY(h, hipMemcpy(h->dTilesC, tc.data(), sizeof(Tile) * tc.size(), hipMemcpyHostToDevice));
             HIP_TRY(h, dalloc(&h->W, 2 * 3 * N));
             HIP_TRY(h, dalloc(&h->Wx, 2 * 3 * N));
             HIP_TRY(h, dalloc(&h->PW, 3 * N));
-            HIP_TRY(h, dalloc(&h->FL, 3 * h->F));
-            HIP_TRY(h, dalloc(&h->FdL, 3 * h->F));
-            HIP_TRY(h, dalloc(&h->Wfs, 3 * h->F));
             HIP_TRY(h, dalloc(&h->Pf, 3 * h->F));
             return 0;
         })());
@@ -392,7 +582,7 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     else
         gks::signal2d_kernel<<<dim3((probs[0].nx + 63) / 64, (probs[0].ny + 3) / 4), dim3(64, 4), 0, h->stream>>>(
             h->dP, h->dS, h->W);
-    gks::finish_kernel<<<(nprob + 63) / 64, 64, 0, h->stream>>>(h->dP, h->dS, nprob, 0);
+    gks::finish_kernel<<<(nprob + 63) / 64, 64, 0, h->stream>>>(h->dP, h->dS, nprob, 0, h->ctr);
     std::vector<ProbState> s(nprob);
     TRY(([&]() -> int {
         HIP_TRY(h, hipGetLastError());
@@ -432,14 +622,18 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
     if (max_steps < 0) return fail(h, GKS_EINVAL, "max_steps < 0");
     std::vector<ProbState> before(h->nprob), after(h->nprob);
     HIP_TRY(h, hipMemcpyAsync(before.data(), h->dS, sizeof(ProbState) * h->nprob, hipMemcpyDeviceToHost, h->stream));
+    if (!h->tuned && max_steps > 0) {
+        const int st = autotune(h);
+        if (st) return st;
+    }
+    const bool graph = h->use_graph && !h->timing && max_steps > 0;
+    if (graph && !h->gexec) {
+        const int st = build_graph(h);
+        if (st) return st;
+    }
     for (int s = 0; s < max_steps; ++s) {
-        if (h->dim == 1) {
-            if (h->precision == GKS_PREC_FP64) launch_step_1d<double>(h);
-            else launch_step_1d<float>(h);
-        } else {
-            if (h->precision == GKS_PREC_FP64) launch_step_2d<double>(h);
-            else launch_step_2d<float>(h);
-        }
+        if (graph) HIP_TRY(h, hipGraphLaunch(h->gexec, h->stream));
+        else launch_step(h, h->stream);
     }
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipMemcpyAsync(after.data(), h->dS, sizeof(ProbState) * h->nprob, hipMemcpyDeviceToHost, h->stream));
@@ -545,6 +739,24 @@ int gks_kernel_time(gks_handle* h, int32_t kernel_id, double* total_ms, int64_t*
     if (total_ms) *total_ms = h->tot_ms[kernel_id];
     if (launches) *launches = h->launches[kernel_id];
     return GKS_OK;
+}
+
+const char* gks_launch_config(const gks_handle* hc)
+{
+    if (!hc) return "";
+    gks_handle* h = const_cast<gks_handle*>(hc);
+    if (h->dim == 2) {
+        h->cfg_text = "2-D: fixed tiles (face rows 64x4, Gauss points 64x2, cells 64x4)";
+    } else if (!h->tuned) {
+        h->cfg_text = "1-D: not tuned yet (tunes on the first gks_step)";
+    } else {
+        const int n = h->nItems[h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2)];
+        char buf[128];
+        snprintf(buf, sizeof buf, "; blk %d gmul %d: %d workgroups for %d work items", h->blk, h->gmul,
+                 h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu), n);
+        h->cfg_text = h->tune_note + buf;
+    }
+    return h->cfg_text.c_str();
 }
 
 int gks_cell_updates(const gks_handle* h, int64_t* count)

@@ -7,7 +7,8 @@
 //     receives W* and then W^{n+1} (the step commits by flipping `cur`, so a
 //     failing step leaves W^n untouched).
 //   2-D (one problem): W[buf][4][ny][nx], Wx, Wy alike.
-//   Face arrays: 1-D [3][F] with F = sum_p (nx_p + 1); 2-D x faces
+//   Face arrays: 1-D [3][F] with F = sum_p (nx_p + 1) (the MSMD partial of
+//     the face values only; fluxes stay in LDS); 2-D x faces
 //     [4][ny][nx+1], y faces [4][ny+1][nx]; face-row reconstructions
 //     [28][rows][faces].
 // Ghost cells are never stored: stencil gathers map indices through the
@@ -61,6 +62,21 @@ __device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi, boo
     }
     return c;
 }
+
+// Two-stage MSMD combinations (Sec. 2.2) with the fused multiply-adds
+// written out (the rounding does not depend on how a kernel is compiled):
+//   msmd_half: a + dt/2 b + dt^2/8 c   (intermediate state / face value)
+//   msmd_pred: a + dt b + dt^2/6 c     (first part of the full step)
+//   msmd_corr: a + dt^2/3 c            (second-stage completion)
+__device__ __forceinline__ double msmd_half(double a, double b, double c, double dt)
+{
+    return __builtin_fma(0.125 * dt * dt, c, __builtin_fma(0.5 * dt, b, a));
+}
+__device__ __forceinline__ double msmd_pred(double a, double b, double c, double dt)
+{
+    return __builtin_fma(dt * dt / 6.0, c, __builtin_fma(dt, b, a));
+}
+__device__ __forceinline__ double msmd_corr(double a, double c, double dt) { return __builtin_fma(dt * dt / 3.0, c, a); }
 
 __device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
@@ -185,131 +201,137 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
 }
 
 // ---------------------------------------------------------------------------
-// 1-D interface kernel: one thread per face.
-//   STAGE 1: writes FL, FdL, Wfs = S0 + dt/2 S1 + dt^2/8 S2 (interface value
-//            at t*), Pf = S0 + dt S1 + dt^2/6 S2 (MSMD partial)
-//   STAGE 2: writes FdL and Wfs = Pf + dt^2/3 S2* (interface value at t^{n+1})
+// Batched 1-D: one launch per MSMD stage for all problems.  A work item is
+// a tile of BLK-1 cells of one problem; the workgroup computes the BLK faces
+// bounding it (the last face of a tile is also the first face of the next
+// and is computed by both, bit-identically), keeps the face results in LDS
+// and updates its cells.  Workgroups take items from a device counter until
+// the list is exhausted, so the same kernel runs persistent (a few
+// workgroups per CU) or as a plain grid (one workgroup per item); every
+// workgroup reaches the exit.  ctr[STAGE-1] is reset by finish_kernel at the
+// end of the step.  Faces owned by the tile (all but its last face, plus the
+// problem's last face) carry the MSMD partial Pf from stage 1 to stage 2.
 // ---------------------------------------------------------------------------
-template <typename T, int STAGE>
-__global__ void __launch_bounds__(kBlock1D) face1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
-                                                          const Tile* __restrict__ tiles, const double* __restrict__ W,
-                                                          const double* __restrict__ Wx, long long Ntot, long long F,
-                                                          double* __restrict__ FL, double* __restrict__ FdL,
-                                                          double* __restrict__ Wfs, double* __restrict__ Pf)
+template <typename T, int STAGE, int BLK>
+__global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                      const Tile* __restrict__ items, int nitems,
+                                                      unsigned* __restrict__ ctr, double* __restrict__ W,
+                                                      double* __restrict__ Wx, double* __restrict__ PW,
+                                                      double* __restrict__ Pf, long long Ntot, long long F)
 {
-    const Tile tl = tiles[blockIdx.x];
-    const ProbParam& P = PP[tl.p];
-    ProbState& S = PS[tl.p];
-    if (!S.active) return;
-    const int f = tl.start + threadIdx.x;
-    if (f > P.nx) return;
-    const int buf = (STAGE == 1) ? S.cur : 1 - S.cur;
-    const double dt = S.dt;
-    const double* Wb = W + (size_t)buf * 3 * Ntot + P.coff;
-    const double* Xb = Wx + (size_t)buf * 3 * Ntot + P.coff;
-    double Wk[4][4], Dk[4][4];
+    __shared__ double sh_FL[3][BLK], sh_FdL[3][BLK], sh_Wf[3][BLK];
+    __shared__ int sh_item;
+    const int t = threadIdx.x;
+    for (;;) {
+        if (t == 0) sh_item = (int)atomicAdd(&ctr[STAGE - 1], 1u);
+        __syncthreads();
+        const int it = sh_item;
+        __syncthreads();
+        if (it >= nitems) break;
+        const Tile tl = items[it];
+        const ProbParam& P = PP[tl.p];
+        ProbState& S = PS[tl.p];
+        if (!S.active) continue; // uniform over the workgroup
+        const int cur = S.cur, nxt = 1 - cur;
+        const double dt = S.dt;
+        // ---- faces c0 .. c0 + BLK - 1
+        const int f = tl.start + t;
+        if (f <= P.nx) {
+            const int buf = (STAGE == 1) ? cur : nxt;
+            const double* Wb = W + (size_t)buf * 3 * Ntot + P.coff;
+            const double* Xb = Wx + (size_t)buf * 3 * Ntot + P.coff;
+            double Wk[4][4], Dk[4][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        bool zero;
-        const int c = map_index(f - 2 + q, P.nx, P.bc[0], P.bc[1], zero);
-        Wk[q][0] = Wb[c];
-        Wk[q][1] = Wb[Ntot + c];
-        Wk[q][2] = 0.0;
-        Wk[q][3] = Wb[2 * Ntot + c];
-        Dk[q][0] = zero ? 0.0 : P.dx * Xb[c];
-        Dk[q][1] = zero ? 0.0 : P.dx * Xb[Ntot + c];
-        Dk[q][2] = 0.0;
-        Dk[q][3] = zero ? 0.0 : P.dx * Xb[2 * Ntot + c];
-    }
-    double o[7][4];
-    auto put = [&](int q, int k, double v) { o[q][k] = v; };
-    bool ok = (P.order == 8) ? face_recon<T, 1, 8>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
-                             : face_recon<T, 1, 6>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put);
-    PointIn<T> in;
-    PointOut<double> out;
-    NonEq<double, 1, T> ne;
-    if (ok) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            in.W0x[k] = T(o[1][k]); in.W0xx[k] = T(o[2][k]);
-            in.W0y[k] = in.W0xy[k] = in.W0yy[k] = T(0);
-            in.Wlx[k] = T(o[5][k]); in.Wrx[k] = T(o[6][k]);
-            in.Wly[k] = in.Wry[k] = T(0);
-        }
-        ok = noneq_states<double, 1, T>(o[3], o[4], P.gamma, P.K, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
-    }
-    if (ok) {
-        const PointPar par{P.gamma, P.K, P.mu, dt};
-        // equilibrium value: kinetic average of the WENO-Z states, or the linear value
-        ok = gks_point<T, 1>(par, in, P.recon ? ne.Xs : o[0], ne, out);
-    }
-    if (!ok) {
-        S.err = 1;
-        return;
-    }
-    const long long g = P.foff + f;
-    const int slot[3] = {0, 1, 3};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int s = slot[k];
-        if (STAGE == 1) {
-            FL[k * F + g] = out.FL[s];
-            FdL[k * F + g] = out.FdL[s];
-            const double s0 = out.S0[s], s1 = out.S1[s], s2 = out.S2[s];
-            Wfs[k * F + g] = s0 + 0.5 * dt * s1 + 0.125 * dt * dt * s2;
-            Pf[k * F + g] = s0 + dt * s1 + dt * dt / 6.0 * s2;
-        } else {
-            FdL[k * F + g] = out.FdL[s];
-            Wfs[k * F + g] = Pf[k * F + g] + dt * dt / 3.0 * out.S2[s];
-        }
-    }
-}
-
-// 1-D cell update, one thread per cell.
-template <int STAGE>
-__global__ void __launch_bounds__(kBlock1D) cell1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
-                                                          const Tile* __restrict__ tiles, double* __restrict__ W,
-                                                          double* __restrict__ Wx, double* __restrict__ PW, long long Ntot,
-                                                          long long F, const double* __restrict__ FL,
-                                                          const double* __restrict__ FdL, const double* __restrict__ Wfs)
-{
-    const Tile tl = tiles[blockIdx.x];
-    const ProbParam& P = PP[tl.p];
-    ProbState& S = PS[tl.p];
-    if (!S.active) return; // block-uniform
-    const int i = tl.start + threadIdx.x;
-    const bool live = i < P.nx;
-    const int cur = S.cur, nxt = 1 - cur;
-    const double dt = S.dt, idx = 1.0 / P.dx;
-    const long long c = P.coff + (live ? i : 0);
-    const long long f = P.foff + (live ? i : 0);
-    double wn[3];
-    if (live) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double dL = -(FdL[k * F + f + 1] - FdL[k * F + f]) * idx;
-            const double slope = (Wfs[k * F + f + 1] - Wfs[k * F + f]) * idx;
-            if (STAGE == 1) {
-                const double L = -(FL[k * F + f + 1] - FL[k * F + f]) * idx;
-                const double w = W[((size_t)cur * 3 + k) * Ntot + c];
-                W[((size_t)nxt * 3 + k) * Ntot + c] = w + 0.5 * dt * L + 0.125 * dt * dt * dL;
-                PW[k * Ntot + c] = w + dt * L + dt * dt / 6.0 * dL;
-            } else {
-                wn[k] = PW[k * Ntot + c] + dt * dt / 3.0 * dL;
-                W[((size_t)nxt * 3 + k) * Ntot + c] = wn[k];
+            for (int q = 0; q < 4; ++q) {
+                bool zero;
+                const int c = map_index(f - 2 + q, P.nx, P.bc[0], P.bc[1], zero);
+                Wk[q][0] = Wb[c];
+                Wk[q][1] = Wb[Ntot + c];
+                Wk[q][2] = 0.0;
+                Wk[q][3] = Wb[2 * Ntot + c];
+                Dk[q][0] = zero ? 0.0 : P.dx * Xb[c];
+                Dk[q][1] = zero ? 0.0 : P.dx * Xb[Ntot + c];
+                Dk[q][2] = 0.0;
+                Dk[q][3] = zero ? 0.0 : P.dx * Xb[2 * Ntot + c];
             }
-            Wx[((size_t)nxt * 3 + k) * Ntot + c] = slope;
+            double o[7][4];
+            auto put = [&](int q, int k, double v) { o[q][k] = v; };
+            bool ok = (P.order == 8) ? face_recon<T, 1, 8>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
+                                     : face_recon<T, 1, 6>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put);
+            PointIn<T> in;
+            PointOut<double> out;
+            NonEq<double, 1, T> ne;
+            if (ok) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    in.W0x[k] = T(o[1][k]); in.W0xx[k] = T(o[2][k]);
+                    in.W0y[k] = in.W0xy[k] = in.W0yy[k] = T(0);
+                    in.Wlx[k] = T(o[5][k]); in.Wrx[k] = T(o[6][k]);
+                    in.Wly[k] = in.Wry[k] = T(0);
+                }
+                ok = noneq_states<double, 1, T>(o[3], o[4], P.gamma, P.K, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+            }
+            if (ok) {
+                const PointPar par{P.gamma, P.K, P.mu, dt};
+                ok = gks_point<T, 1>(par, in, P.recon ? ne.Xs : o[0], ne, out);
+            }
+            if (!ok) {
+                S.err = 1;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = 0.0;
+            }
+            const bool own = (t < BLK - 1) || (f == P.nx);
+            const long long g = P.foff + f;
+            const int slot[3] = {0, 1, 3};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int sl = slot[k];
+                sh_FdL[k][t] = out.FdL[sl];
+                if (STAGE == 1) {
+                    const double s0 = out.S0[sl], s1 = out.S1[sl], s2 = out.S2[sl];
+                    sh_FL[k][t] = out.FL[sl];
+                    sh_Wf[k][t] = msmd_half(s0, s1, s2, dt);
+                    if (own) Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
+                } else {
+                    sh_Wf[k][t] = msmd_corr(Pf[k * F + g], out.S2[sl], dt);
+                }
+            }
         }
-    }
-    if (STAGE == 2) {
-        double s = 0.0;
+        __syncthreads();
+        // ---- cells c0 .. c0 + BLK - 2
+        const int i = tl.start + t;
+        const bool live = (t < BLK - 1) && (i < P.nx);
+        const double idx = 1.0 / P.dx;
+        double wn[3] = {0.0, 0.0, 0.0};
         if (live) {
-            const double rho = wn[0], U = wn[1] / rho;
-            const double p = (P.gamma - 1.0) * (wn[2] - 0.5 * rho * U * U);
-            if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
-            else s = (fabs(U) + sqrt(P.gamma * p / rho)) * idx;
+            const long long c = P.coff + i;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double dL = -(sh_FdL[k][t + 1] - sh_FdL[k][t]) * idx;
+                const double slope = (sh_Wf[k][t + 1] - sh_Wf[k][t]) * idx;
+                if (STAGE == 1) {
+                    const double L = -(sh_FL[k][t + 1] - sh_FL[k][t]) * idx;
+                    const double w = W[((size_t)cur * 3 + k) * Ntot + c];
+                    W[((size_t)nxt * 3 + k) * Ntot + c] = msmd_half(w, L, dL, dt);
+                    PW[k * Ntot + c] = msmd_pred(w, L, dL, dt);
+                } else {
+                    wn[k] = msmd_corr(PW[k * Ntot + c], dL, dt);
+                    W[((size_t)nxt * 3 + k) * Ntot + c] = wn[k];
+                }
+                Wx[((size_t)nxt * 3 + k) * Ntot + c] = slope;
+            }
         }
-        block_max_atomic(s, &S.smax);
+        if (STAGE == 2) {
+            double sp = 0.0;
+            if (live) {
+                const double rho = wn[0], U = wn[1] / rho;
+                const double p = (P.gamma - 1.0) * (wn[2] - 0.5 * rho * U * U);
+                if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
+                else sp = (fabs(U) + sqrt(P.gamma * p / rho)) * idx;
+            }
+            block_max_atomic(sp, &S.smax);
+        }
+        __syncthreads(); // LDS reuse by the next item
     }
 }
 
@@ -340,9 +362,11 @@ __global__ void __launch_bounds__(kBlock1D) signal1d_kernel(const ProbParam* __r
 //               after an error, the problem stops with W^n kept.
 //   Then the next dt follows from the maximum signal speed of the state.
 // ---------------------------------------------------------------------------
-__global__ void finish_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob, int commit)
+__global__ void finish_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob, int commit,
+                              unsigned* __restrict__ ctr)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ctr && p < 2) ctr[p] = 0u; // work counters of the persistent stage kernels
     if (p >= nprob) return;
     const ProbParam& P = PP[p];
     ProbState& S = PS[p];
@@ -589,11 +613,11 @@ __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__
         if (STAGE == 1) {
             FL[o] = acc[0][k];
             FdL[o] = acc[1][k];
-            Wfs[o] = acc[2][k] + 0.5 * dt * acc[3][k] + 0.125 * dt * dt * acc[4][k];
-            Pf[o] = acc[2][k] + dt * acc[3][k] + dt * dt / 6.0 * acc[4][k];
+            Wfs[o] = msmd_half(acc[2][k], acc[3][k], acc[4][k], dt);
+            Pf[o] = msmd_pred(acc[2][k], acc[3][k], acc[4][k], dt);
         } else {
             FdL[o] = acc[1][k];
-            Wfs[o] = Pf[o] + dt * dt / 3.0 * acc[4][k];
+            Wfs[o] = msmd_corr(Pf[o], acc[4][k], dt);
         }
     }
 }
@@ -632,10 +656,10 @@ __global__ void __launch_bounds__(256) cell2d_kernel(const ProbParam* __restrict
                 const double L = -(FLx[k * nfx + fx + 1] - FLx[k * nfx + fx]) * idx -
                                  (FLy[k * nfy + fy + nx] - FLy[k * nfy + fy]) * idy;
                 const double w = W[((size_t)cur * 4 + k) * plane + c];
-                W[((size_t)nxt * 4 + k) * plane + c] = w + 0.5 * dt * L + 0.125 * dt * dt * dL;
-                PW[k * plane + c] = w + dt * L + dt * dt / 6.0 * dL;
+                W[((size_t)nxt * 4 + k) * plane + c] = msmd_half(w, L, dL, dt);
+                PW[k * plane + c] = msmd_pred(w, L, dL, dt);
             } else {
-                wn[k] = PW[k * plane + c] + dt * dt / 3.0 * dL;
+                wn[k] = msmd_corr(PW[k * plane + c], dL, dt);
                 W[((size_t)nxt * 4 + k) * plane + c] = wn[k];
             }
             Wx[((size_t)nxt * 4 + k) * plane + c] = (Wfx[k * nfx + fx + 1] - Wfx[k * nfx + fx]) * idx;

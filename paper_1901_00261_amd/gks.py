@@ -57,12 +57,15 @@ def lib():
         L.gks_kernel_timing.argtypes = [hnd, C.c_int32]
         L.gks_kernel_time.argtypes = [hnd, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.gks_cell_updates.argtypes = [hnd, C.POINTER(C.c_int64)]
+        L.gks_launch_config.argtypes = [hnd]
+        L.gks_launch_config.restype = C.c_char_p
         _lib = L
     return _lib
 
 
 EXPORTED = ("gks_init", "gks_init_device", "gks_step", "gks_state", "gks_state_device", "gks_problem_status",
-            "gks_free", "gks_last_error", "gks_kernel_timing", "gks_kernel_time", "gks_cell_updates")
+            "gks_free", "gks_last_error", "gks_kernel_timing", "gks_kernel_time", "gks_cell_updates",
+            "gks_launch_config")
 
 
 def to_struct(p) -> gks_problem:
@@ -158,6 +161,9 @@ class Solver:
         c = C.c_int64(0)
         self._check(lib().gks_cell_updates(self.h, C.byref(c)))
         return c.value
+
+    def launch_config(self):
+        return lib().gks_launch_config(self.h).decode()
 
     def close(self):
         if getattr(self, "h", None):

@@ -1,0 +1,143 @@
+"""Batched 1-D path: launch configurations, graph replay, autotuner (GPU).
+
+Every launch configuration (tile of 64/128/256 threads, persistent grid of
+GMUL workgroups per CU or one workgroup per work item) runs the same
+per-face and per-cell arithmetic, so all must agree bit for bit; the batch
+must also match the oracle problem by problem.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_00261_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def gks():
+    from paper_1901_00261_amd import gks as g
+    return g
+
+
+def run(probs, steps=None, tune=None, graph=None, precision=0):
+    g = gks()
+    old = {k: os.environ.get(k) for k in ("GKS_TUNE", "GKS_GRAPH")}
+    try:
+        for k, v in (("GKS_TUNE", tune), ("GKS_GRAPH", graph)):
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        S = g.Solver(probs, precision)
+        if steps is None:
+            while S.step(1000) > 0:
+                pass
+        else:
+            S.step(steps)
+        cfg = S.launch_config()
+        out = [S.state(p) for p in range(len(probs))]
+        S.close()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return out, cfg
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return wl.batch_1d(count=12, seed=7, nmin=40, nmax=700, t_end=0.05)
+
+
+@pytest.mark.parametrize("tune", ["64:0", "64:1", "128:2", "256:0", "256:4"])
+def test_launch_modes_bit_identical(batch, tune):
+    ref, _ = run(batch, tune="128:0", graph="0")
+    got, cfg = run(batch, tune=tune)
+    assert cfg.startswith("forced")
+    for a, b in zip(ref, got):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]
+
+
+@pytest.mark.parametrize("tune", ["64:1", "256:0"])
+def test_launch_modes_bit_identical_mixed(batch, tune):
+    ref, _ = run(batch, tune="128:0", graph="0", precision=1)
+    got, _ = run(batch, tune=tune, precision=1)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4]
+
+
+def test_bad_tune_string_is_rejected(batch):
+    g = gks()
+    os.environ["GKS_TUNE"] = "persistent"
+    try:
+        S = g.Solver(batch[:2])
+        with pytest.raises(g.GksError) as e:
+            S.step(1)
+        assert e.value.code == g.GKS_EINVAL and "GKS_TUNE" in str(e.value)
+        S.close()
+    finally:
+        os.environ.pop("GKS_TUNE")
+
+
+def test_batch_matches_oracle(batch):
+    got, cfg = run(batch)
+    print("autotuned:", cfg)
+    for p, g in zip(batch, got):
+        want = oracle.run(1, p.W, p.Wx, **p.oracle_kwargs())
+        err = np.abs(g[0] - want[0]).max() / np.abs(want[0]).max()
+        assert g[4] == want[4] and err < 1e-10, (p.nx, err)
+
+
+def test_graph_replays_match_eager_with_host_reads(batch):
+    g = gks()
+    os.environ["GKS_TUNE"] = "128:2"
+    try:
+        os.environ["GKS_GRAPH"] = "1"
+        A = g.Solver(batch)
+        os.environ["GKS_GRAPH"] = "0"
+        B = g.Solver(batch)
+    finally:
+        os.environ.pop("GKS_GRAPH", None)
+        os.environ.pop("GKS_TUNE", None)
+    for rep in range(6):
+        A.step(3)
+        B.step(3)
+        for p in (0, 5, 11):  # host reads between replays
+            a, b = A.state(p), B.state(p)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4], (rep, p)
+    A.close()
+    B.close()
+
+
+def test_tune_cache_round_trip(tmp_path, batch):
+    cache = tmp_path / "tune.txt"
+    os.environ["GKS_TUNE_CACHE"] = str(cache)
+    try:
+        _, cfg1 = run(batch[:4], steps=2)
+        assert cfg1.startswith("tuned") and cache.exists()
+        _, cfg2 = run(batch[:4], steps=2)
+        assert cfg2.startswith("cache")
+    finally:
+        os.environ.pop("GKS_TUNE_CACHE", None)
+
+
+def test_2d_graph_matches_eager():
+    p = wl.isentropic_vortex_2d(24, ny=20, mu=1e-3, acoustic_amp=1e-2)
+    g = gks()
+    os.environ["GKS_GRAPH"] = "0"
+    try:
+        B = g.Solver(p)
+    finally:
+        os.environ.pop("GKS_GRAPH")
+    A = g.Solver(p)
+    for rep in range(3):
+        A.step(2)
+        B.step(2)
+        a, b = A.state(0), B.state(0)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    A.close()
+    B.close()
