@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the compact 8th-order gas-kinetic scheme on one MI355X.
 
-A step is one two-stage MSMD step of the whole hot path (reconstruction,
-WENO-Z, interface distribution at every Gauss point of every face, MSMD
-update of averages and gradients) over the 2-D Navier-Stokes workload:
-isentropic vortex (strength 5) plus a seeded random-phase acoustic
-perturbation (amplitude 1e-3, wavenumbers 1..32), mu = 1e-4, periodic
-[0, 10]^2, 1024 x 1024 cells, CFL 0.3.  Inputs are synthetic and resident in
-HBM before the timed region.  Prints one JSON line.
+Default line: a step is one two-stage MSMD step of the whole hot path
+(face-row reconstruction with WENO-Z, tangential reconstruction and the
+interface distribution at every Gauss point of every face, MSMD update of
+averages and gradients) over the 2-D Navier-Stokes workload: isentropic
+vortex (strength 5) plus a seeded random-phase acoustic perturbation
+(amplitude 1e-3, wavenumbers 1..32), mu = 1e-4, periodic [0, 10]^2,
+1024 x 1024 cells, CFL 0.3.  FP64 gives `value`; the FP32-mixed form is
+timed on the same input and reported beside it.  Inputs are synthetic and
+resident in HBM before the timed region.  Prints one JSON line.
+
+Other modes (reports, not the headline line):
+  --workload batch1d    256 uneven 1-D Riemann problems run to t = 0.14
+  --workload riemann2d  2-D four-quadrant Euler Riemann problem, 4096^2
+  --study equal-l1      L1(rho) and throughput of both precisions over
+                        N = 128..1024 against an FP64 2048^2 reference
 """
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -20,17 +30,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s per MSMD step, 2D 8th-order GKS: FP32-mixed vs FP64 at equal L1"
-FP64_VALU_PEAK = 78.6  # TFLOP/s, MI355X vector FP64
+# MI355X vector peaks: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6
+# TFLOP/s for FP64 and unpacked FP32; 157.3 TFLOP/s is the packed-FP32 peak.
+FP64_VALU_PEAK = 78.6
 FP32_VALU_PEAK = 157.3
+HBM_PEAK = 8000.0  # GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gp2d_hbm_traffic_vortex1024.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1901_00261_amd", "csrc", f)
+                  for f in ("gks_math.h", "gks_kernels.h", "gks_api.hip")]
 
 
 def parse():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=1024, help="cells per direction")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--n", type=int, default=0, help="cells per direction (2-D workloads)")
+    ap.add_argument("--workload", choices=["vortex2d", "batch1d", "riemann2d"], default="vortex2d")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--study", choices=["none", "equal-l1"], default="none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=400, help="oracle sample: window edge in cells, one step")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -38,9 +56,95 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the interface kernel from the committed
+    rocprofv3 counter summary, or None when the kernel sources changed
+    since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_FILE).read(), flags=re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d
+
+
+def vortex(n):
+    from paper_1901_00261_amd import workloads as wl
+    return wl.isentropic_vortex_2d(n, mu=1e-4, eps=5.0, acoustic_amp=1e-3, nmodes=32, seed=3,
+                                   order=8, recon=1, cfl=0.3, t_end=1e9)
+
+
+def device_solver(prob, prec):
+    """Inputs moved to HBM as torch tensors and handed to the library by
+    device pointer; the library runs on torch's current stream."""
+    import numpy as np
+    import torch
+    from paper_1901_00261_amd import gks
+    dev = torch.device("cuda:0")
+    ts = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (prob.W, prob.Wx, prob.Wy)]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream().cuda_stream
+    S = gks.Solver(prob, prec, stream=stream, device_arrays=[tuple(t.data_ptr() for t in ts)])
+    torch.cuda.synchronize()
+    del ts
+    return S
+
+
+def time_2d(prob, prec, steps, warmup):
+    """Warm-up, then `steps` MSMD steps timed end to end with HIP events on
+    every kernel launch (on the library's stream, torch's current stream)."""
+    import numpy as np
+    import torch
+    from paper_1901_00261_amd import gks
+    S = device_solver(prob, prec)
+    if warmup:
+        S.step(warmup)
+    t_before = S.state(0)[3]
+    S.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    W, _, _, t_after, nsteps = S.state(0)
+    k = {name: S.kernel_time(kid) for name, kid in
+         (("interface", gks.KERNEL_FLUX), ("face_row", gks.KERNEL_ROW), ("cell_update", gks.KERNEL_CELL))}
+    S.close()
+    ok = bool(np.isfinite(W).all()) and nsteps == warmup + steps and t_after > t_before
+    return {"elapsed": el, "kernels": k, "ok": ok, "t_before": t_before, "t_after": t_after}
+
+
+def roofline_2d(prob, res, ops, prec):
+    """Interface (Gauss-point) kernel: algorithmic flops per launch = face
+    rows per launch x 3 Gauss points x flops per Gauss point (stage 1 and
+    stage 2 launches alternate, so the mean of the two stage counts)."""
+    key = "gauss_point_ns" if prob.mu > 0 else "gauss_point_euler"
+    fpg = 0.5 * (ops[key]["flops"] + ops[key + "_s2"]["flops"])
+    rows = ((prob.nx + 1) * prob.ny + (prob.ny + 1) * prob.nx) / 2.0
+    flops = rows * 3 * fpg
+    ms, n = res["kernels"]["interface"]
+    avg_s = ms / max(n, 1) / 1e3
+    achieved = flops / avg_s / 1e12
+    peak = FP64_VALU_PEAK if prec == 0 else FP32_VALU_PEAK
+    out = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+           "traffic": None, "kernel": "gp2d_kernel (interface, Gauss points)", "avg_launch_ms": avg_s * 1e3,
+           "launches": n, "flops_per_launch": flops, "flops_per_gauss_point": fpg}
+    return out
+
+
 def cpu_baseline(prob, dt, window):
     """The oracle advancing a window of the same initial data (extrapolated
-    edges) by one MSMD step with the GPU's first dt."""
+    edges) by one MSMD step with the GPU's dt."""
     import numpy as np
     import oracle
 
@@ -57,7 +161,206 @@ def cpu_baseline(prob, dt, window):
     el = time.perf_counter() - t0
     return {"value": w * w / el, "unit": "cell-updates/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"one MSMD step on the central {w}x{w} window of the same {n}x{n} initial data "
-                      f"(extrapolated window edges, dt of the first GPU step), {el:.1f} s"}
+                      f"(extrapolated window edges, dt of the GPU steps), {el:.1f} s"}
+
+
+def load_ops():
+    return json.load(open(os.path.join(ROOT, "paper_1901_00261_amd", "opcount.json")))
+
+
+def bench_vortex(args):
+    n = args.n or 1024
+    prob = vortex(n)
+    ops = load_ops()
+    precs = {"fp64": [0], "mixed": [1], "both": [0, 1]}[args.precision]
+    results = {p: time_2d(prob, p, args.steps, args.warmup) for p in precs}
+    main_p = precs[0]
+    res = results[main_p]
+    cells = prob.nx * prob.ny
+    value = cells * args.steps / res["elapsed"]
+    roof = roofline_2d(prob, res, ops, main_p)
+    traffic = measured_traffic() if main_p == 0 and n == 1024 else None
+    if traffic:
+        roof["traffic"] = traffic["bytes_per_launch"]
+        roof["traffic_hbm_GBps"] = traffic["bytes_per_launch"] / (roof["avg_launch_ms"] / 1e3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["elapsed"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_p == 0 else "f32+f64acc",
+        "data": "synthetic",
+        "config": {"workload": f"2-D Navier-Stokes isentropic vortex (strength 5) + seeded acoustic perturbation "
+                               f"(1e-3, k=1..32), {prob.nx}x{prob.ny} periodic on [0,10]^2, 8th-order compact "
+                               f"WENO-Z GKS, mu=1e-4, CFL 0.3",
+                   "nx": prob.nx, "ny": prob.ny, "precision": "fp64" if main_p == 0 else "mixed",
+                   "t_reached": res["t_after"],
+                   "kernel_ms_per_step": {k: v[0] / args.steps for k, v in res["kernels"].items()}},
+        "roofline": roof,
+    }
+    if 1 in results and main_p == 0:
+        rm = results[1]
+        line["config"]["mixed"] = {
+            "value": cells * args.steps / rm["elapsed"], "ms_per_step": rm["elapsed"] / args.steps * 1e3,
+            "kernel_ms_per_step": {k: v[0] / args.steps for k, v in rm["kernels"].items()},
+            "roofline": roofline_2d(prob, rm, ops, 1)}
+    if not all(r["ok"] for r in results.values()):
+        line["error"] = "non-finite state or missing steps"
+    if not args.no_cpu_baseline:
+        dt0 = (res["t_after"] - res["t_before"]) / args.steps
+        line["cpu_baseline"] = cpu_baseline(prob, dt0, args.cpu_window)
+    return line
+
+
+def bench_riemann2d(args):
+    from paper_1901_00261_amd import workloads as wl
+    n = args.n or 4096
+    prob = wl.riemann_2d(n, seed=5, order=8, recon=1, cfl=0.3)
+    ops = load_ops()
+    precs = {"fp64": [0], "mixed": [1], "both": [0, 1]}[args.precision]
+    out = {"workload": f"2-D Euler four-quadrant Riemann problem, {n}x{n} on [0,1]^2, seeded quadrant states "
+                       f"(seed 5), 8th-order compact WENO-Z, CFL 0.3, extrapolated boundaries",
+           "steps": args.steps, "warmup": args.warmup, "unit": "cell-updates/s"}
+    for p in precs:
+        r = time_2d(prob, p, args.steps, args.warmup)
+        out["fp64" if p == 0 else "mixed"] = {
+            "value": n * n * args.steps / r["elapsed"], "ms_per_step": r["elapsed"] / args.steps * 1e3, "ok": r["ok"],
+            "t_reached": r["t_after"], "kernel_ms_per_step": {k: v[0] / args.steps for k, v in r["kernels"].items()},
+            "roofline": roofline_2d(prob, r, ops, p)}
+    return out
+
+
+def bench_batch1d(args):
+    """All 256 problems to t = 0.14 (graph-replayed steps, autotuned launch);
+    value = sum over problems of cells x steps / wall time.  A second run
+    with kernel events gives the stage-kernel durations."""
+    import numpy as np
+    import torch
+    from paper_1901_00261_amd import gks
+    from paper_1901_00261_amd import workloads as wl
+    probs = wl.batch_1d()
+    ops = load_ops()
+    precs = {"fp64": [0], "mixed": [1], "both": [0, 1]}[args.precision]
+    out = {"workload": "batched 1-D Euler Riemann problems: 256 problems, N ~ U[200,4000] (seed 4), order 6 or 8, "
+                       "WENO-Z, CFL 0.3, t = 0.14, extrapolated boundaries", "unit": "cell-updates/s"}
+    for p in precs:
+        rec = {}
+        for timing in (False, True):
+            S = gks.Solver(probs, p)
+            S.step(1)  # autotune + first step (untimed)
+            if timing:
+                S.timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            upd = 0
+            steps = 0
+            while True:
+                r = S.step(100, raise_on_error=False)
+                upd += S.cell_updates()
+                steps += 100
+                if r == 0:
+                    break
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            stopped = [k for k in range(len(probs)) if S.status(k) == gks.GKS_ENONPHYS]
+            if not timing:
+                rec.update(value=upd / el, seconds=el, cell_updates=upd, launch=S.launch_config(),
+                           stopped_nonphysical=stopped)
+            else:
+                ms, nl = S.kernel_time(gks.KERNEL_FLUX)
+                # the active set shrinks as problems finish, so the figure is the
+                # mean over the run: algorithmic flops of all faces (about one per
+                # cell-update per stage) over the summed stage-kernel time
+                f1 = ops["face_1d"]["flops"] + ops["face_1d_s2"]["flops"]
+                achieved = upd * f1 / (ms / 1e3) / 1e12
+                peak = FP64_VALU_PEAK if p == 0 else FP32_VALU_PEAK
+                rec["stage_kernels"] = {"ms_total": ms, "launch_pairs": nl, "mean_pair_ms": ms / max(nl, 1),
+                                        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                                                     "unit": "TFLOP/s", "frac": achieved / peak}}
+            S.close()
+        out["fp64" if p == 0 else "mixed"] = rec
+    return out
+
+
+def study_equal_l1(args):
+    """Equal-L1 study on the vortex workload: T3 = time reached by 200 FP64
+    steps at 1024^2; reference = FP64 at 2048^2 to T3; for N = 128..1024
+    and both precisions, L1(rho) against the reference block-averaged to
+    N^2 (exact cell averages of the reference field) and the measured
+    cell-updates/s of the whole run."""
+    import numpy as np
+    import torch
+    from paper_1901_00261_amd import gks
+    from paper_1901_00261_amd import workloads as wl
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    def run_to(prob, prec, t_end=None, steps=None):
+        if t_end is not None:
+            prob.t_end = t_end
+        S = gks.Solver(prob, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if steps is not None:
+            S.step(steps)
+        else:
+            while S.step(1000) > 0:
+                pass
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        W, _, _, t, n = S.state(0)
+        S.close()
+        return W, t, n, el
+
+    base = vortex(1024)
+    _, T3, n3, _ = run_to(base, 0, steps=200)
+    log(f"T3 = {T3:.9f} after {n3} FP64 steps at 1024^2")
+    ref_prob = vortex(2048)
+    Wref, tr, nr, elr = run_to(ref_prob, 0, t_end=T3)
+    log(f"reference 2048^2: {nr} steps, t = {tr:.9f}, {elr:.2f} s")
+    rho_ref = Wref[:, :, 0]
+    rows = []
+    for N in (128, 256, 512, 1024):
+        prob = base if N == 1024 else vortex(N)
+        f = 2048 // N
+        ref_N = rho_ref.reshape(N, f, N, f).mean(axis=(1, 3))
+        for prec in (0, 1):
+            W, t, n, el = run_to(prob, prec, t_end=T3)
+            l1 = float(np.abs(W[:, :, 0] - ref_N).mean())
+            linf = float(np.abs(W[:, :, 0] - ref_N).max())
+            row = {"N": N, "precision": "fp64" if prec == 0 else "mixed", "steps": n, "t": t, "L1_rho": l1,
+                   "Linf_rho": linf, "seconds": el, "cell_updates_per_s": N * N * n / el}
+            rows.append(row)
+            log(json.dumps(row))
+    # equal-L1 pairs: FP64 grid with the same L1 (log-log interpolation in N) and its time to solution
+    f64 = [r for r in rows if r["precision"] == "fp64"]
+    pairs = []
+    for r in rows:
+        if r["precision"] != "mixed":
+            continue
+        target = r["L1_rho"]
+        Ns = np.log([x["N"] for x in f64])
+        Ls = np.log([x["L1_rho"] for x in f64])
+        ts = np.log([x["seconds"] for x in f64])
+        # FP64 L1 decreases with N; find N' with L1(N') = target
+        if target >= math.exp(Ls[0]):
+            n_eq, t_eq = float("nan"), float("nan")
+        elif target <= math.exp(Ls[-1]):
+            n_eq, t_eq = float("nan"), float("nan")
+        else:
+            order = np.argsort(Ls)
+            ln = float(np.interp(math.log(target), Ls[order], Ns[order]))
+            n_eq = math.exp(ln)
+            t_eq = math.exp(float(np.interp(ln, Ns, ts)))
+        pairs.append({"mixed_N": r["N"], "mixed_L1": target, "mixed_seconds": r["seconds"],
+                      "fp64_N_at_equal_L1": n_eq, "fp64_seconds_at_equal_L1": t_eq})
+    return {"study": "equal-L1", "T3": T3, "reference": {"N": 2048, "steps": nr, "seconds": elr},
+            "rows": rows, "equal_L1_pairs": pairs}
 
 
 def main():
@@ -66,7 +369,6 @@ def main():
         print("bench.py: this build measures one GPU only (the scheme's single-GPU path); "
               "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     if args.copy_probe_mib:
@@ -78,80 +380,16 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 8}))
         return
-
-    from paper_1901_00261_amd import gks
-    from paper_1901_00261_amd import workloads as wl
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
-    prob = wl.isentropic_vortex_2d(args.n, mu=1e-4, eps=5.0, acoustic_amp=1e-3, nmodes=32, seed=3,
-                                   order=8, recon=1, cfl=0.3, t_end=1e9)
-    # inputs resident in HBM (torch owns them), handed to the library by device pointer
-    tW, tWx, tWy = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (prob.W, prob.Wx, prob.Wy))
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream().cuda_stream
-    prec = gks.PREC_FP64 if args.precision == "fp64" else gks.PREC_FP32_MIXED
-    S = gks.Solver(prob, prec, stream=stream, device_arrays=[(tW.data_ptr(), tWx.data_ptr(), tWy.data_ptr())])
-    del tW, tWx, tWy
-    if args.warmup:
-        S.step(args.warmup)
-    t_before = S.state(0)[3]
-    S.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    S.step(args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    W, _, _, t_after, nsteps = S.state(0)
-    flux_ms, flux_n = S.kernel_time(gks.KERNEL_FLUX)
-    row_ms, row_n = S.kernel_time(gks.KERNEL_ROW)
-    cell_ms, cell_n = S.kernel_time(gks.KERNEL_CELL)
-    S.close()
-    cells = prob.nx * prob.ny
-    value = cells * args.steps / el
-
-    # roofline of the dominant kernel (Gauss-point interface kernel):
-    # algorithmic flops per launch = face rows per launch * 3 Gauss points *
-    # flops per Gauss point (operation count of the interface arithmetic)
-    ops = json.load(open(os.path.join(ROOT, "paper_1901_00261_amd", "opcount.json")))
-    fpg = ops["gauss_point_ns"]["flops"]
-    rows_per_launch = ((prob.nx + 1) * prob.ny + (prob.ny + 1) * prob.nx) / 2.0
-    flops_per_launch = rows_per_launch * 3 * fpg
-    avg_s = flux_ms / max(flux_n, 1) / 1e3
-    achieved = flops_per_launch / avg_s / 1e12
-    peak = FP64_VALU_PEAK
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64acc",
-        "data": "synthetic",
-        "config": {"workload": f"2-D Navier-Stokes isentropic vortex + seeded acoustic perturbation, "
-                               f"{prob.nx}x{prob.ny} periodic on [0,10]^2, 8th-order compact WENO-Z GKS, "
-                               f"mu=1e-4, CFL 0.3",
-                   "nx": prob.nx, "ny": prob.ny, "precision": args.precision, "t_reached": t_after,
-                   "kernel_ms_per_step": {"interface": flux_ms / args.steps, "face_row": row_ms / args.steps,
-                                          "cell_update": cell_ms / args.steps}},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "gp2d_kernel (interface, Gauss points)",
-                     "avg_launch_ms": avg_s * 1e3, "launches": flux_n},
-    }
-    ok = bool(np.isfinite(W).all()) and nsteps == args.warmup + args.steps and t_after > t_before
-    if not ok:
-        line["error"] = "non-finite state or missing steps"
-    if not args.no_cpu_baseline:
-        dt0 = (t_after - t_before) / args.steps
-        line["cpu_baseline"] = cpu_baseline(prob, dt0, args.cpu_window)
-    print(json.dumps(line), flush=True)
+    if args.study == "equal-l1":
+        print(json.dumps(study_equal_l1(args)), flush=True)
+    elif args.workload == "vortex2d":
+        print(json.dumps(bench_vortex(args)), flush=True)
+    elif args.workload == "riemann2d":
+        print(json.dumps(bench_riemann2d(args)), flush=True)
+    else:
+        print(json.dumps(bench_batch1d(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -2,51 +2,100 @@
 //
 // Host program: instantiates the same templates the kernels use
 // (face_recon, gp_inputs, kinetic_average, gks_point) with a counting scalar
-// type and tallies every +, -, *, / and every sqrt / exp / expm1 / erfc they
-// perform on one representative smooth input.  Sign changes and comparisons
-// are not counted.  The counts are per unit of work of the kernels:
-//   face_row_2d : one face row of the 2-D face-row kernel (WENO-Z mode)
-//   gauss_point : one Gauss point of the 2-D interface kernel (inputs,
-//                 kinetic average, interface distribution)
-//   face_1d     : one face of the 1-D interface kernel
+// type and tallies the +, -, *, / and sqrt / exp / expm1 / erfc on which
+// the unit's outputs depend, for one representative smooth input.  Sign
+// changes and comparisons are not counted; a fused multiply-add counts as
+// two operations.  The counts are per unit of work of the kernels:
+//   face_row_2d        : one face row of the 2-D face-row kernel (WENO-Z)
+//   gauss_point_*      : one Gauss point of the 2-D interface kernel
+//                        (tangential inputs, kinetic average, interface
+//                        distribution); *_s2: outputs of the second stage
+//                        only (flux time derivative, second time
+//                        derivative of the interface state)
+//   face_1d, face_1d_s2: one face of the 1-D stage kernel
 // Output: JSON on stdout.
 #include "gks_kernels.h"
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
+// Every arithmetic result is a node of an expression graph (operation kind
+// and operands); a unit's count is the number of nodes its outputs depend
+// on, so work whose result is not used by the requested outputs (for
+// example the flux value in the second MSMD stage, which needs only the
+// flux time derivative and the second time derivative of the interface
+// state) is not counted.
 namespace cnt {
-long long add = 0, mul = 0, dv = 0, trans = 0;
+enum Kind : unsigned char { ADD, MUL, DIV, TRANS };
+struct Node {
+    Kind k;
+    int a, b;
+};
+std::vector<Node> g;
+int make(Kind k, int a, int b)
+{
+    g.push_back({k, a, b});
+    return (int)g.size() - 1;
 }
+} // namespace cnt
 
 struct Cnt {
     double v;
-    Cnt() : v(0) {}
-    Cnt(double x) : v(x) {}
+    int id; // -1: input or constant
+    Cnt() : v(0), id(-1) {}
+    Cnt(double x) : v(x), id(-1) {}
+    Cnt(double x, int i) : v(x), id(i) {}
     explicit operator double() const { return v; }
     explicit operator float() const { return (float)v; }
 };
-inline Cnt operator+(Cnt a, Cnt b) { ++cnt::add; return Cnt(a.v + b.v); }
-inline Cnt operator-(Cnt a, Cnt b) { ++cnt::add; return Cnt(a.v - b.v); }
-inline Cnt operator*(Cnt a, Cnt b) { ++cnt::mul; return Cnt(a.v * b.v); }
-inline Cnt operator/(Cnt a, Cnt b) { ++cnt::dv; return Cnt(a.v / b.v); }
-inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt op(cnt::Kind k, double v, Cnt a, Cnt b) { return Cnt(v, cnt::make(k, a.id, b.id)); }
+inline Cnt operator+(Cnt a, Cnt b) { return op(cnt::ADD, a.v + b.v, a, b); }
+inline Cnt operator-(Cnt a, Cnt b) { return op(cnt::ADD, a.v - b.v, a, b); }
+inline Cnt operator*(Cnt a, Cnt b) { return op(cnt::MUL, a.v * b.v, a, b); }
+inline Cnt operator/(Cnt a, Cnt b) { return op(cnt::DIV, a.v / b.v, a, b); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v, a.id); }
 inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
 inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
 inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
-inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
+inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v), a.id); }
 inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
-inline Cnt sqrt(Cnt a) { ++cnt::trans; return Cnt(std::sqrt(a.v)); }
-inline Cnt exp(Cnt a) { ++cnt::trans; return Cnt(std::exp(a.v)); }
-inline Cnt expm1(Cnt a) { ++cnt::trans; return Cnt(std::expm1(a.v)); }
-inline Cnt erfc(Cnt a) { ++cnt::trans; return Cnt(std::erfc(a.v)); }
+inline Cnt sqrt(Cnt a) { return op(cnt::TRANS, std::sqrt(a.v), a, Cnt()); }
+inline Cnt exp(Cnt a) { return op(cnt::TRANS, std::exp(a.v), a, Cnt()); }
+inline Cnt expm1(Cnt a) { return op(cnt::TRANS, std::expm1(a.v), a, Cnt()); }
+inline Cnt erfc(Cnt a) { return op(cnt::TRANS, std::erfc(a.v), a, Cnt()); }
 
 struct Tally {
-    long long add, mul, dv, trans;
+    long long add = 0, mul = 0, dv = 0, trans = 0;
 };
-static Tally snap() { return {cnt::add, cnt::mul, cnt::dv, cnt::trans}; }
-static Tally diff(Tally a, Tally b) { return {b.add - a.add, b.mul - a.mul, b.dv - a.dv, b.trans - a.trans}; }
+
+// nodes created since `first` that the outputs depend on
+static Tally live(size_t first, const std::vector<Cnt>& outs, double scale = 1.0)
+{
+    std::vector<char> seen(cnt::g.size(), 0);
+    std::vector<int> stack;
+    for (const Cnt& o : outs)
+        if (o.id >= 0) stack.push_back(o.id);
+    Tally t;
+    while (!stack.empty()) {
+        const int n = stack.back();
+        stack.pop_back();
+        if (n < 0 || seen[n]) continue;
+        seen[n] = 1;
+        if ((size_t)n < first) continue;
+        const cnt::Node& d = cnt::g[n];
+        (d.k == cnt::ADD ? t.add : d.k == cnt::MUL ? t.mul : d.k == cnt::DIV ? t.dv : t.trans) += 1;
+        stack.push_back(d.a);
+        stack.push_back(d.b);
+    }
+    t.add = (long long)(t.add / scale + 0.5);
+    t.mul = (long long)(t.mul / scale + 0.5);
+    t.dv = (long long)(t.dv / scale + 0.5);
+    t.trans = (long long)(t.trans / scale + 0.5);
+    return t;
+}
 static void emit(const char* name, Tally t, bool comma)
 {
     printf("  \"%s\": {\"add\": %lld, \"mul\": %lld, \"div\": %lld, \"trans\": %lld, \"flops\": %lld}%s\n", name, t.add,
@@ -57,6 +106,11 @@ static void smooth_state(Cnt* W, double s)
 {
     const double rho = 1.0 + 0.1 * s, U = 0.3 - 0.05 * s, V = -0.2 + 0.04 * s, p = 1.0 + 0.07 * s;
     W[0] = rho; W[1] = rho * U; W[2] = rho * V; W[3] = p / 0.4 + 0.5 * rho * (U * U + V * V);
+}
+
+static void push4(std::vector<Cnt>& v, const Cnt* a)
+{
+    for (int k = 0; k < 4; ++k) v.push_back(a[k]);
 }
 
 int main()
@@ -70,9 +124,11 @@ int main()
             smooth_state(Wk[q], 0.1 * q);
             for (int k = 0; k < 4; ++k) Dk[q][k] = 0.01 * (k + 1) * (q + 1);
         }
-        Tally a = snap();
+        const size_t first = cnt::g.size();
         gks::face_recon<Cnt, 2, 8, Cnt>(Wk, Dk, Cnt(0.01), Cnt(gamma), true, [&](int q, int k, Cnt v) { o[q][k] = v; });
-        emit("face_row_2d", diff(a, snap()), true);
+        std::vector<Cnt> outs;
+        for (int q = 0; q < 7; ++q) push4(outs, o[q]);
+        emit("face_row_2d", live(first, outs), true);
     }
     // ---- 2-D Gauss point (NS: mu > 0; and Euler), WENO-Z, averaged over the 3 points
     for (int ns = 1; ns >= 0; --ns) {
@@ -88,9 +144,10 @@ int main()
         }
         auto rv = [&](int q, int k, int r) { return rows[q][k][r]; };
         const gks::PointPar par{gamma, K2, ns ? 1e-4 : 0.0, 1e-3};
-        Tally a = snap();
+        const size_t first = cnt::g.size();
         bool ok = true;
-        auto one = [&](int G) {
+        std::vector<Cnt> all, s2;
+        for (int G = 0; G < 3; ++G) {
             gks::PointIn<Cnt> in;
             gks::PointOut<Cnt> out;
             Cnt W0[4], Wl[4], Wr[4];
@@ -98,17 +155,15 @@ int main()
             gks::NonEq<Cnt, 2> ne;
             ok = ok && gks::noneq_states<Cnt, 2>(Wl, Wr, Cnt(gamma), Cnt(K2), ne, in.Wlx, in.Wly, in.Wrx, in.Wry) &&
                  gks::gks_point<Cnt, 2, Cnt>(par, in, ne.Xs, ne, out);
-        };
-        one(0);
-        one(1);
-        one(2);
+            push4(all, out.FL); push4(all, out.FdL); push4(all, out.S0); push4(all, out.S1); push4(all, out.S2);
+            push4(s2, out.FdL); push4(s2, out.S2);
+        }
         if (!ok) {
             fprintf(stderr, "opcount: unexpected non-physical sample\n");
             return 1;
         }
-        Tally t = diff(a, snap());
-        t.add /= 3; t.mul /= 3; t.dv /= 3; t.trans /= 3;
-        emit(ns ? "gauss_point_ns" : "gauss_point_euler", t, true);
+        emit(ns ? "gauss_point_ns" : "gauss_point_euler", live(first, all, 3.0), true);
+        emit(ns ? "gauss_point_ns_s2" : "gauss_point_euler_s2", live(first, s2, 3.0), true);
     }
     // ---- 1-D face, 8th order, WENO-Z, Euler
     {
@@ -119,7 +174,7 @@ int main()
             Wk[q][3] = 1.0 / 0.4 + 0.5 * Wk[q][1].v * Wk[q][1].v / Wk[q][0].v;
             for (int k = 0; k < 4; ++k) Dk[q][k] = k == 2 ? 0.0 : 0.01 * (k + 1) * (q + 1);
         }
-        Tally a = snap();
+        const size_t first = cnt::g.size();
         bool ok = gks::face_recon<Cnt, 1, 8, Cnt>(Wk, Dk, Cnt(0.01), Cnt(gamma), true, [&](int q, int k, Cnt v) { o[q][k] = v; });
         gks::PointIn<Cnt> in;
         gks::PointOut<Cnt> out;
@@ -137,7 +192,15 @@ int main()
             fprintf(stderr, "opcount: unexpected non-physical sample\n");
             return 1;
         }
-        emit("face_1d", diff(a, snap()), false);
+        // 1-D state slots 0, 1, 3 (slot 2 is the absent v-momentum)
+        std::vector<Cnt> all, s2;
+        for (int k : {0, 1, 3}) {
+            for (const Cnt* a : {out.FL, out.FdL, out.S0, out.S1, out.S2}) all.push_back(a[k]);
+            s2.push_back(out.FdL[k]);
+            s2.push_back(out.S2[k]);
+        }
+        emit("face_1d", live(first, all), true);
+        emit("face_1d_s2", live(first, s2), false);
     }
     printf("}\n");
     return 0;
