@@ -576,33 +576,39 @@ __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__
     const double dt = S.dt;
     const PointPar par{P.gamma, P.K, P.mu, dt};
     const bool weno = P.recon != 0;
-    double acc[5][4];
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[q][k] = 0.0;
+    // Gauss sums of the outputs live in LDS (this lane's column), not in
+    // registers across the Gauss-point loop: slot m = 4 q + k, q = 0 FL,
+    // 1 FdL, 2 S0, 3 S1, 4 S2 (stage 2: FdL and S2 only, slots 0..7)
+    constexpr int NQ = STAGE == 1 ? 5 : 2;
+    __shared__ double sacc[NQ * 4][128];
+    const int lane = threadIdx.y * blockDim.x + threadIdx.x;
     bool ok = true;
 #pragma unroll 1
     for (int g = 0; g < 3; ++g) {
         PointOut<double> o;
         ok = ok && gauss_point<T>(rv, g, ht, weno, par, o);
         const double wg = g == 1 ? 8.0 / 18.0 : 5.0 / 18.0;
-        if (ok)
+        if (ok) {
+            const double* src[5] = {o.FL, o.FdL, o.S0, o.S1, o.S2};
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (STAGE == 1) {
-                    acc[0][k] += wg * o.FL[k];
-                    acc[2][k] += wg * o.S0[k];
-                    acc[3][k] += wg * o.S1[k];
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double v = wg * src[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k];
+                    double& slot = sacc[q * 4 + k][lane];
+                    slot = g == 0 ? v : slot + v;
                 }
-                acc[1][k] += wg * o.FdL[k];
-                acc[4][k] += wg * o.S2[k];
-            }
+        }
     }
     if (!ok) {
         S.err = 1;
         return;
     }
+    double acc[5][4];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k] = sacc[q * 4 + k][lane];
     // back to the global frame
     const int gk[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
     const size_t nfa = DIR == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;

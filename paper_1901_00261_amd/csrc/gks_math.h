@@ -6,6 +6,8 @@
 // (rho, rho U, rho V, rho E); in 1-D slot 2 is identically zero.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -116,23 +118,37 @@ GKS_HD void weno_left(const T* w, const T* d, T& val, T& der)
         d0 = T(3.0 / 98.0); d1 = T(5.0 / 98.0); d2 = T(4.0 / 49.0); d3 = T(7.0 / 98.0);
         d4 = T(7.0 / 98.0); d5 = T(17.0 / 49.0); d6 = T(17.0 / 49.0);
     }
-    const T al0 = d0 * (T(1) + Z / (b0 + eps));
-    const T al1 = d1 * (T(1) + Z / (b1 + eps));
-    const T al2 = d2 * (T(1) + Z / (b2 + eps));
-    const T al3 = d3 * (T(1) + Z / (b3 + eps));
-    const T al4 = d4 * (T(1) + Z / (b4 + eps));
-    const T al5 = d5 * (T(1) + Z / (b5 + eps));
-    const T al6 = d6 * (T(1) + Z / (b6 + eps));
-    const T inv = T(1) / (al0 + al1 + al2 + al3 + al4 + al5 + al6);
-    val = (al0 * c0 + (al1 + al3) * c1 + al2 * c2 + al4 * c4 + al5 * c5 + al6 * c6) * inv;
+    // alpha_k = d_k (1 + Z / e_k), e_k = beta_k + eps.  All seven are scaled by
+    // prod_j e_j, which cancels in the normalisation:
+    //   alpha'_k = d_k (e_k + Z) prod_{j != k} e_j,
+    // formed with prefix and suffix products (in FP64 also for FP32 data:
+    // e_k >= eps keeps the products in range), so one division serves all.
+    using R = std::conditional_t<std::is_same_v<T, float>, double, T>;
+    const R e[7] = {R(b0 + eps), R(b1 + eps), R(b2 + eps), R(b3 + eps), R(b4 + eps), R(b5 + eps), R(b6 + eps)};
+    R pre[7], suf[7];
+    pre[0] = R(1);
+    suf[6] = R(1);
+#pragma unroll
+    for (int k = 1; k < 7; ++k) pre[k] = pre[k - 1] * e[k - 1];
+#pragma unroll
+    for (int k = 5; k >= 0; --k) suf[k] = suf[k + 1] * e[k + 1];
+    const R Zr = R(Z);
+    const R dk[7] = {R(d0), R(d1), R(d2), R(d3), R(d4), R(d5), R(d6)};
+    R al[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) al[k] = dk[k] * (e[k] + Zr) * (pre[k] * suf[k]);
+    const R invr = R(1) / (al[0] + al[1] + al[2] + al[3] + al[4] + al[5] + al[6]);
+    const T al0 = T(al[0] * invr), al1 = T(al[1] * invr), al2 = T(al[2] * invr), al3 = T(al[3] * invr),
+            al4 = T(al[4] * invr), al5 = T(al[5] * invr), al6 = T(al[6] * invr);
+    val = al0 * c0 + (al1 + al3) * c1 + al2 * c2 + al4 * c4 + al5 * c5 + al6 * c6;
     // dx * derivative of each candidate at x = dx/2: b1 + b2/2 + b3/8 + b4/48
-    const T e0 = a01 + T(0.5) * a02;
-    const T e1 = a31 + T(0.5) * a32; // w_1 and w_3 are the same quadratic
-    const T e2 = a21 + T(0.5) * a22 + T(0.125) * a23;
-    const T e4 = a41 + T(0.5) * a42;
-    const T e5 = a51 + T(0.5) * a52 + T(0.125) * a53 + T(1.0 / 48.0) * a54;
-    const T e6 = a61 + T(0.5) * a62 + T(0.125) * a63 + T(1.0 / 48.0) * a64;
-    der = (al0 * e0 + (al1 + al3) * e1 + al2 * e2 + al4 * e4 + al5 * e5 + al6 * e6) * inv;
+    const T g0 = a01 + T(0.5) * a02;
+    const T g1 = a31 + T(0.5) * a32; // w_1 and w_3 are the same quadratic
+    const T g2 = a21 + T(0.5) * a22 + T(0.125) * a23;
+    const T g4 = a41 + T(0.5) * a42;
+    const T g5 = a51 + T(0.5) * a52 + T(0.125) * a53 + T(1.0 / 48.0) * a54;
+    const T g6 = a61 + T(0.5) * a62 + T(0.125) * a63 + T(1.0 / 48.0) * a64;
+    der = al0 * g0 + (al1 + al3) * g1 + al2 * g2 + al4 * g4 + al5 * g5 + al6 * g6;
 }
 
 // Right state at x_{i+1/2}: the mirror image (reversed stencil, slopes
@@ -271,9 +287,10 @@ GKS_HD T tan_weno(const T* q, int g)
                      T(13.0 / 12.0) * s2a * s2a + T(0.25) * s2b * s2b};
     const T Z = tabs(be[0] - be[2]);
     const T eps = T(kWenoEps);
-    T r[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) r[k] = T(1) + Z / (be[k] + eps);
+    // alpha_k = gamma_k (1 + Z / e_k), e_k = beta_k + eps, scaled by e_0 e_1 e_2
+    // (the scale cancels in the normalisation): gamma_k (e_k + Z) prod_{j != k} e_j
+    const T e0 = be[0] + eps, e1 = be[1] + eps, e2 = be[2] + eps;
+    const T r[3] = {(e0 + Z) * (e1 * e2), (e1 + Z) * (e0 * e2), (e2 + Z) * (e0 * e1)};
     if (g != 1) {
         T a[3], sum = T(0), v = T(0);
 #pragma unroll
@@ -285,8 +302,8 @@ GKS_HD T tan_weno(const T* q, int g)
     // gamma+ = (g + 3|g|)/2, gamma- = gamma+ - g
     constexpr double gp0 = 0.1125, gp1 = 2.45, gp2 = 0.1125, sp = 2.675;
     constexpr double gm0 = 0.225, gm1 = 1.225, gm2 = 0.225, sm = 1.675;
-    const T ap0 = T(gp0 / sp) * r[0], ap1 = T(gp1 / sp) * r[1], ap2 = T(gp2 / sp) * r[2];
-    const T am0 = T(gm0 / sm) * r[0], am1 = T(gm1 / sm) * r[1], am2 = T(gm2 / sm) * r[2];
+    const T ap0 = T(gp0) * r[0], ap1 = T(gp1) * r[1], ap2 = T(gp2) * r[2];
+    const T am0 = T(gm0) * r[0], am1 = T(gm1) * r[1], am2 = T(gm2) * r[2];
     const T vp = (ap0 * cand[0] + ap1 * cand[1] + ap2 * cand[2]) / (ap0 + ap1 + ap2);
     const T vm = (am0 * cand[0] + am1 * cand[1] + am2 * cand[2]) / (am0 + am1 + am2);
     return T(sp) * vp - T(sm) * vm;
@@ -480,8 +497,9 @@ template <typename T, int DIM>
 GKS_HD bool primitive(const T* W, T gamma, T& rho, T& U, T& V, T& lam, T& p)
 {
     rho = W[0];
-    U = W[1] / rho;
-    V = (DIM == 2) ? W[2] / rho : T(0);
+    const T ir = T(1) / rho;
+    U = W[1] * ir;
+    V = (DIM == 2) ? W[2] * ir : T(0);
     p = (gamma - T(1)) * (W[3] - T(0.5) * rho * (U * U + V * V));
     lam = T(0.5) * rho / p;
     return (rho > T(0)) && (p > T(0));
@@ -489,8 +507,8 @@ GKS_HD bool primitive(const T* W, T gamma, T& rho, T& U, T& V, T& lam, T& p)
 
 template <typename T> GKS_HD bool physical(const T* W, T gamma, int dim)
 {
-    const T rho = W[0];
-    const T U = W[1] / rho, V = dim == 2 ? W[2] / rho : T(0);
+    const T rho = W[0], ir = T(1) / rho;
+    const T U = W[1] * ir, V = dim == 2 ? W[2] * ir : T(0);
     const T p = (gamma - T(1)) * (W[3] - T(0.5) * rho * (U * U + V * V));
     return (rho > T(0)) && (p > T(0));
 }
@@ -503,7 +521,7 @@ template <typename T> GKS_HD bool physical(const T* W, T gamma, int dim)
 template <typename D>
 GKS_HD void exp_fit(D tau_n, D dt, D& ke, D& kte, D& kde, D& kdte)
 {
-    const D x1 = D(0.5) * dt / tau_n, x2 = dt / tau_n;
+    const D x2 = dt / tau_n, x1 = D(0.5) * x2;
     const D q1 = exp(-x1), q2 = exp(-x2);
     const D om1 = -expm1(-x1), om2 = -expm1(-x2); // 1 - e^{-x}
     const D Ie1 = tau_n * om1, Ie2 = tau_n * om2;
@@ -533,6 +551,7 @@ struct Central {
     T h[7]; // h^n
     T N;
     T U, V, E0;
+    T ih, iN; // 1/h, 1/N (shared by every Gram solve of the point)
 };
 
 constexpr double dfact(int n) { return n <= 0 ? 1.0 : double(n) * dfact(n - 2); }
@@ -651,11 +670,11 @@ GKS_HD void from_central(const Central<T>& C, const T* o, T s, T* b)
 template <typename T, int DIM>
 GKS_HD void gsolve(const Central<T>& C, const T* b, T* a)
 {
-    const T ih = T(1) / C.h[1];
+    const T ih = C.ih;
     a[1] = b[1] * ih;
     a[2] = DIM == 2 ? b[2] * ih : T(0);
     a[0] = T(0.5) * (C.N + T(2)) * b[0] - b[3] * ih;
-    a[3] = -b[0] * ih + T(2) * b[3] * ih * ih / C.N;
+    a[3] = -b[0] * ih + T(2) * b[3] * ih * ih * C.iN;
 }
 
 // ---------------------------------------------------------------------------
@@ -799,6 +818,8 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
     C.N = T(par.K) + T(DIM);
     C.h[0] = T(1);
     C.h[1] = T(p0d / r0d);
+    C.ih = T(r0d / p0d);
+    C.iN = T(1) / C.N;
 #pragma unroll
     for (int n = 2; n < 7; ++n) C.h[n] = C.h[n - 1] * C.h[1];
     const T U = C.U, V = C.V;
