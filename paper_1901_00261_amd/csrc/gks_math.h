@@ -823,52 +823,105 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
 #pragma unroll
     for (int n = 2; n < 7; ++n) C.h[n] = C.h[n - 1] * C.h[1];
     const T U = C.U, V = C.V;
-    T bx[4], by[4] = {T(0), T(0), T(0), T(0)}, bxx[4], bxy[4] = {T(0), T(0), T(0), T(0)},
-             byy[4] = {T(0), T(0), T(0), T(0)};
-    to_central<T, DIM>(C, in.W0x, ir0, bx);
-    to_central<T, DIM>(C, in.W0xx, ir0, bxx);
-    if constexpr (DIM == 2) {
-        to_central<T, DIM>(C, in.W0y, ir0, by);
-        to_central<T, DIM>(C, in.W0xy, ir0, bxy);
-        to_central<T, DIM>(C, in.W0yy, ir0, byy);
+    const T tau = T(tau_d);
+
+    // The outputs are sums of separately formed terms:
+    //   FL  = F0 - tau <u(a.u + Abar)psi> + ke Me + kte Mte
+    //   FdL = <u Abar psi> - tau <u(G_xt u + G_yt v + G_tt)psi> + kde Me + kdte Mte
+    //   S0  = W0 + ke Ne + kte Nte,  S1 = <Abar psi> + kde Ne + kdte Nte,  S2 = <G_tt psi>
+    // with Me = Xf - F0, Ne = Xs - W0 (values of the two states) and
+    // Mte = <u(a.u)psi>_0 - Hm, Nte = -<Abar psi> - Hn (their slope parts).
+    // Each term is added as soon as it is formed, so the intermediate
+    // vectors do not stay live to the end.
+    {
+        D F0[4];
+        F0[0] = W0d[1];
+        F0[1] = W0d[1] * U0d + p0d;
+        F0[2] = W0d[2] * U0d;
+        F0[3] = U0d * (W0d[3] + p0d);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const D Me = ne.Xf[k] - F0[k];
+            const D Ne = ne.Xs[k] - W0d[k];
+            const D hm = D(ne.Hm[k]), hn = D(ne.Hn[k]);
+            out.FL[k] = F0[k] + ke * Me - kte * hm;
+            out.FdL[k] = kde * Me - kdte * hm;
+            out.S0[k] = W0d[k] + ke * Ne - kte * hn;
+            out.S1[k] = kde * Ne - kdte * hn;
+        }
     }
     T a1[4], a2[4] = {T(0), T(0), T(0), T(0)}, At[4], t1[4], t2[4];
-    gsolve<T, DIM>(C, bx, a1);
-    if constexpr (DIM == 2) gsolve<T, DIM>(C, by, a2);
-    // compatibility: G Abar = -(U b_x + <c a1 phi> + V b_y + <w a2 phi>)
-    T S1c[4];
-    clin<1, 0, DIM>(C, a1, t1);
+    {
+        T bx[4], by[4] = {T(0), T(0), T(0), T(0)};
+        to_central<T, DIM>(C, in.W0x, ir0, bx);
+        if constexpr (DIM == 2) to_central<T, DIM>(C, in.W0y, ir0, by);
+        gsolve<T, DIM>(C, bx, a1);
+        if constexpr (DIM == 2) gsolve<T, DIM>(C, by, a2);
+        // <u (a1 u + a2 v) psi>0 (initial-layer slope term of g0), central form
+        T Mc[4];
+        clin<1, 0, DIM>(C, a1, t1);
+        clin<2, 0, DIM>(C, a1, t2);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) S1c[k] = -(U * bx[k] + t1[k]);
-    if constexpr (DIM == 2) {
-        clin<0, 1, DIM>(C, a2, t2);
+        for (int k = 0; k < 4; ++k) Mc[k] = U * U * bx[k] + T(2) * U * t1[k] + t2[k];
+        // compatibility: G Abar = -(U b_x + <c a1 phi> + V b_y + <w a2 phi>)
+        T S1c[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) S1c[k] -= V * by[k] + t2[k];
+        for (int k = 0; k < 4; ++k) S1c[k] = -(U * bx[k] + t1[k]);
+        if constexpr (DIM == 2) {
+            T t3[4];
+            clin<0, 1, DIM>(C, a2, t3);
+            clin<1, 0, DIM>(C, a2, t1);
+            clin<1, 1, DIM>(C, a2, t2);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Mc[k] += U * V * by[k] + U * t3[k] + V * t1[k] + t2[k];
+                S1c[k] -= V * by[k] + t3[k];
+            }
+        }
+        gsolve<T, DIM>(C, S1c, At);
+        // <u Abar psi> = central U <Abar phi> + <c Abar phi>
+        T F1c[4];
+        clin<1, 0, DIM>(C, At, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) F1c[k] = U * S1c[k] + t1[k];
+        T Mte[4], F1[4], S1n[4];
+        from_central<T, DIM>(C, Mc, r0, Mte);
+        from_central<T, DIM>(C, F1c, r0, F1);
+        from_central<T, DIM>(C, S1c, r0, S1n);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            out.FL[k] += kte * D(Mte[k]);
+            out.FdL[k] += D(F1[k]) + kdte * D(Mte[k]);
+            out.S0[k] -= kte * D(S1n[k]);
+            out.S1[k] += D(S1n[k]) - kdte * D(S1n[k]);
+        }
+        // Navier-Stokes: <u (a1 u + a2 v + Abar) psi> = Mc + F1c
+        if (par.mu > 0.0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out.FL[k] -= D(tau * (Mte[k] + F1[k]));
     }
-    gsolve<T, DIM>(C, S1c, At);
-    // second-order coefficients: <G_xx phi> = b_xx etc.
-    T axx[4], axy[4] = {T(0), T(0), T(0), T(0)}, ayy[4] = {T(0), T(0), T(0), T(0)};
-    cbil<0, 0, DIM>(C, a1, a1, t1);
+    // second-order coefficients: <G_xx phi> = b_xx etc.;
+    // <G_xt phi> = -<(U + c) G_xx phi> - <(V + w) G_xy phi>  (= Pxt), same for yt
+    T Pxt[4], Pyt[4] = {T(0), T(0), T(0), T(0)};
+    {
+        T bxx[4], axx[4];
+        to_central<T, DIM>(C, in.W0xx, ir0, bxx);
+        cbil<0, 0, DIM>(C, a1, a1, t1);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) t1[k] = bxx[k] - t1[k];
-    gsolve<T, DIM>(C, t1, axx);
+        for (int k = 0; k < 4; ++k) t1[k] = bxx[k] - t1[k];
+        gsolve<T, DIM>(C, t1, axx);
+        clin<1, 0, DIM>(C, axx, t1);
+        cbil<1, 0, DIM>(C, a1, a1, t2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Pxt[k] = -(U * bxx[k] + t1[k] + t2[k]);
+    }
     if constexpr (DIM == 2) {
+        T bxy[4], axy[4];
+        to_central<T, DIM>(C, in.W0xy, ir0, bxy);
         cbil<0, 0, DIM>(C, a1, a2, t1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) t1[k] = bxy[k] - t1[k];
         gsolve<T, DIM>(C, t1, axy);
-        cbil<0, 0, DIM>(C, a2, a2, t1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) t1[k] = byy[k] - t1[k];
-        gsolve<T, DIM>(C, t1, ayy);
-    }
-    // <G_xt phi> = -<(U + c) G_xx phi> - <(V + w) G_xy phi>  (= Pxt), same for yt
-    T Pxt[4], Pyt[4] = {T(0), T(0), T(0), T(0)};
-    clin<1, 0, DIM>(C, axx, t1);
-    cbil<1, 0, DIM>(C, a1, a1, t2);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Pxt[k] = -(U * bxx[k] + t1[k] + t2[k]);
-    if constexpr (DIM == 2) {
         clin<0, 1, DIM>(C, axy, t1);
         cbil<0, 1, DIM>(C, a1, a2, t2);
 #pragma unroll
@@ -877,6 +930,12 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
         cbil<1, 0, DIM>(C, a1, a2, t2);
 #pragma unroll
         for (int k = 0; k < 4; ++k) Pyt[k] = -(U * bxy[k] + t1[k] + t2[k]);
+        T byy[4], ayy[4];
+        to_central<T, DIM>(C, in.W0yy, ir0, byy);
+        cbil<0, 0, DIM>(C, a2, a2, t1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t1[k] = byy[k] - t1[k];
+        gsolve<T, DIM>(C, t1, ayy);
         clin<0, 1, DIM>(C, ayy, t1);
         cbil<0, 1, DIM>(C, a2, a2, t2);
 #pragma unroll
@@ -905,32 +964,15 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
 #pragma unroll
         for (int k = 0; k < 4; ++k) { cy[k] = t1[k] + t2[k]; S2c[k] -= V * Pyt[k] + cy[k]; } // cy = <w G_yt phi>
     }
-    // <u Abar psi>: central U <Abar phi> + <c Abar phi>
-    T F1c[4], Mc[4];
-    clin<1, 0, DIM>(C, At, t1);
+    {
+        T S2n[4];
+        from_central<T, DIM>(C, S2c, r0, S2n);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) F1c[k] = U * S1c[k] + t1[k];
-    // <u (a1 u + a2 v) psi>0 (initial-layer slope term of g0)
-    clin<1, 0, DIM>(C, a1, t1);
-    clin<2, 0, DIM>(C, a1, t2);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Mc[k] = U * U * bx[k] + T(2) * U * t1[k] + t2[k];
-    if constexpr (DIM == 2) {
-        T t3[4];
-        clin<0, 1, DIM>(C, a2, t3);
-        clin<1, 0, DIM>(C, a2, t1);
-        clin<1, 1, DIM>(C, a2, t2);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Mc[k] += U * V * by[k] + U * t3[k] + V * t1[k] + t2[k];
+        for (int k = 0; k < 4; ++k) out.S2[k] = D(S2n[k]);
     }
-    T F0t[4] = {T(0), T(0), T(0), T(0)}, F1t[4] = {T(0), T(0), T(0), T(0)};
     if (par.mu > 0.0) {
-        // <u (a1 u + a2 v + Abar) psi> = Mc + U <Abar phi> + <c Abar phi>
-        clin<1, 0, DIM>(C, At, t1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) F0t[k] = Mc[k] + U * S1c[k] + t1[k];
         // <u (G_xt u + G_yt v + G_tt) psi>
-        T att[4];
+        T F1t[4], att[4];
         cbil<0, 0, DIM>(C, At, At, t1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) t1[k] = S2c[k] - t1[k];
@@ -954,45 +996,9 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
 #pragma unroll
             for (int k = 0; k < 4; ++k) F1t[k] += t3[k];
         }
-    }
-    // back to conservative components, times rho0
-    T F1[4], S1n[4], S2n[4], Mte[4], Nte[4];
-    from_central<T, DIM>(C, F1c, r0, F1);
-    from_central<T, DIM>(C, S1c, r0, S1n);
-    from_central<T, DIM>(C, S2c, r0, S2n);
-    from_central<T, DIM>(C, Mc, r0, Mte);
+        from_central<T, DIM>(C, F1t, r0, t1);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Nte[k] = -S1n[k];
-    if (par.mu > 0.0) {
-        from_central<T, DIM>(C, F0t, r0, t1);
-        from_central<T, DIM>(C, F1t, r0, t2);
-        const T tau = T(tau_d);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) { F0t[k] = tau * t1[k]; F1[k] -= tau * t2[k]; }
-    }
-
-    // ---- non-equilibrium slope terms (computed with the states) ----
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        Nte[k] -= ne.Hn[k];
-        Mte[k] -= ne.Hm[k];
-    }
-
-    // ---- equilibrium flux (type D) and the e^{-t/tau_n} value parts ----
-    D F0[4];
-    F0[0] = W0d[1];
-    F0[1] = W0d[1] * U0d + p0d;
-    F0[2] = W0d[2] * U0d;
-    F0[3] = U0d * (W0d[3] + p0d);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const D Me = ne.Xf[k] - F0[k];
-        const D Ne = ne.Xs[k] - W0d[k];
-        out.FL[k] = F0[k] - D(F0t[k]) + ke * Me + kte * D(Mte[k]);
-        out.FdL[k] = D(F1[k]) + kde * Me + kdte * D(Mte[k]);
-        out.S0[k] = W0d[k] + ke * Ne + kte * D(Nte[k]);
-        out.S1[k] = D(S1n[k]) + kde * Ne + kdte * D(Nte[k]);
-        out.S2[k] = D(S2n[k]);
+        for (int k = 0; k < 4; ++k) out.FdL[k] -= D(tau * t1[k]);
     }
     if constexpr (DIM == 1) {
         out.FL[2] = out.FdL[2] = out.S0[2] = out.S1[2] = out.S2[2] = D(0);
