@@ -138,3 +138,80 @@ def test_2d_riemann_small():
     S.close()
     want = oracle_run(p, max_steps=6)
     check(p, got, want, tol_w=1e-10, tol_s=1e-8)
+
+
+def _nonphysical_2d(W, gamma):
+    rho = W[..., 0]
+    safe = np.where(rho > 0, rho, 1.0)
+    p = (gamma - 1.0) * (W[..., 3] - 0.5 * (W[..., 1] ** 2 + W[..., 2] ** 2) / safe)
+    return bool((~(rho > 0)).any() or (~(p > 0)).any())
+
+
+def test_2d_nonphysical_stop_matches_oracle():
+    """Seeded four-quadrant problem (seed 6, 32^2) whose solution by this
+    unlimited scheme turns non-physical: the GPU reports GKS_ENONPHYS on the
+    same step as the oracle and keeps the state of the last good step; the
+    handle stays usable (later calls return GKS_OK with no active problem).
+    Ten steps in, both agree to the FP64 bar; approaching the breakdown the
+    state nears vacuum and rounding differences grow with every step, so at
+    the stop the states are compared to 1e-6 and the times to 1e-9."""
+    g = gks()
+    p = wl.riemann_2d(32, seed=6)
+    S = g.Solver(p)
+    assert S.step(10) == 1
+    check(p, S.state(0), oracle_run(p, max_steps=10), tol_w=1e-10, tol_s=1e-8)
+    r = S.step(200, raise_on_error=False)
+    assert r == g.GKS_ENONPHYS
+    assert S.status(0) == g.GKS_ENONPHYS
+    got = S.state(0)
+    n = got[4]
+    assert 10 < n < 200
+    want = oracle_run(p, max_steps=n)
+    print(f"stop after {n} steps: W {rel(got[0], want[0]):.2e}  Wx {rel(got[1], want[1]):.2e}  "
+          f"t {abs(got[3] - want[3]):.2e}", flush=True)
+    assert want[4] == n
+    assert abs(got[3] - want[3]) <= 1e-9 * abs(want[3])
+    assert rel(got[0], want[0]) <= 1e-6 and rel(got[1], want[1]) <= 1e-5 and rel(got[2], want[2]) <= 1e-5
+    try:
+        nxt = oracle_run(p, max_steps=n + 1)
+        assert _nonphysical_2d(nxt[0], p.gamma)
+    except oracle.OracleError:
+        pass
+    assert S.step(5) == 0
+    assert S.state(0)[4] == n
+    S.close()
+
+
+def test_invalid_arguments_are_rejected():
+    """Host-side validation: every bad field gives GKS_EINVAL with a message
+    and no handle; a non-physical initial state is rejected at init."""
+    g = gks()
+    base = wl.sine_wave_1d(16)
+    cases = [("nx", 3, "nx"), ("gamma", 1.0, "gamma"), ("mu", -1.0, "mu"), ("t_end", 0.0, "t_end"),
+             ("recon", 5, "recon"), ("cfl", 0.0, "cfl")]
+    for field, val, word in cases:
+        q = wl.sine_wave_1d(16)
+        setattr(q, field, val)
+        if field == "nx":
+            q.W, q.Wx = q.W[:3], q.Wx[:3]
+        with pytest.raises(g.GksError) as e:
+            g.Solver(q)
+        assert e.value.code == g.GKS_EINVAL and word in str(e.value), (field, str(e.value))
+    q = wl.sine_wave_1d(16)
+    q.bc = (0, 1, 0, 0)
+    with pytest.raises(g.GksError) as e:
+        g.Solver(q)
+    assert "paired" in str(e.value)
+    q = wl.sine_wave_1d(16)
+    q.W = q.W.copy()
+    q.W[5, 2] = -1.0  # negative energy: non-physical initial state
+    with pytest.raises(g.GksError) as e:
+        g.Solver(q)
+    assert e.value.code == g.GKS_EINVAL and "non-physical" in str(e.value)
+    # mixed dims in one handle
+    with pytest.raises(g.GksError):
+        g.Solver([base, wl.isentropic_vortex_2d(8)])
+    # a valid handle still works after the failures
+    S = g.Solver(base)
+    assert S.step(3) == 1
+    S.close()
