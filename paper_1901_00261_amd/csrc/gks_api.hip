@@ -53,6 +53,10 @@ struct gks_handle {
     unsigned* ctr = nullptr;
     Tile* dItems[3] = {nullptr, nullptr, nullptr}; // tile sizes 64, 128, 256 (BLK - 1 cells each)
     int nItems[3] = {0, 0, 0};
+    int* dFirst[3] = {nullptr, nullptr, nullptr}; // per problem: first item and item count
+    int* dCount[3] = {nullptr, nullptr, nullptr};
+    Tile* dAct[3] = {nullptr, nullptr, nullptr};  // items of the active problems (rebuilt every step)
+    int* dNact = nullptr;
     int ncu = 256;
     // launch configuration (autotuned): threads per tile, workgroups per CU
     // (0: one workgroup per work item)
@@ -182,19 +186,22 @@ void harvest(gks_handle* h)
 template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
 {
     const int b = h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2);
-    const Tile* it = h->dItems[b];
     const int n = h->nItems[b];
+    gks::compact_items_kernel<<<1, gks::kCompactThreads, 0, st>>>(h->dS, h->nprob, h->dItems[b], h->dFirst[b],
+                                                                  h->dCount[b], h->dAct[b], h->dNact);
+    const Tile* it = h->dAct[b];
+    const int* na = h->dNact;
     const int G = h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu);
     record(h, st, 0, true);
     if (h->blk == 64) {
-        gks::stage1d_kernel<T, 1, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
-        gks::stage1d_kernel<T, 2, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 1, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
     } else if (h->blk == 128) {
-        gks::stage1d_kernel<T, 1, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
-        gks::stage1d_kernel<T, 2, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 1, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
     } else {
-        gks::stage1d_kernel<T, 1, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
-        gks::stage1d_kernel<T, 2, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, n, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 1, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
     }
     record(h, st, 0, false);
     gks::finish_kernel<<<(h->nprob + 63) / 64, 64, 0, st>>>(h->dP, h->dS, h->nprob, 1, h->ctr);
@@ -407,7 +414,13 @@ void release(gks_handle* h)
     drop_graph(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     dfree(h->ctr);
-    for (int b = 0; b < 3; ++b) dfree(h->dItems[b]);
+    for (int b = 0; b < 3; ++b) {
+        dfree(h->dItems[b]);
+        dfree(h->dFirst[b]);
+        dfree(h->dCount[b]);
+        dfree(h->dAct[b]);
+    }
+    dfree(h->dNact);
     for (auto& e : h->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto& e : h->pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -504,6 +517,7 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     TRY(([&]() -> int {
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         HIP_TRY(h, dalloc(&h->ctr, 2));
+        HIP_TRY(h, dalloc(&h->dNact, 1));
         HIP_TRY(h, hipMemset(h->ctr, 0, 2 * sizeof(unsigned)));
         return 0;
     })());
@@ -511,12 +525,21 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
         const int blks[3] = {64, 128, 256};
         for (int b = 0; b < 3; ++b) {
             std::vector<Tile> items;
-            for (int p = 0; p < nprob; ++p)
+            std::vector<int> first(nprob), count(nprob);
+            for (int p = 0; p < nprob; ++p) {
+                first[p] = (int)items.size();
                 for (int s = 0; s < probs[p].nx; s += blks[b] - 1) items.push_back(Tile{p, s});
+                count[p] = (int)items.size() - first[p];
+            }
             h->nItems[b] = (int)items.size();
             TRY(([&]() -> int {
                 HIP_TRY(h, dalloc(&h->dItems[b], items.size()));
+                HIP_TRY(h, dalloc(&h->dAct[b], items.size()));
+                HIP_TRY(h, dalloc(&h->dFirst[b], (size_t)nprob));
+                HIP_TRY(h, dalloc(&h->dCount[b], (size_t)nprob));
                 HIP_TRY(h, hipMemcpy(h->dItems[b], items.data(), sizeof(Tile) * items.size(), hipMemcpyHostToDevice));
+                HIP_TRY(h, hipMemcpy(h->dFirst[b], first.data(), sizeof(int) * nprob, hipMemcpyHostToDevice));
+                HIP_TRY(h, hipMemcpy(h->dCount[b], count.data(), sizeof(int) * nprob, hipMemcpyHostToDevice));
                 return 0;
             })());
         }

@@ -208,13 +208,15 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
 // and updates its cells.  Workgroups take items from a device counter until
 // the list is exhausted, so the same kernel runs persistent (a few
 // workgroups per CU) or as a plain grid (one workgroup per item); every
-// workgroup reaches the exit.  ctr[STAGE-1] is reset by finish_kernel at the
-// end of the step.  Faces owned by the tile (all but its last face, plus the
+// workgroup reaches the exit.  The item list holds only the problems still
+// active (compact_items_kernel, start of the step); its length is read from
+// device memory.  ctr[STAGE-1] is reset by finish_kernel at the end of the
+// step.  Faces owned by the tile (all but its last face, plus the
 // problem's last face) carry the MSMD partial Pf from stage 1 to stage 2.
 // ---------------------------------------------------------------------------
 template <typename T, int STAGE, int BLK>
 __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
-                                                      const Tile* __restrict__ items, int nitems,
+                                                      const Tile* __restrict__ items, const int* __restrict__ nitems_p,
                                                       unsigned* __restrict__ ctr, double* __restrict__ W,
                                                       double* __restrict__ Wx, double* __restrict__ PW,
                                                       double* __restrict__ Pf, long long Ntot, long long F)
@@ -222,6 +224,7 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
     __shared__ double sh_FL[3][BLK], sh_FdL[3][BLK], sh_Wf[3][BLK];
     __shared__ int sh_item;
     const int t = threadIdx.x;
+    const int nitems = *nitems_p;
     for (;;) {
         if (t == 0) sh_item = (int)atomicAdd(&ctr[STAGE - 1], 1u);
         __syncthreads();
@@ -333,6 +336,38 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
         }
         __syncthreads(); // LDS reuse by the next item
     }
+}
+
+// Work list of the next step: the items of the problems still active, in
+// problem order (a single workgroup scans the problems in chunks).  first[p],
+// count[p]: problem p's items in the full list.  Writes act[0..n) and *nact.
+constexpr int kCompactThreads = 256;
+__global__ void __launch_bounds__(kCompactThreads) compact_items_kernel(const ProbState* __restrict__ PS, int nprob,
+                                                                        const Tile* __restrict__ all,
+                                                                        const int* __restrict__ first,
+                                                                        const int* __restrict__ count,
+                                                                        Tile* __restrict__ act, int* __restrict__ nact)
+{
+    __shared__ int scan[kCompactThreads];
+    const int t = threadIdx.x;
+    int base = 0;
+    for (int p0 = 0; p0 < nprob; p0 += kCompactThreads) {
+        const int p = p0 + t;
+        const int c = (p < nprob && PS[p].active) ? count[p] : 0;
+        scan[t] = c;
+        __syncthreads();
+        for (int off = 1; off < kCompactThreads; off <<= 1) { // inclusive scan
+            const int v = t >= off ? scan[t - off] : 0;
+            __syncthreads();
+            scan[t] += v;
+            __syncthreads();
+        }
+        const int dst = base + scan[t] - c;
+        for (int i = 0; i < c; ++i) act[dst + i] = all[first[p] + i];
+        base += scan[kCompactThreads - 1];
+        __syncthreads(); // scan[] reuse by the next chunk
+    }
+    if (t == 0) *nact = base;
 }
 
 // maximum signal speed of the current state (start of a run)
