@@ -57,6 +57,7 @@ struct gks_handle {
     int* dCount[3] = {nullptr, nullptr, nullptr};
     Tile* dAct[3] = {nullptr, nullptr, nullptr};  // items of the active problems (rebuilt every step)
     int* dNact = nullptr;
+    int act_blk = -1; // tile size the device work list was last built for (-1: stale)
     int ncu = 256;
     // launch configuration (autotuned): threads per tile, workgroups per CU
     // (0: one workgroup per work item)
@@ -183,28 +184,39 @@ void harvest(gks_handle* h)
     h->pending.clear();
 }
 
+// the device work list for the current tile size, rebuilt from the problem
+// states when it is stale (first step, tile size changed, state restored)
+void ensure_work_list(gks_handle* h, hipStream_t st)
+{
+    if (h->act_blk == h->blk) return;
+    const int b = h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2);
+    gks::compact_items_kernel<<<1, gks::kCompactThreads, 0, st>>>(h->dS, h->nprob, h->dItems[b], h->dFirst[b],
+                                                                  h->dCount[b], h->dAct[b], h->dNact);
+    h->act_blk = h->blk;
+}
+
 template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
 {
     const int b = h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2);
     const int n = h->nItems[b];
-    gks::compact_items_kernel<<<1, gks::kCompactThreads, 0, st>>>(h->dS, h->nprob, h->dItems[b], h->dFirst[b],
-                                                                  h->dCount[b], h->dAct[b], h->dNact);
-    const Tile* it = h->dAct[b];
-    const int* na = h->dNact;
+    ensure_work_list(h, st);
+    Tile* it = h->dAct[b];
+    int* na = h->dNact;
     const int G = h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu);
     record(h, st, 0, true);
     if (h->blk == 64) {
-        gks::stage1d_kernel<T, 1, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
-        gks::stage1d_kernel<T, 2, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 1, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+        gks::stage1d_kernel<T, 2, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
     } else if (h->blk == 128) {
-        gks::stage1d_kernel<T, 1, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
-        gks::stage1d_kernel<T, 2, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 1, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+        gks::stage1d_kernel<T, 2, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
     } else {
-        gks::stage1d_kernel<T, 1, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
-        gks::stage1d_kernel<T, 2, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 1, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+        gks::stage1d_kernel<T, 2, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
     }
     record(h, st, 0, false);
-    gks::finish_kernel<<<(h->nprob + 63) / 64, 64, 0, st>>>(h->dP, h->dS, h->nprob, 1, h->ctr);
+    // the last workgroup of the second stage commits the step and rebuilds the work list
+    h->act_blk = h->blk;
 }
 
 template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
@@ -272,6 +284,7 @@ void drop_graph(gks_handle* h)
 int build_graph(gks_handle* h)
 {
     drop_graph(h);
+    if (h->dim == 1) ensure_work_list(h, h->stream); // the captured step assumes a current list
     HIP_TRY(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     launch_step(h, h->cap);
     HIP_TRY(h, hipStreamEndCapture(h->cap, &h->graph));
@@ -382,7 +395,9 @@ int autotune(gks_handle* h)
             st = fail(h, GKS_EDEVICE, "autotune: state restore failed");
             break;
         }
+        h->act_blk = -1; // the work list reflects the tuning steps, not the restored state
     }
+    h->act_blk = -1;
     h->timing = was_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -516,9 +531,9 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     if (const char* g = getenv("GKS_GRAPH")) h->use_graph = atoi(g) != 0;
     TRY(([&]() -> int {
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-        HIP_TRY(h, dalloc(&h->ctr, 2));
+        HIP_TRY(h, dalloc(&h->ctr, 3));
         HIP_TRY(h, dalloc(&h->dNact, 1));
-        HIP_TRY(h, hipMemset(h->ctr, 0, 2 * sizeof(unsigned)));
+        HIP_TRY(h, hipMemset(h->ctr, 0, 3 * sizeof(unsigned)));
         return 0;
     })());
     if (dim == 1) {

@@ -201,6 +201,91 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
 }
 
 // ---------------------------------------------------------------------------
+// Per-problem step bookkeeping.
+//   commit = 1: the step just run is accepted (flip buffers, advance t) or,
+//               after an error, the problem stops with W^n kept.
+//   Then the next dt follows from the maximum signal speed of the state.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void finish_problem(const ProbParam& P, ProbState& S, int commit)
+{
+    if (!S.active) return;
+    if (S.err) {
+        S.active = 0;
+        return;
+    }
+    if (commit) {
+        S.cur = 1 - S.cur;
+        S.t = S.last ? P.t_end : S.t + S.dt;
+        S.nsteps += 1;
+    }
+    const double smax = bits_to_double(S.smax);
+    S.smax = 0ull;
+    if (!(S.t < P.t_end)) {
+        S.active = 0;
+        return;
+    }
+    double dt = P.dt_fixed > 0.0 ? P.dt_fixed : P.cfl / smax;
+    int last = 0;
+    if (S.t + dt >= P.t_end - 1e-9 * dt) {
+        dt = P.t_end - S.t;
+        last = 1;
+    }
+    S.dt = dt;
+    S.last = last;
+}
+
+// one thread per problem (initial dt, and the 2-D step); ctr: work counters
+// of the batched 1-D kernels, reset here (null for 2-D)
+__global__ void finish_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob, int commit,
+                              unsigned* __restrict__ ctr)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ctr && p < 3) ctr[p] = 0u;
+    if (p < nprob) finish_problem(PP[p], PS[p], commit);
+}
+
+// Work list of the next step: the items of the problems still active, in
+// problem order, built by one workgroup of NT threads that scans the
+// problems in chunks (scan: NT ints of LDS).  first[p], count[p]: problem
+// p's items in the full list.  Writes act[0..n) and *nact.
+template <int NT>
+__device__ void compact_items_block(const ProbState* __restrict__ PS, int nprob, const Tile* __restrict__ all,
+                                    const int* __restrict__ first, const int* __restrict__ count,
+                                    Tile* __restrict__ act, int* __restrict__ nact, int* scan)
+{
+    const int t = threadIdx.x;
+    int base = 0;
+    for (int p0 = 0; p0 < nprob; p0 += NT) {
+        const int p = p0 + t;
+        const int c = (p < nprob && PS[p].active) ? count[p] : 0;
+        scan[t] = c;
+        __syncthreads();
+        for (int off = 1; off < NT; off <<= 1) { // inclusive scan
+            const int v = t >= off ? scan[t - off] : 0;
+            __syncthreads();
+            scan[t] += v;
+            __syncthreads();
+        }
+        const int dst = base + scan[t] - c;
+        for (int i = 0; i < c; ++i) act[dst + i] = all[first[p] + i];
+        base += scan[NT - 1];
+        __syncthreads(); // scan[] reuse by the next chunk
+    }
+    if (t == 0) *nact = base;
+}
+
+constexpr int kCompactThreads = 256;
+__global__ void __launch_bounds__(kCompactThreads) compact_items_kernel(const ProbState* __restrict__ PS, int nprob,
+                                                                        const Tile* __restrict__ all,
+                                                                        const int* __restrict__ first,
+                                                                        const int* __restrict__ count,
+                                                                        Tile* __restrict__ act, int* __restrict__ nact)
+{
+    __shared__ int scan[kCompactThreads];
+    compact_items_block<kCompactThreads>(PS, nprob, all, first, count, act, nact, scan);
+}
+
+// ---------------------------------------------------------------------------
 // Batched 1-D: one launch per MSMD stage for all problems.  A work item is
 // a tile of BLK-1 cells of one problem; the workgroup computes the BLK faces
 // bounding it (the last face of a tile is also the first face of the next
@@ -209,17 +294,20 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
 // the list is exhausted, so the same kernel runs persistent (a few
 // workgroups per CU) or as a plain grid (one workgroup per item); every
 // workgroup reaches the exit.  The item list holds only the problems still
-// active (compact_items_kernel, start of the step); its length is read from
-// device memory.  ctr[STAGE-1] is reset by finish_kernel at the end of the
-// step.  Faces owned by the tile (all but its last face, plus the
+// active; its length is read from device memory.  The last workgroup of the
+// second stage to finish (a done-counter, ctr[2]) commits the step for every
+// problem, resets the counters and rebuilds the list for the next step, so
+// a step is two launches.  Faces owned by the tile (all but its last face, plus the
 // problem's last face) carry the MSMD partial Pf from stage 1 to stage 2.
 // ---------------------------------------------------------------------------
 template <typename T, int STAGE, int BLK>
 __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
-                                                      const Tile* __restrict__ items, const int* __restrict__ nitems_p,
+                                                      Tile* items, int* nitems_p,
                                                       unsigned* __restrict__ ctr, double* __restrict__ W,
                                                       double* __restrict__ Wx, double* __restrict__ PW,
-                                                      double* __restrict__ Pf, long long Ntot, long long F)
+                                                      double* __restrict__ Pf, long long Ntot, long long F,
+                                                      int nprob, const Tile* __restrict__ all,
+                                                      const int* __restrict__ first, const int* __restrict__ count)
 {
     __shared__ double sh_FL[3][BLK], sh_FdL[3][BLK], sh_Wf[3][BLK];
     __shared__ int sh_item;
@@ -279,7 +367,7 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
                 ok = gks_point<T, 1>(par, in, P.recon ? ne.Xs : o[0], ne, out);
             }
             if (!ok) {
-                S.err = 1;
+                atomicOr(&S.err, 1);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = 0.0;
             }
@@ -329,45 +417,33 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
             if (live) {
                 const double rho = wn[0], U = wn[1] / rho;
                 const double p = (P.gamma - 1.0) * (wn[2] - 0.5 * rho * U * U);
-                if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
+                if (!(rho > 0.0) || !(p > 0.0)) atomicOr(&S.err, 1);
                 else sp = (fabs(U) + sqrt(P.gamma * p / rho)) * idx;
             }
             block_max_atomic(sp, &S.smax);
         }
         __syncthreads(); // LDS reuse by the next item
     }
-}
-
-// Work list of the next step: the items of the problems still active, in
-// problem order (a single workgroup scans the problems in chunks).  first[p],
-// count[p]: problem p's items in the full list.  Writes act[0..n) and *nact.
-constexpr int kCompactThreads = 256;
-__global__ void __launch_bounds__(kCompactThreads) compact_items_kernel(const ProbState* __restrict__ PS, int nprob,
-                                                                        const Tile* __restrict__ all,
-                                                                        const int* __restrict__ first,
-                                                                        const int* __restrict__ count,
-                                                                        Tile* __restrict__ act, int* __restrict__ nact)
-{
-    __shared__ int scan[kCompactThreads];
-    const int t = threadIdx.x;
-    int base = 0;
-    for (int p0 = 0; p0 < nprob; p0 += kCompactThreads) {
-        const int p = p0 + t;
-        const int c = (p < nprob && PS[p].active) ? count[p] : 0;
-        scan[t] = c;
+    if (STAGE == 2) {
+        // the last workgroup to finish commits the step for every problem,
+        // sets the next dt and builds the next step's work list
+        __shared__ int sh_last;
+        __shared__ int sh_scan[BLK];
+        // (the last workgroup reads only what other workgroups wrote with
+        // device-scope atomics: the error flags and the signal-speed maxima;
+        // the barrier waits for this workgroup's atomics to complete)
         __syncthreads();
-        for (int off = 1; off < kCompactThreads; off <<= 1) { // inclusive scan
-            const int v = t >= off ? scan[t - off] : 0;
+        if (t == 0) sh_last = atomicAdd(&ctr[2], 1u) == gridDim.x - 1;
+        __syncthreads();
+        if (sh_last) {
+            __threadfence(); // acquire: no stale cached copies of the problem states
+            for (int p = t; p < nprob; p += BLK) finish_problem(PP[p], PS[p], 1);
+            if (t < 3) ctr[t] = 0u;
+            __threadfence();
             __syncthreads();
-            scan[t] += v;
-            __syncthreads();
+            compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
         }
-        const int dst = base + scan[t] - c;
-        for (int i = 0; i < c; ++i) act[dst + i] = all[first[p] + i];
-        base += scan[kCompactThreads - 1];
-        __syncthreads(); // scan[] reuse by the next chunk
     }
-    if (t == 0) *nact = base;
 }
 
 // maximum signal speed of the current state (start of a run)
@@ -389,46 +465,6 @@ __global__ void __launch_bounds__(kBlock1D) signal1d_kernel(const ProbParam* __r
         else s = (fabs(U) + sqrt(P.gamma * p / rho)) / P.dx;
     }
     block_max_atomic(s, &S.smax);
-}
-
-// ---------------------------------------------------------------------------
-// Per-problem step bookkeeping (one thread per problem).
-//   commit = 1: the step just run is accepted (flip buffers, advance t) or,
-//               after an error, the problem stops with W^n kept.
-//   Then the next dt follows from the maximum signal speed of the state.
-// ---------------------------------------------------------------------------
-__global__ void finish_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob, int commit,
-                              unsigned* __restrict__ ctr)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ctr && p < 2) ctr[p] = 0u; // work counters of the persistent stage kernels
-    if (p >= nprob) return;
-    const ProbParam& P = PP[p];
-    ProbState& S = PS[p];
-    if (!S.active) return;
-    if (S.err) {
-        S.active = 0;
-        return;
-    }
-    if (commit) {
-        S.cur = 1 - S.cur;
-        S.t = S.last ? P.t_end : S.t + S.dt;
-        S.nsteps += 1;
-    }
-    const double smax = bits_to_double(S.smax);
-    S.smax = 0ull;
-    if (!(S.t < P.t_end)) {
-        S.active = 0;
-        return;
-    }
-    double dt = P.dt_fixed > 0.0 ? P.dt_fixed : P.cfl / smax;
-    int last = 0;
-    if (S.t + dt >= P.t_end - 1e-9 * dt) {
-        dt = P.t_end - S.t;
-        last = 1;
-    }
-    S.dt = dt;
-    S.last = last;
 }
 
 // ---------------------------------------------------------------------------
