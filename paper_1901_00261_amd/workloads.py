@@ -102,6 +102,77 @@ def riemann_1d(n, left, right, *, x0=0.5, order=8, recon=1, gamma=1.4, cfl=0.3, 
                    (1, 1, 0, 0), W, Wx, None, name="riemann1d")
 
 
+def _cell_quadrature_1d(fn, n, xlo, xhi):
+    """Cell averages of fn(x) -> [..., nv] (8-point Gauss-Legendre per cell)
+    and the exact cell-averaged gradient (fn at the faces over dx)."""
+    dx = (xhi - xlo) / n
+    xc = xlo + dx * (np.arange(n) + 0.5)
+    pts = xc[:, None] + 0.5 * dx * _GL_X[None, :]
+    avg = np.einsum("q,nqk->nk", 0.5 * _GL_W, fn(pts))
+    xf = xlo + dx * np.arange(n + 1)
+    Wf = fn(xf)
+    return avg, (Wf[1:] - Wf[:-1]) / dx
+
+
+def shu_osher_1d(n=200, *, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=1.8):
+    """Shock / density-wave interaction (Sec. 4.2): (rho, U, p) =
+    (3.857134, 2.629369, 10.33333) for x <= 1 and (1 + 0.2 sin 5x, 0, 1)
+    beyond, on [0, 10]; non-reflecting (extrapolated) ends.  With n a
+    multiple of 10 the shock sits on a face."""
+    xlo, xhi = 0.0, 10.0
+    left = (3.857134, 2.629369, 10.33333)
+
+    def fn(x):
+        post = x <= 1.0
+        rho = np.where(post, left[0], 1.0 + 0.2 * np.sin(5.0 * x))
+        U = np.where(post, left[1], 0.0)
+        p = np.where(post, left[2], 1.0)
+        return prim_to_cons(rho, U, p, gamma)
+
+    W, Wx = _cell_quadrature_1d(fn, n, xlo, xhi)
+    dx = (xhi - xlo) / n
+    jshock = int(round((1.0 - xlo) / dx))
+    Wx[:jshock] = 0.0  # constant post-shock state
+    # the face values at the shock face mix the two sides: the first
+    # pre-shock cell's gradient comes from its own (smooth) side only
+    xa, xb = xlo + jshock * dx, xlo + (jshock + 1) * dx
+    Wa = prim_to_cons(1.0 + 0.2 * np.sin(5.0 * xa), 0.0, 1.0, gamma)
+    Wb = prim_to_cons(1.0 + 0.2 * np.sin(5.0 * xb), 0.0, 1.0, gamma)
+    Wx[jshock] = (Wb - Wa) / dx
+    return Problem(1, n, 1, xlo, xhi, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   (1, 1, 0, 0), W, Wx, None, name=f"shu_osher_n{n}")
+
+
+ACOUSTIC = dict(eps=1e-5, omega=6.0 * math.pi, rho_inf=1.1771, p_inf=101325.0)
+
+
+def acoustic_1d(n, *, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=0.01, eps=ACOUSTIC["eps"],
+                omega=ACOUSTIC["omega"], rho_inf=ACOUSTIC["rho_inf"], p_inf=ACOUSTIC["p_inf"]):
+    """Linear acoustic wave (Sec. 4.3, after Bai et al.): U = eps a cos(w x),
+    rho = rho_inf (1 + eps cos 2 w x), p = p_inf (rho/rho_inf)^gamma on
+    [0, 1/3], periodic; exact cell averages of the conservative variables and
+    of their gradients."""
+    a = math.sqrt(gamma * p_inf / rho_inf)
+
+    def fn(x):
+        rho = rho_inf * (1.0 + eps * np.cos(2.0 * omega * x))
+        return prim_to_cons(rho, eps * a * np.cos(omega * x), p_inf * (rho / rho_inf) ** gamma, gamma)
+
+    W, Wx = _cell_quadrature_1d(fn, n, 0.0, 1.0 / 3.0)
+    return Problem(1, n, 1, 0.0, 1.0 / 3.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   (0, 0, 0, 0), W, Wx, None, name=f"acoustic1d_n{n}")
+
+
+def acoustic_linear_rho(x, t, *, gamma=1.4, eps=ACOUSTIC["eps"], omega=ACOUSTIC["omega"],
+                        rho_inf=ACOUSTIC["rho_inf"], p_inf=ACOUSTIC["p_inf"]):
+    """The linear-acoustics solution for the density of acoustic_1d (two
+    counter-propagating pairs of waves); exact for the linearised equations."""
+    a = math.sqrt(gamma * p_inf / rho_inf)
+    xm, xp = x - a * t, x + a * t
+    return rho_inf + 0.5 * eps * rho_inf * (np.cos(2 * omega * xm) + np.cos(2 * omega * xp)
+                                            + np.cos(omega * xm) - np.cos(omega * xp))
+
+
 def random_riemann_states(seed):
     """(rho_L, u_L, p_L), (rho_R, u_R, p_R): rho ~ U[0.1, 1], u ~ U[-1, 1],
     p ~ U[0.1, 1], drawn in that order from PCG64(seed)."""
