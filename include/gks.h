@@ -38,7 +38,12 @@ enum {
     GKS_ENONPHYS = -4, /* a non-physical state (rho <= 0 or p <= 0) was met */
     GKS_ESTATE = -5    /* handle unusable after a device fault */
 };
-enum { GKS_BC_PERIODIC = 0, GKS_BC_EXTRAP = 1 };
+/* Boundary conditions, per side.  Periodic: wrap (both sides of a direction).
+   Extrapolated (the paper's non-reflecting ends): ghost cells copy the
+   boundary cell with zero normal slope.  Reflecting wall: ghost cells are the
+   mirror image of the interior (normal momentum negated; normal slopes of
+   the other variables negated). */
+enum { GKS_BC_PERIODIC = 0, GKS_BC_EXTRAP = 1, GKS_BC_REFLECT = 2 };
 enum { GKS_RECON_LINEAR = 0, GKS_RECON_WENOZ = 1 };
 enum { GKS_PREC_FP64 = 0, GKS_PREC_FP32_MIXED = 1 };
 

@@ -757,12 +757,17 @@ typedef struct {
 
 #define CELL(P, i, j) (((size_t)((j) + (P)->gy) * (P)->sx + (size_t)((i) + (P)->gx)) * (P)->nv)
 
-enum { BC_PERIODIC = 0, BC_EXTRAP = 1 };
+enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2 };
 
 /* Two ghost layers per side.  Periodic: wrap.  Extrapolated (reading A16):
    ghost average = boundary average, ghost normal slope = 0, ghost
    tangential slope = boundary tangential slope.  x first (interior rows),
    then y over all columns so that corners are filled. */
+/* Ghost cells.  Periodic: wrap.  Extrapolated: copy of the boundary cell
+   with zero normal slope.  Reflecting wall: the mirror image of the field,
+   W_g(x) = M W(2 x_w - x) with M negating the normal momentum, so a ghost
+   holds M times the mirrored cell's average, M times its tangential
+   gradient and -M times its normal gradient. */
 static void fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy)
 {
     int nv = P->nv;
@@ -770,13 +775,16 @@ static void fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy)
         for (int g = 1; g <= P->gx; ++g) {
             int dst[2] = {-g, P->nx - 1 + g};
             for (int side = 0; side < 2; ++side) {
-                int per = P->bc[side] == BC_PERIODIC;
-                int src = per ? (side == 0 ? P->nx - g : g - 1) : (side == 0 ? 0 : P->nx - 1);
+                int bc = P->bc[side];
+                int src = bc == BC_PERIODIC ? (side == 0 ? P->nx - g : g - 1)
+                        : bc == BC_REFLECT  ? (side == 0 ? g - 1 : P->nx - g)
+                                            : (side == 0 ? 0 : P->nx - 1);
                 size_t d = CELL(P, dst[side], j), s = CELL(P, src, j);
                 for (int k = 0; k < nv; ++k) {
-                    W[d + k] = W[s + k];
-                    Wx[d + k] = per ? Wx[s + k] : 0.0;
-                    if (Wy) Wy[d + k] = Wy[s + k];
+                    double m = (bc == BC_REFLECT && k == 1) ? -1.0 : 1.0;
+                    W[d + k] = m * W[s + k];
+                    Wx[d + k] = bc == BC_PERIODIC ? Wx[s + k] : (bc == BC_REFLECT ? -m * Wx[s + k] : 0.0);
+                    if (Wy) Wy[d + k] = m * Wy[s + k];
                 }
             }
         }
@@ -785,13 +793,16 @@ static void fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy)
         for (int g = 1; g <= P->gy; ++g) {
             int dst[2] = {-g, P->ny - 1 + g};
             for (int side = 0; side < 2; ++side) {
-                int per = P->bc[2 + side] == BC_PERIODIC;
-                int src = per ? (side == 0 ? P->ny - g : g - 1) : (side == 0 ? 0 : P->ny - 1);
+                int bc = P->bc[2 + side];
+                int src = bc == BC_PERIODIC ? (side == 0 ? P->ny - g : g - 1)
+                        : bc == BC_REFLECT  ? (side == 0 ? g - 1 : P->ny - g)
+                                            : (side == 0 ? 0 : P->ny - 1);
                 size_t d = CELL(P, i, dst[side]), s = CELL(P, i, src);
                 for (int k = 0; k < nv; ++k) {
-                    W[d + k] = W[s + k];
-                    Wx[d + k] = Wx[s + k];
-                    Wy[d + k] = per ? Wy[s + k] : 0.0;
+                    double m = (bc == BC_REFLECT && k == 2) ? -1.0 : 1.0;
+                    W[d + k] = m * W[s + k];
+                    Wx[d + k] = m * Wx[s + k];
+                    Wy[d + k] = bc == BC_PERIODIC ? Wy[s + k] : (bc == BC_REFLECT ? -m * Wy[s + k] : 0.0);
                 }
             }
         }

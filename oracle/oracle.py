@@ -12,7 +12,7 @@ from . import build as _build
 
 _lib = None
 
-PERIODIC, EXTRAP = 0, 1
+PERIODIC, EXTRAP, REFLECT = 0, 1, 2
 LINEAR, WENOZ = 0, 1
 
 

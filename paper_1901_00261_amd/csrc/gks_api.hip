@@ -143,7 +143,8 @@ int validate(const gks_problem* pr, int32_t nprob, int32_t precision)
         if (q.recon != GKS_RECON_LINEAR && q.recon != GKS_RECON_WENOZ) return bad("unknown recon");
         const int nb = dim == 2 ? 4 : 2;
         for (int k = 0; k < nb; ++k)
-            if (q.bc[k] != GKS_BC_PERIODIC && q.bc[k] != GKS_BC_EXTRAP) return bad("unknown boundary condition");
+            if (q.bc[k] != GKS_BC_PERIODIC && q.bc[k] != GKS_BC_EXTRAP && q.bc[k] != GKS_BC_REFLECT)
+                return bad("unknown boundary condition");
         for (int k = 0; k < nb; k += 2)
             if ((q.bc[k] == GKS_BC_PERIODIC) != (q.bc[k + 1] == GKS_BC_PERIODIC))
                 return bad("periodic boundaries must be paired");

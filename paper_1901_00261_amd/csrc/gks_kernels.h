@@ -13,7 +13,7 @@
 //     [28][rows][faces].
 // Ghost cells are never stored: stencil gathers map indices through the
 // boundary condition (periodic wrap; extrapolation = copy of the boundary
-// cell with the normal slope set to zero).
+// cell with the normal slope set to zero; reflecting wall = mirror image).
 #pragma once
 
 #include "gks_math.h"
@@ -45,22 +45,50 @@ struct Tile {
 
 constexpr int kBlock1D = 128;
 
-// cell index through the boundary condition; zero: the normal slope of a
-// ghost cell of an extrapolated side
-__device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi, bool& zero)
+// Cell index through the boundary condition.  kind: 0 interior or
+// periodic; 1 ghost of an extrapolated side (copy of the boundary cell,
+// normal slope 0); 2 ghost of a reflecting wall (mirror image: the mirrored
+// cell with its normal momentum negated, its normal slopes negated except
+// that of the normal momentum).
+enum : int { kGhostNone = 0, kGhostCopy = 1, kGhostMirror = 2 };
+__device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi, int& kind)
 {
-    zero = false;
+    kind = kGhostNone;
     if (c < 0) {
         if (bc_lo == 0) return c + n;
-        zero = true;
+        if (bc_lo == 2) {
+            kind = kGhostMirror;
+            return -1 - c;
+        }
+        kind = kGhostCopy;
         return 0;
     }
     if (c >= n) {
         if (bc_hi == 0) return c - n;
-        zero = true;
+        if (bc_hi == 2) {
+            kind = kGhostMirror;
+            return 2 * n - 1 - c;
+        }
+        kind = kGhostCopy;
         return n - 1;
     }
     return c;
+}
+
+// Local-frame stencil entry (slot 1 = normal momentum, slot 2 = tangential
+// momentum in 2-D) of a cell reached through map_index along the normal
+// (kn) and the transverse (kt) direction: values w, normal slopes d.
+__device__ __forceinline__ void ghost_frame(int kn, int kt, double (&w)[4], double (&d)[4])
+{
+    if (kn == kGhostCopy) d[0] = d[1] = d[2] = d[3] = 0.0;
+    if (kn == kGhostMirror) {
+        w[1] = -w[1];
+        d[0] = -d[0]; d[2] = -d[2]; d[3] = -d[3];
+    }
+    if (kt == kGhostMirror) {
+        w[2] = -w[2];
+        d[2] = -d[2];
+    }
 }
 
 // Two-stage MSMD combinations (Sec. 2.2) with the fused multiply-adds
@@ -334,16 +362,13 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
             double Wk[4][4], Dk[4][4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                bool zero;
-                const int c = map_index(f - 2 + q, P.nx, P.bc[0], P.bc[1], zero);
-                Wk[q][0] = Wb[c];
-                Wk[q][1] = Wb[Ntot + c];
-                Wk[q][2] = 0.0;
-                Wk[q][3] = Wb[2 * Ntot + c];
-                Dk[q][0] = zero ? 0.0 : P.dx * Xb[c];
-                Dk[q][1] = zero ? 0.0 : P.dx * Xb[Ntot + c];
-                Dk[q][2] = 0.0;
-                Dk[q][3] = zero ? 0.0 : P.dx * Xb[2 * Ntot + c];
+                int kind;
+                const int c = map_index(f - 2 + q, P.nx, P.bc[0], P.bc[1], kind);
+                double w[4] = {Wb[c], Wb[Ntot + c], 0.0, Wb[2 * Ntot + c]};
+                double d[4] = {P.dx * Xb[c], P.dx * Xb[Ntot + c], 0.0, P.dx * Xb[2 * Ntot + c]};
+                ghost_frame(kind, kGhostNone, w, d);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { Wk[q][k] = w[k]; Dk[q][k] = d[k]; }
             }
             double o[7][4];
             auto put = [&](int q, int k, double v) { o[q][k] = v; };
@@ -500,24 +525,27 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
     const double* Nb = (DIR == 0 ? Wx : Wy) + (size_t)buf * 4 * plane;
     const double h = DIR == 0 ? P.dx : P.dy;
     double Wk[4][4], Dk[4][4];
-    bool zt;
-    const int t = DIR == 0 ? map_index(tr, ny, P.bc[2], P.bc[3], zt) : map_index(tr, nx, P.bc[0], P.bc[1], zt);
+    // ghost rows (transverse direction): extrapolated rows are copies with
+    // their normal slopes; mirrored rows negate the transverse momentum
+    int kt;
+    const int t = DIR == 0 ? map_index(tr, ny, P.bc[2], P.bc[3], kt) : map_index(tr, nx, P.bc[0], P.bc[1], kt);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        bool zn;
-        const int c = DIR == 0 ? map_index(face - 2 + q, nx, P.bc[0], P.bc[1], zn)
-                               : map_index(face - 2 + q, ny, P.bc[2], P.bc[3], zn);
+        int kn;
+        const int c = DIR == 0 ? map_index(face - 2 + q, nx, P.bc[0], P.bc[1], kn)
+                               : map_index(face - 2 + q, ny, P.bc[2], P.bc[3], kn);
         const size_t cell = DIR == 0 ? (size_t)t * nx + c : (size_t)c * nx + t;
         double w[4], d[4];
+        // local frame: normal momentum in slot 1, tangential in slot 2
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            w[k] = Wb[k * plane + cell];
-            d[k] = zn ? 0.0 : h * Nb[k * plane + cell];
+            const int g = (DIR == 1 && (k == 1 || k == 2)) ? 3 - k : k;
+            w[k] = Wb[g * plane + cell];
+            d[k] = h * Nb[g * plane + cell];
         }
-        // local frame: normal velocity in slot 1
-        Wk[q][0] = w[0]; Wk[q][3] = w[3]; Dk[q][0] = d[0]; Dk[q][3] = d[3];
-        Wk[q][1] = DIR == 0 ? w[1] : w[2]; Wk[q][2] = DIR == 0 ? w[2] : w[1];
-        Dk[q][1] = DIR == 0 ? d[1] : d[2]; Dk[q][2] = DIR == 0 ? d[2] : d[1];
+        ghost_frame(kn, kt, w, d);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { Wk[q][k] = w[k]; Dk[q][k] = d[k]; }
     }
     const size_t AB = (size_t)A * B, ab = (size_t)a * B + b;
     auto put = [&](int q, int k, double v) { R[(q * 4 + k) * AB + ab] = v; };

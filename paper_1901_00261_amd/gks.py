@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgks.so")
 GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EDEVICE, GKS_ENONPHYS, GKS_ESTATE = 0, -1, -2, -3, -4, -5
 PREC_FP64, PREC_FP32_MIXED = 0, 1
 KERNEL_FLUX, KERNEL_ROW, KERNEL_CELL = 0, 1, 2
+BC_PERIODIC, BC_EXTRAP, BC_REFLECT = 0, 1, 2
 
 
 class GksError(RuntimeError):

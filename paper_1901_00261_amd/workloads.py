@@ -52,7 +52,7 @@ class Problem:
     t_end: float
     order: int
     recon: int  # 0 linear, 1 WENO-Z
-    bc: tuple   # (xlo, xhi, ylo, yhi): 0 periodic, 1 extrapolated
+    bc: tuple   # (xlo, xhi, ylo, yhi): 0 periodic, 1 extrapolated, 2 reflecting wall
     W: np.ndarray = field(repr=False)
     Wx: np.ndarray = field(repr=False)
     Wy: np.ndarray | None = field(repr=False, default=None)
@@ -312,3 +312,41 @@ def riemann_2d(n, *, ny=None, seed=5, states=None, order=8, recon=1, gamma=1.4, 
     Z = np.zeros_like(W)
     return Problem(2, n, ny, 0.0, 1.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
                    (1, 1, 1, 1), W, Z, Z.copy(), name=f"riemann2d_{n}x{ny}")
+
+
+def pulse_box_2d(n, *, ny=None, bc=(2, 2, 2, 2), mu=0.0, gamma=1.4, order=8, recon=1, cfl=0.3, t_end=1e9,
+                 xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0):
+    """Smooth off-centre pressure / density pulse with a swirl on the unit
+    box (reflecting walls by default, any boundary combination allowed):
+    rho = 1 + 0.2 G, p = 1 + 0.5 G, (u, v) = 0.2 G (-(y - 0.55), x - 0.4)/0.15,
+    G = exp(-((x - 0.4)^2 + (y - 0.55)^2) / 0.03); exact cell averages and
+    cell-averaged gradients."""
+    ny = n if ny is None else ny
+
+    def fn(X, Y):
+        G = np.exp(-((X - 0.4) ** 2 + (Y - 0.55) ** 2) / 0.03)
+        rho = 1.0 + 0.2 * G
+        u = -0.2 * G * (Y - 0.55) / 0.15
+        v = 0.2 * G * (X - 0.4) / 0.15
+        return prim_to_cons(rho, u, 1.0 + 0.5 * G, gamma, V=v)
+
+    W, Wx, Wy = _cell_quadrature_2d(fn, n, ny, xlo, xhi, ylo, yhi)
+    return Problem(2, n, ny, xlo, xhi, ylo, yhi, gamma, mu, cfl, 0.0, t_end, order, recon,
+                   tuple(bc), W, Wx, Wy, name=f"pulse2d_{n}x{ny}")
+
+
+def mirror_pair_1d(n, *, gamma=1.4, order=8, recon=1, cfl=0.3, t_end=0.5):
+    """Data symmetric about x = 1 on the periodic [0, 2] (2n cells) and the
+    same data on [1, 2] (n cells) between two reflecting walls: the walls'
+    solution is the right half of the periodic one."""
+    def fn(x):
+        rho = 1.0 + 0.2 * np.cos(np.pi * x)
+        return prim_to_cons(rho, 0.1 * np.sin(np.pi * x), 1.0 + 0.1 * np.cos(np.pi * x), gamma)
+
+    Wf, Wxf = _cell_quadrature_1d(fn, 2 * n, 0.0, 2.0)
+    Wh, Wxh = _cell_quadrature_1d(fn, n, 1.0, 2.0)
+    full = Problem(1, 2 * n, 1, 0.0, 2.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon, (0, 0, 0, 0),
+                   Wf, Wxf, None, name=f"mirror_full_n{2 * n}")
+    half = Problem(1, n, 1, 1.0, 2.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon, (2, 2, 0, 0),
+                   Wh, Wxh, None, name=f"mirror_walls_n{n}")
+    return full, half

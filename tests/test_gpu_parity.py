@@ -247,3 +247,42 @@ def test_acoustic_wave(n, t_end):
     # rounding of the 2.5e5-sized energy at every step, relative to a 1e-5
     # perturbation: measured 5e-10 (10 crossings) to 9e-9 (1000 crossings)
     assert e_w <= 1e-7 and e_x <= 1e-6
+
+
+def test_reflecting_walls_1d():
+    """Reflecting walls (mirror ghosts) through the C ABI: the two-wall
+    problem against the oracle, and against the right half of its periodic
+    mirror image run on the GPU."""
+    full, half = wl.mirror_pair_1d(40)
+    got_h, got_f = gpu_run([half])[0], gpu_run([full])[0]
+    check(half, got_h, oracle_run(half))
+    assert np.abs(got_f[0][40:] - got_h[0]).max() < 1e-13
+    assert np.abs(got_f[1][40:] - got_h[1]).max() < 1e-11
+
+
+@pytest.mark.parametrize("bc", [(2, 2, 2, 2), (2, 1, 0, 0), (1, 2, 2, 1)])
+def test_reflecting_walls_2d(bc):
+    """Swirling pulse in a box with walls on all sides, and mixed wall /
+    extrapolated / periodic boundaries, against the oracle after 6 steps."""
+    p = wl.pulse_box_2d(24, ny=20, bc=bc)
+    g = gks()
+    S = g.Solver(p)
+    S.step(6)
+    got = S.state(0)
+    S.close()
+    check(p, got, oracle_run(p, max_steps=6))
+
+
+def test_batch_with_mixed_boundaries_equals_solo():
+    """One handle holding problems with periodic, extrapolated and
+    reflecting ends gives each problem's solo result."""
+    _, half = wl.mirror_pair_1d(30)
+    probs = [half, wl.sine_wave_1d(24, order=8, recon=1, t_end=0.5), wl.riemann_1d(50, *wl.SOD, t_end=0.05)]
+    r = wl.riemann_1d(60, *wl.SOD, t_end=0.05)
+    r.bc = (2, 1, 0, 0)
+    probs.append(r)
+    batch = gpu_run(probs)
+    for p, b in zip(probs, batch):
+        solo = gpu_run([p])[0]
+        assert np.array_equal(solo[0], b[0]) and np.array_equal(solo[1], b[1]) and solo[4] == b[4], p.name
+        check(p, b, oracle_run(p))

@@ -651,3 +651,51 @@ def test_shu_osher_invariants():
     ahead = (x > x[drop] + 0.2) & (x < 7.85)
     assert ahead.sum() >= 3
     assert np.abs(rho[ahead] - p.W[ahead, 0]).max() < 1e-3
+
+
+# ---------------------------------------------------------------- reflecting walls (blast-wave boundaries)
+def test_reflecting_wall_is_mirror_image_1d():
+    """A wall is the mirror image of the flow: data symmetric about x = 1 on
+    the periodic [0, 2] evolve exactly like the same data on [1, 2] between
+    two reflecting walls (up to the rounding of the mirrored reconstructions),
+    and the walls conserve mass and energy."""
+    full, half = wl.mirror_pair_1d(40)
+    f = oracle.run(1, full.W, full.Wx, **full.oracle_kwargs())
+    h = oracle.run(1, half.W, half.Wx, **half.oracle_kwargs())
+    assert f[4] == h[4] and f[3] == h[3] == 0.5
+    assert np.abs(f[0][40:] - h[0]).max() < 1e-13
+    assert np.abs(f[1][40:] - h[1]).max() < 1e-11
+    for k in (0, 2):
+        assert abs(h[0][:, k].sum() - half.W[:, k].sum()) <= 1e-13 * half.W[:, k].sum()
+
+
+def test_reflecting_wall_is_mirror_image_2d():
+    """2-D: the pulse in the unit box with walls on all sides equals the
+    lower-left quarter of the same pulse mirrored into the periodic box
+    [0, 2]^2 (mirror images across x = 1 and y = 1), for a few steps."""
+    n = 12
+    box = wl.pulse_box_2d(n, ny=n)
+    M = np.array([1.0, -1.0, 1.0, 1.0]), np.array([1.0, 1.0, -1.0, 1.0])
+
+    def mirror(a, which, negate_normal_slope):
+        # which: 0 mirror across x = 1 (axis 1), 1 across y = 1 (axis 0)
+        m = M[which] * (-1.0 if negate_normal_slope else 1.0)
+        return np.flip(a, axis=1 - which) * m
+
+    def big(a, sx, sy):
+        """Assemble the periodic [0,2]^2 field from the quarter; sx/sy: this
+        array is the x / y slope (its sign flips across the matching mirror)."""
+        right = mirror(a, 0, sx)
+        lower = np.concatenate([a, right], axis=1)
+        upper = mirror(lower, 1, sy)
+        return np.ascontiguousarray(np.concatenate([lower, upper], axis=0))
+
+    W2, Wx2, Wy2 = big(box.W, False, False), big(box.Wx, True, False), big(box.Wy, False, True)
+    kw = {**box.oracle_kwargs(), "max_steps": 4}
+    b = oracle.run(2, box.W, box.Wx, box.Wy, **kw)
+    p = oracle.run(2, W2, Wx2, Wy2, **{**kw, "xhi": 2.0, "yhi": 2.0, "bc": (0, 0, 0, 0)})
+    assert b[4] == p[4] == 4 and abs(b[3] - p[3]) < 1e-15
+    assert np.abs(p[0][:n, :n] - b[0]).max() < 1e-13
+    assert np.abs(p[1][:n, :n] - b[1]).max() < 1e-11 and np.abs(p[2][:n, :n] - b[2]).max() < 1e-11
+    for k in (0, 3):
+        assert abs(b[0][..., k].sum() - box.W[..., k].sum()) <= 1e-13 * box.W[..., k].sum()
