@@ -20,6 +20,10 @@
  *     Separate handles are independent.
  *   - All device work runs on the stream given to gks_init (a hipStream_t;
  *     NULL means the library creates its own default-priority stream).
+ *   - The library links the HIP runtime by its soname (libamdhip64.so.7).  In
+ *     a process that also uses another copy of the runtime (PyTorch bundles
+ *     one), load that copy first so that this library binds to it: streams
+ *     and device buffers are then shared by one runtime.
  */
 #ifndef GKS_H
 #define GKS_H

@@ -233,7 +233,10 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
     const int gc = tiles(nx, ny, bc);
     for (int stage = 1; stage <= 2; ++stage) {
         record(h, st, 1, true);
-        gks::row2d_kernel<T, 0><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
+        if (P.order == 8)
+            gks::row2d_kernel<T, 0, 8><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
+        else
+            gks::row2d_kernel<T, 0, 6><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
         record(h, st, 1, false);
         record(h, st, 0, true);
         if (stage == 1)
@@ -242,7 +245,10 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
             gks::gp2d_kernel<T, 0, 2><<<ggx, bg, 0, st>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
         record(h, st, 0, false);
         record(h, st, 1, true);
-        gks::row2d_kernel<T, 1><<<gry, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
+        if (P.order == 8)
+            gks::row2d_kernel<T, 1, 8><<<gry, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
+        else
+            gks::row2d_kernel<T, 1, 6><<<gry, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
         record(h, st, 1, false);
         record(h, st, 0, true);
         if (stage == 1)

@@ -495,12 +495,13 @@ __global__ void __launch_bounds__(kBlock1D) signal1d_kernel(const ProbParam* __r
 // ---------------------------------------------------------------------------
 // 2-D.  DIR 0: x faces, DIR 1: y faces (local frame swaps slots 1 and 2).
 // Face-row kernel: one thread per (face, transverse row incl. two ghost rows
-// per side); stores the seven reconstructed vectors of face_recon.
+// per side); stores the seven reconstructed vectors of face_recon.  ORDER
+// (6 or 8) is the problem's, chosen at launch.
 // Row buffer R[28][A][B], thread-x index b fastest:
 //   DIR 0: a = row + 2 (ny + 4 rows), b = face (nx + 1)
 //   DIR 1: a = face (ny + 1), b = column + 2 (nx + 4)
 // ---------------------------------------------------------------------------
-template <typename T, int DIR>
+template <typename T, int DIR, int ORDER>
 __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
                                                     const double* __restrict__ W, const double* __restrict__ Wx,
                                                     const double* __restrict__ Wy, int stage, double* __restrict__ R)
@@ -549,8 +550,7 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
     }
     const size_t AB = (size_t)A * B, ab = (size_t)a * B + b;
     auto put = [&](int q, int k, double v) { R[(q * 4 + k) * AB + ab] = v; };
-    const bool ok = (P.order == 8) ? face_recon<T, 2, 8>(Wk, Dk, h, P.gamma, P.recon != 0, put)
-                                   : face_recon<T, 2, 6>(Wk, Dk, h, P.gamma, P.recon != 0, put);
+    const bool ok = face_recon<T, 2, ORDER>(Wk, Dk, h, P.gamma, P.recon != 0, put);
     if (!ok) S.err = 1;
 }
 

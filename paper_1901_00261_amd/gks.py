@@ -42,6 +42,15 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime under the same soname.  Loaded
+        # first, it is the runtime this library binds to, so the process has
+        # one runtime and PyTorch's device buffers and streams are valid here;
+        # loaded after this library, PyTorch would start a second runtime,
+        # whose GPU initialisation fails.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         pp = C.POINTER(C.POINTER(C.c_double))
         hnd = C.c_void_p
@@ -143,6 +152,12 @@ class Solver:
         self._check(lib().gks_state(self.h, p, W.ctypes.data, Wx.ctypes.data,
                                     Wy.ctypes.data if Wy is not None else None, C.byref(t), C.byref(n)))
         return W, Wx, Wy, t.value, n.value
+
+    def state_device(self, p, W_ptr, Wx_ptr, Wy_ptr=None):
+        """Copy problem p into caller-owned device buffers (addresses as ints,
+        layout as the host arrays of state())."""
+        self._check(lib().gks_state_device(self.h, p, C.c_void_p(W_ptr), C.c_void_p(Wx_ptr),
+                                           C.c_void_p(Wy_ptr) if Wy_ptr else None))
 
     def status(self, p=0):
         s = C.c_int32(0)

@@ -8,6 +8,14 @@ TESTS = os.path.dirname(os.path.abspath(__file__))
 if TESTS not in sys.path:
     sys.path.insert(0, TESTS)
 
+# PyTorch's bundled HIP runtime must be loaded before libgks.so (which binds
+# to the first runtime of its soname in the process); some tests load the
+# library directly with ctypes, so load PyTorch at session start.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")

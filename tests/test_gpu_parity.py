@@ -286,3 +286,34 @@ def test_batch_with_mixed_boundaries_equals_solo():
         solo = gpu_run([p])[0]
         assert np.array_equal(solo[0], b[0]) and np.array_equal(solo[1], b[1]) and solo[4] == b[4], p.name
         check(p, b, oracle_run(p))
+
+
+def test_device_pointer_entry_points_with_torch_stream():
+    """gks_init_device / gks_state_device with torch-owned device buffers on
+    torch's current stream give the same results as the host entry points,
+    for a 2-D problem and a 1-D batch."""
+    import torch
+    g = gks()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    p2 = wl.pulse_box_2d(20, ny=16, bc=(2, 1, 0, 0))
+    b1 = [wl.sine_wave_1d(16, order=8, recon=1), wl.riemann_1d(40, *wl.SOD, t_end=0.05)]
+    for probs in ([p2], b1):
+        host = g.Solver(probs)
+        host.step(5)
+        want = [host.state(k) for k in range(len(probs))]
+        host.close()
+        ts = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) if a is not None else None
+               for a in (p.W, p.Wx, p.Wy)] for p in probs]
+        torch.cuda.synchronize()
+        S = g.Solver(probs, stream=stream,
+                     device_arrays=[tuple(t.data_ptr() if t is not None else 0 for t in tt) for tt in ts])
+        S.step(5)
+        for k, p in enumerate(probs):
+            outs = [torch.empty_like(t) if t is not None else None for t in ts[k]]
+            S.state_device(k, outs[0].data_ptr(), outs[1].data_ptr(), outs[2].data_ptr() if outs[2] is not None else 0)
+            torch.cuda.synchronize()
+            assert np.array_equal(outs[0].cpu().numpy(), want[k][0]) and np.array_equal(outs[1].cpu().numpy(), want[k][1])
+            if outs[2] is not None:
+                assert np.array_equal(outs[2].cpu().numpy(), want[k][2])
+        S.close()
