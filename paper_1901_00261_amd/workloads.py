@@ -350,3 +350,16 @@ def mirror_pair_1d(n, *, gamma=1.4, order=8, recon=1, cfl=0.3, t_end=0.5):
     half = Problem(1, n, 1, 1.0, 2.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon, (2, 2, 0, 0),
                    Wh, Wxh, None, name=f"mirror_walls_n{n}")
     return full, half
+
+
+def sine_wave_2d(n, *, order=6, recon=0, gamma=1.4, cfl=0.3, dt_fixed=0.0, t_end=2.0, amp=0.2):
+    """2-D analogue of the accuracy test of Sec. 4.1: rho = 1 + amp sin(pi (x + y)),
+    U = V = 1, p = 1 on the periodic [0, 2]^2; the exact solution translates
+    along the diagonal (period 2 in time).  Exact cell averages and gradients."""
+    def fn(X, Y):
+        rho = 1.0 + amp * np.sin(np.pi * (X + Y))
+        return prim_to_cons(rho, 1.0, 1.0, gamma, V=1.0)
+
+    W, Wx, Wy = _cell_quadrature_2d(fn, n, n, 0.0, 2.0, 0.0, 2.0)
+    return Problem(2, n, n, 0.0, 2.0, 0.0, 2.0, gamma, 0.0, cfl, dt_fixed, t_end, order, recon,
+                   (0, 0, 0, 0), W, Wx, Wy, name=f"sine2d_n{n}")
