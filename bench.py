@@ -366,8 +366,8 @@ def study_equal_l1(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the scheme's single-GPU path); "
-              "--gpus must be 1", file=sys.stderr)
+        print("bench.py: measures the single-GPU path only; --gpus must be 1 "
+              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 

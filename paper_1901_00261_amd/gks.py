@@ -37,11 +37,11 @@ _lib = None
 
 
 def lib():
-    """Load libgks.so (built by __graft_entry__.build()); raise if absent."""
+    """Load libgks.so (built by paper_1901_00261_amd/build.py); raise if absent."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run python paper_1901_00261_amd/build.py)")
         # PyTorch ships its own HIP runtime under the same soname.  Loaded
         # first, it is the runtime this library binds to, so the process has
         # one runtime and PyTorch's device buffers and streams are valid here;

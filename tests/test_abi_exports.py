@@ -26,7 +26,7 @@ def test_header_declares_the_step_api():
 def test_library_exports_every_declared_function():
     from paper_1901_00261_amd import gks
     if not os.path.exists(gks.LIB_PATH):
-        pytest.fail("libgks.so is not built (run __graft_entry__.build())")
+        pytest.fail("libgks.so is not built (run python paper_1901_00261_amd/build.py)")
     lib = ctypes.CDLL(gks.LIB_PATH)
     missing = [n for n in declared() if not hasattr(lib, n)]
     assert not missing, missing
