@@ -40,3 +40,50 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(gks, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         gks.lib()
+
+
+def _struct(p):
+    from paper_1901_00261_amd import gks
+    return gks.to_struct(p)
+
+
+def test_host_validation_without_gpu():
+    """Argument checks run on the host before any HIP call: empty and
+    malformed problem sets return GKS_EINVAL with a message, and a valid
+    problem on a machine without a GPU returns GKS_EDEVICE (no compute)."""
+    import numpy as np
+    from paper_1901_00261_amd import gks, workloads as wl
+    L = gks.lib()
+    PD = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p()
+
+    def init(probs, arrays):
+        n = len(probs)
+        arr = (gks.gks_problem * max(n, 1))(*[_struct(p) for p in probs])
+        ptr = [(PD * max(n, 1))(*[a[k].ctypes.data_as(PD) if a[k] is not None else PD() for a in arrays])
+               for k in range(3)]
+        st = L.gks_init(arr, n, 0, ptr[0], ptr[1], ptr[2], None, ctypes.byref(h))
+        return st, L.gks_last_error(None).decode()
+
+    p = wl.sine_wave_1d(16)
+    arrays = [(p.W, p.Wx, None)]
+    st, msg = init([], [])
+    assert st == gks.GKS_EINVAL and "no problems" in msg
+    big = wl.Problem(2, 4400, 4400, 0.0, 1.0, 0.0, 1.0, 1.4, 0.0, 0.3, 0.0, 1.0, 8, 1, (0, 0, 0, 0),
+                     np.zeros(1), np.zeros(1), np.zeros(1))
+    st, msg = init([big], [(big.W, big.Wx, big.Wy)])
+    assert st == gks.GKS_EINVAL and "too large" in msg
+    two2d = [wl.isentropic_vortex_2d(8), wl.isentropic_vortex_2d(8)]
+    st, msg = init(two2d, [(q.W, q.Wx, q.Wy) for q in two2d])
+    assert st == gks.GKS_EINVAL and "exactly one" in msg
+    st, msg = init([p], [(p.W, None, None)])
+    assert st == gks.GKS_EINVAL and "missing" in msg
+    q = wl.sine_wave_1d(16)
+    q.bc = (0, 2, 0, 0)
+    st, msg = init([q], arrays)
+    assert st == gks.GKS_EINVAL and "paired" in msg
+    assert L.gks_step(None, 1, None) == gks.GKS_EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        st, msg = init([p], arrays)
+        assert st == gks.GKS_EDEVICE and "device" in msg
