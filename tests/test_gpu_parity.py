@@ -359,3 +359,26 @@ def test_free_stream_is_preserved_exactly(precision):
         W, Wx, Wy, t, n = S.state(0)
         S.close()
         assert n == 5 and np.array_equal(W, p.W) and not Wx.any() and (Wy is None or not Wy.any()), p.dim
+
+
+@pytest.mark.parametrize("gamma,mu,order,recon", [(5.0 / 3.0, 0.0, 8, 1), (1.4, 1e-2, 6, 1), (1.3, 5e-3, 8, 0)])
+def test_1d_gamma_and_viscosity(gamma, mu, order, recon):
+    """1-D Navier-Stokes (viscous terms through the physical collision time)
+    and gammas other than 1.4 (K = (3 - gamma)/(gamma - 1) internal degrees
+    of freedom), 60 cells of the sine wave to t = 0.3."""
+    p = wl.sine_wave_1d(60, order=order, recon=recon, gamma=gamma, t_end=0.3)
+    p.mu = mu
+    check(p, gpu_run([p])[0], oracle_run(p))
+
+
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.3])
+def test_2d_gamma(gamma):
+    """2-D with K = (4 - 2 gamma)/(gamma - 1): the swirling pulse, periodic
+    box, Navier-Stokes, 4 steps."""
+    p = wl.pulse_box_2d(20, ny=16, bc=(0, 0, 0, 0), mu=2e-3, gamma=gamma)
+    g = gks()
+    S = g.Solver(p)
+    S.step(4)
+    got = S.state(0)
+    S.close()
+    check(p, got, oracle_run(p, max_steps=4))
