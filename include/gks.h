@@ -40,7 +40,8 @@ enum {
     GKS_ENOMEM = -2,   /* device allocation failed */
     GKS_EDEVICE = -3,  /* HIP runtime error */
     GKS_ENONPHYS = -4, /* a non-physical state (rho <= 0 or p <= 0) was met */
-    GKS_ESTATE = -5    /* handle unusable after a device fault */
+    GKS_ESTATE = -5    /* handle unusable: a HIP runtime call failed on it earlier (that call returned
+                          GKS_EDEVICE or GKS_ENOMEM); only gks_free and gks_last_error remain useful */
 };
 /* Boundary conditions, per side.  Periodic: wrap (both sides of a direction).
    Extrapolated (the paper's non-reflecting ends): ghost cells copy the

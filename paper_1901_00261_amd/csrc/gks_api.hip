@@ -43,6 +43,7 @@ struct gks_handle {
     double* stage = nullptr; // transpose staging
     size_t stage_len = 0;
     std::string err;
+    bool dead = false; // a HIP call failed: the device state is not trusted any more
     bool timing = false;
     std::vector<EventPair> pending;
     std::vector<EventPair> pool;
@@ -64,6 +65,7 @@ struct gks_handle {
     bool tuned = false;
     int blk = 128, gmul = 2;
     std::string tune_note, cfg_text;
+    ProbState last_state{}; // problem state read by the last gks_state call
     // step graph
     bool use_graph = true;
     hipStream_t cap = nullptr;
@@ -80,12 +82,22 @@ int fail(gks_handle* h, int code, const std::string& msg)
     return code;
 }
 
+// a HIP runtime failure on a handle leaves it unusable (GKS_ESTATE from then on)
+int fail_hip(gks_handle* h, hipError_t e, const char* what)
+{
+    if (h) h->dead = true;
+    return fail(h, e == hipErrorOutOfMemory ? GKS_ENOMEM : GKS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int dead_handle(gks_handle* h)
+{
+    return fail(h, GKS_ESTATE, "handle unusable after an earlier HIP runtime error (" + h->err + ")");
+}
+
 #define HIP_TRY(h, expr)                                                                          \
     do {                                                                                          \
         hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess)                                                                     \
-            return fail(h, e_ == hipErrorOutOfMemory ? GKS_ENOMEM : GKS_EDEVICE,                  \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));                       \
+        if (e_ != hipSuccess) return fail_hip(h, e_, #expr);                                      \
     } while (0)
 
 template <typename Ptr> hipError_t dalloc(Ptr** p, size_t n)
@@ -664,6 +676,7 @@ int gks_init_device(const gks_problem* probs, int32_t nprob, int32_t precision, 
 int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
 {
     if (!h) return fail(nullptr, GKS_EINVAL, "NULL handle");
+    if (h->dead) return dead_handle(h);
     if (max_steps < 0) return fail(h, GKS_EINVAL, "max_steps < 0");
     std::vector<ProbState> before(h->nprob), after(h->nprob);
     HIP_TRY(h, hipMemcpyAsync(before.data(), h->dS, sizeof(ProbState) * h->nprob, hipMemcpyDeviceToHost, h->stream));
@@ -706,8 +719,9 @@ static int state_common(const gks_handle* hc, int32_t p, double* W, double* Wx, 
 {
     gks_handle* h = const_cast<gks_handle*>(hc);
     if (!h) return fail(nullptr, GKS_EINVAL, "NULL handle");
+    if (h->dead) return dead_handle(h);
     if (p < 0 || p >= h->nprob) return fail(h, GKS_EINVAL, "problem index out of range");
-    ProbState s;
+    ProbState& s = h->last_state;
     HIP_TRY(h, hipMemcpyAsync(&s, h->dS + p, sizeof s, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const ProbParam& P = h->hp[p];
@@ -732,9 +746,7 @@ int gks_state(const gks_handle* hc, int32_t p, double* W, double* Wx, double* Wy
 {
     int st = state_common(hc, p, W, Wx, Wy, false);
     if (st) return st;
-    gks_handle* h = const_cast<gks_handle*>(hc);
-    ProbState s;
-    HIP_TRY(h, hipMemcpy(&s, h->dS + p, sizeof s, hipMemcpyDeviceToHost));
+    const ProbState& s = hc->last_state; // read by state_common on the handle's stream
     if (t) *t = s.t;
     if (nsteps) *nsteps = s.nsteps;
     return GKS_OK;
@@ -749,6 +761,7 @@ int gks_problem_status(const gks_handle* hc, int32_t p, int32_t* status)
 {
     gks_handle* h = const_cast<gks_handle*>(hc);
     if (!h || !status) return fail(h, GKS_EINVAL, "NULL argument");
+    if (h->dead) return dead_handle(h);
     if (p < 0 || p >= h->nprob) return fail(h, GKS_EINVAL, "problem index out of range");
     ProbState s;
     HIP_TRY(h, hipMemcpyAsync(&s, h->dS + p, sizeof s, hipMemcpyDeviceToHost, h->stream));
