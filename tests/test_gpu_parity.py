@@ -382,3 +382,17 @@ def test_2d_gamma(gamma):
     got = S.state(0)
     S.close()
     check(p, got, oracle_run(p, max_steps=4))
+
+
+@pytest.mark.parametrize("nx,ny,bc,steps", [(4, 4, (0, 0, 0, 0), 5), (4, 5, (2, 2, 2, 2), 5), (130, 70, (2, 1, 0, 0), 3)])
+def test_2d_smallest_and_ragged_grids(nx, ny, bc, steps):
+    """The smallest grid the library accepts (4 cells a side, every stencil
+    wraps or mirrors several times) and a ragged grid larger than one tile in
+    both directions (partial tiles in every kernel), against the oracle."""
+    p = wl.pulse_box_2d(nx, ny=ny, bc=bc)
+    g = gks()
+    S = g.Solver(p)
+    S.step(steps)
+    got = S.state(0)
+    S.close()
+    check(p, got, oracle_run(p, max_steps=steps))
