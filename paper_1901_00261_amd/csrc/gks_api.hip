@@ -144,7 +144,7 @@ int validate(const gks_problem* pr, int32_t nprob, int32_t precision)
         if (q.nx < 4 || (dim == 2 && q.ny < 4) || (dim == 1 && q.ny != 1 && q.ny != 0)) return bad("bad nx/ny");
         if ((long long)q.nx * (dim == 2 ? q.ny : 1) > (1ll << 31) - 1) return bad("too many cells");
         // 2-D face-row buffers are read through 32-bit byte offsets
-        if (dim == 2 && 28ll * (q.ny + 4) * (q.nx + 4) * 8 > 0xffffffffll)
+        if (dim == 2 && (28ll * (q.ny + 4) * (q.nx + 4) + gks::row_buffer_pad(q.nx)) * 8 > 0xffffffffll)
             return bad("2-D grid too large for one handle (at most about 4370 x 4370 cells)");
         if (!(q.xhi > q.xlo) || (dim == 2 && !(q.yhi > q.ylo))) return bad("empty domain");
         if (!(q.gamma > 1.0) || !std::isfinite(q.gamma)) return bad("gamma must be > 1");
@@ -236,7 +236,7 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
 {
     const ProbParam& P = h->hp[0];
     const int nx = P.nx, ny = P.ny;
-    const dim3 br(64, 4), bg(64, 2), bc(64, 4);
+    const dim3 br(64, 4), bg(gks::kGpX, gks::kGpY), bc(64, 4);
     // 1-D grids of 2-D tiles; the kernels map workgroups to tiles per XCD.
     // x faces: rows (ny + 4) x faces (nx + 1); y faces: faces (ny + 1) x columns (nx + 4)
     auto tiles = [](int ext_x, int ext_y, dim3 b) { return ((ext_x + b.x - 1) / b.x) * ((ext_y + b.y - 1) / b.y); };
@@ -607,8 +607,8 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
             HIP_TRY(h, dalloc(&h->FdLy, 4 * nfy));
             HIP_TRY(h, dalloc(&h->Wfsy, 4 * nfy));
             HIP_TRY(h, dalloc(&h->Pfy, 4 * nfy));
-            HIP_TRY(h, dalloc(&h->Rx, 28 * (ny + 4) * (nx + 1)));
-            HIP_TRY(h, dalloc(&h->Ry, 28 * (ny + 1) * (nx + 4)));
+            HIP_TRY(h, dalloc(&h->Rx, 28 * (ny + 4) * (nx + 1) + gks::row_buffer_pad((int)nx)));
+            HIP_TRY(h, dalloc(&h->Ry, 28 * (ny + 1) * (nx + 4) + gks::row_buffer_pad((int)nx)));
             return 0;
         })());
     }

@@ -560,51 +560,60 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
 // non-equilibrium values (with the positivity fallback to the face-row line
 // value).  rv(q, k, r): quantity q (face_recon order), component k, row
 // r = 0..4 (rows j-2..j+2).  Values in type D: W0 (linear), Wl, Wr.
+//
+// gp_inputs_k forms component k alone (it reads only rv(., k, .)), so a
+// caller can stage the stencil one component at a time; gp_fallback then
+// applies the positivity fallback, which reads the centre row of all four.
 template <typename T, typename D, typename Acc>
-GKS_HD void gp_inputs(const Acc& rv, int g, D ht, bool weno, D gamma, PointIn<T>& in, D* W0, D* Wl, D* Wr)
+GKS_HD void gp_inputs_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T>& in, D* W0, D* Wl, D* Wr)
 {
-    const D iht = D(1) / ht;
+    D v0 = D(0), v1 = D(0), v2 = D(0), v5 = D(0), v6 = D(0), d0 = D(0), d1 = D(0), d3 = D(0), d4 = D(0),
+      dd0 = D(0);
+    const D base = rv(0, k, 2);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        D v0 = D(0), v1 = D(0), v2 = D(0), v5 = D(0), v6 = D(0), d0 = D(0), d1 = D(0), d3 = D(0), d4 = D(0),
-          dd0 = D(0);
-        const D base = rv(0, k, 2);
-#pragma unroll
-        for (int r = 0; r < 5; ++r) {
-            const D c0 = D(kTanLin[g][0][r]), c1 = D(kTanLin[g][1][r]), c2 = D(kTanLin[g][2][r]);
-            const D q0 = rv(0, k, r) - base;
-            v0 += c0 * q0;
-            d0 += c1 * q0;
-            dd0 += c2 * q0;
-            const D q1 = rv(1, k, r);
-            v1 += c0 * q1;
-            d1 += c1 * q1;
-            v2 += c0 * rv(2, k, r);
-            v5 += c0 * rv(5, k, r);
-            v6 += c0 * rv(6, k, r);
-            d3 += c1 * (rv(3, k, r) - base);
-            d4 += c1 * (rv(4, k, r) - base);
-        }
-        W0[k] = base + v0;
-        in.W0x[k] = T(v1);
-        in.W0xx[k] = T(v2);
-        in.W0y[k] = T(d0 * iht);
-        in.W0xy[k] = T(d1 * iht);
-        in.W0yy[k] = T(dd0 * iht * iht);
-        in.Wlx[k] = T(v5);
-        in.Wrx[k] = T(v6);
-        in.Wly[k] = T(d3 * iht);
-        in.Wry[k] = T(d4 * iht);
-        if (!weno) {
-            Wl[k] = Wr[k] = W0[k];
-        } else {
-            D ql[5], qr[5];
-#pragma unroll
-            for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
-            Wl[k] = base + tan_weno<D>(ql, g);
-            Wr[k] = base + tan_weno<D>(qr, g);
-        }
+    for (int r = 0; r < 5; ++r) {
+        const D c0 = D(kTanLin[g][0][r]), c1 = D(kTanLin[g][1][r]), c2 = D(kTanLin[g][2][r]);
+        const D q0 = rv(0, k, r) - base;
+        v0 += c0 * q0;
+        d0 += c1 * q0;
+        dd0 += c2 * q0;
+        const D q1 = rv(1, k, r);
+        v1 += c0 * q1;
+        d1 += c1 * q1;
+        v2 += c0 * rv(2, k, r);
+        v5 += c0 * rv(5, k, r);
+        v6 += c0 * rv(6, k, r);
+        d3 += c1 * (rv(3, k, r) - base);
+        d4 += c1 * (rv(4, k, r) - base);
     }
+    W0[k] = base + v0;
+    in.W0x[k] = T(v1);
+    in.W0xx[k] = T(v2);
+    in.W0y[k] = T(d0 * iht);
+    in.W0xy[k] = T(d1 * iht);
+    in.W0yy[k] = T(dd0 * iht * iht);
+    in.Wlx[k] = T(v5);
+    in.Wrx[k] = T(v6);
+    in.Wly[k] = T(d3 * iht);
+    in.Wry[k] = T(d4 * iht);
+    // both values formed first and stored once: stores to different arrays
+    // in the two branches would otherwise be merged into one store through a
+    // selected pointer, which keeps the arrays in scratch memory
+    D wl = W0[k], wr = W0[k];
+    if (weno) {
+        D ql[5], qr[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
+        wl = base + tan_weno<D>(ql, g);
+        wr = base + tan_weno<D>(qr, g);
+    }
+    Wl[k] = wl;
+    Wr[k] = wr;
+}
+
+template <typename D, typename Acc>
+GKS_HD void gp_fallback(const Acc& rv, bool weno, D gamma, D* Wl, D* Wr)
+{
     if (weno) {
         if (!physical<D>(Wl, gamma, 2))
 #pragma unroll
@@ -615,8 +624,18 @@ GKS_HD void gp_inputs(const Acc& rv, int g, D ht, bool weno, D gamma, PointIn<T>
     }
 }
 
+template <typename T, typename D, typename Acc>
+GKS_HD void gp_inputs(const Acc& rv, int g, D ht, bool weno, D gamma, PointIn<T>& in, D* W0, D* Wl, D* Wr)
+{
+    const D iht = D(1) / ht;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gp_inputs_k<T, D>(rv, g, k, iht, weno, in, W0, Wl, Wr);
+    gp_fallback<D>(rv, weno, gamma, Wl, Wr);
+}
+
 // Row-buffer reads through a buffer resource: 32-bit per-lane offsets for
-// the five stencil rows, the quantity plane as a scalar offset.
+// the five stencil rows, the quantity plane as a scalar offset.  The
+// interface kernel uses it only for the rare positivity fallback.
 struct RowReader {
     __amdgpu_buffer_rsrc_t rsrc;
     unsigned voff[5];  // byte offset of row r (lane dependent)
@@ -628,23 +647,89 @@ struct RowReader {
     }
 };
 
-template <typename T>
-__device__ __forceinline__ bool gauss_point(const RowReader& rv, int g, double ht, bool weno, const PointPar& par,
-                                            PointOut<double>& out)
+// Interface-kernel workgroup: 64 lanes along the contiguous index of the
+// row buffer (x faces: the face; y faces: the transverse cell) times 2 waves
+// (x faces: two transverse rows; y faces: two faces).
+constexpr int kGpX = 64, kGpY = 2;
+
+// LDS staging of one component k of the workgroup's stencil (the 7
+// quantities of face_recon, each over the rows the workgroup needs), copied
+// by the waves themselves with direct-to-LDS dword loads, so the copy takes
+// no registers and runs while the previous component is computed.
+//   x faces: 6 transverse rows (2 waves + 4 stencil rows) x 64 faces;
+//   y faces: 2 face rows x 96 transverse entries (64 lanes + 4 stencil
+//            entries, rounded up to three 256-byte copies).
+template <int DIR>
+struct GpStage {
+    static constexpr int rows = DIR == 0 ? kGpY + 4 : kGpY; // rows per quantity
+    static constexpr int len = DIR == 0 ? kGpX : 96;         // doubles per row
+    static constexpr int doubles = 7 * rows * len;
+};
+
+// Reader of a staged component: lane's row r of quantity q.
+template <int DIR>
+struct StageReader {
+    const double* p; // x faces: slot + w*64 + lane; y faces: slot + w*96 + lane
+    __device__ __forceinline__ double operator()(int q, int, int r) const
+    {
+        return DIR == 0 ? p[(q * GpStage<DIR>::rows + r) * GpStage<DIR>::len] : p[q * GpStage<DIR>::rows * GpStage<DIR>::len + r];
+    }
+};
+
+// Doubles allocated past the end of a 2-D row buffer: the staging copies
+// of the workgroups at the grid's far edges read up to one row (x faces:
+// nx + 1, y faces: nx + 4 doubles) plus a rounded-up row segment beyond the
+// last plane, so every copy stays inside the allocation.
+__host__ __device__ constexpr long long row_buffer_pad(int nx) { return (long long)nx + 128; }
+
+// Wave w's share of the copy of component k into slot dst.  sofs: byte
+// offset in the row buffer of the workgroup's first row of quantity 0 at
+// component k; plane / rstride: bytes between quantity planes / rows.  The
+// uniform offsets go to the scalar offset, the lane's 4 bytes to the vector
+// offset.  The empty asm makes the scalar inputs opaque at each call, so
+// the compiler recomputes the 42 offsets and LDS addresses (a scalar add
+// each) instead of keeping every component's set live across the
+// Gauss-point loop.
+template <int DIR>
+__device__ __forceinline__ void stage_component(__amdgpu_buffer_rsrc_t rs, double* dst, unsigned sofs,
+                                                unsigned plane, unsigned rstride, int w, unsigned vlane)
 {
-    PointIn<T> in;
-    double W0[4], Wl[4], Wr[4];
-    gp_inputs<T, double>(rv, g, ht, weno, par.gamma, in, W0, Wl, Wr);
-    NonEq<double, 2, T> ne;
-    if (!noneq_states<double, 2, T>(Wl, Wr, par.gamma, par.K, ne, in.Wlx, in.Wly, in.Wrx, in.Wry)) return false;
-    return gks_point<T, 2>(par, in, weno ? ne.Xs : W0, ne, out);
+    using G = GpStage<DIR>;
+    asm volatile("" : "+s"(sofs), "+s"(plane), "+s"(rstride), "+s"(w));
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const unsigned qo = sofs + (unsigned)(q * 4) * plane;
+        if constexpr (DIR == 0) {
+            // wave w copies byte half w of each of the 6 rows
+#pragma unroll
+            for (int r = 0; r < G::rows; ++r)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (__attribute__((address_space(3))) void*)(dst + (q * G::rows + r) * G::len + w * 32), 4,
+                    vlane, qo + (unsigned)r * rstride + (unsigned)w * 256u, 0, 0);
+        } else {
+            // wave w copies its own face row
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (__attribute__((address_space(3))) void*)(dst + (q * G::rows + w) * G::len + c * 32), 4,
+                    vlane, qo + (unsigned)w * rstride + (unsigned)c * 256u, 0, 0);
+        }
+    }
+}
+
+// Wait for this wave's staging copies, then for the whole workgroup: after
+// it, the slot just copied is complete and the other slot is free.
+__device__ __forceinline__ void stage_sync()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70); // vmcnt(0)
+    __syncthreads();
 }
 
 template <typename T, int DIR, int STAGE>
-__global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
-                                                   const double* __restrict__ R, double* __restrict__ FL,
-                                                   double* __restrict__ FdL, double* __restrict__ Wfs,
-                                                   double* __restrict__ Pf)
+__global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                          const double* __restrict__ R, double* __restrict__ FL,
+                                                          double* __restrict__ FdL, double* __restrict__ Wfs,
+                                                          double* __restrict__ Pf)
 {
     const ProbParam& P = PP[0];
     ProbState& S = PS[0];
@@ -653,25 +738,41 @@ __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__
     const int nf = DIR == 0 ? nx + 1 : ny + 1;
     const int nt = DIR == 0 ? ny : nx;
     const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
-    const int bw = DIR == 0 ? nf : nt; // extent of the thread-x index
+    const int bw = DIR == 0 ? nf : nt; // extent of the lane index
     int tx, ty;
-    tile_xy((bw + blockDim.x - 1) / blockDim.x, tx, ty);
-    const int b = tx * blockDim.x + threadIdx.x; // DIR 0: face, DIR 1: transverse cell
-    const int a = ty * blockDim.y + threadIdx.y; // DIR 0: transverse cell, DIR 1: face
+    tile_xy((bw + kGpX - 1) / kGpX, tx, ty);
+    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int b = tx * kGpX + lane; // DIR 0: face, DIR 1: transverse cell
+    const int a = ty * kGpY + w;    // DIR 0: transverse cell, DIR 1: face
     const int face = DIR == 0 ? b : a, tc = DIR == 0 ? a : b;
-    if (face >= nf || tc >= nt) return;
+    // Lanes outside the grid take part in the staging and the barriers and
+    // compute on whatever the slots hold there, but store nothing.
+    const bool valid = face < nf && tc < nt;
     const size_t AB = (size_t)A * B;
+    // the host guarantees (28 (nx + 4)(ny + 4) + row_buffer_pad(nx)) * 8 < 2^32
+    const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)R, (short)0, (int)(unsigned)((AB * 28 + row_buffer_pad(nx)) * sizeof(double)), 0x00020000);
+    const unsigned plane = (unsigned)(AB * sizeof(double));
+    const unsigned rstride = (unsigned)B * (unsigned)sizeof(double);
     // row r of the stencil = transverse index tc - 2 + r, stored at (tc + r)
-    const unsigned a0 = DIR == 0 ? (unsigned)tc * B + face : (unsigned)face * B + tc;
-    const unsigned bstride = DIR == 0 ? (unsigned)B : 1u;
-    RowReader rv;
-    // the host guarantees 28 * AB * 8 < 2^32 bytes
-    rv.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)R, (short)0, (int)(unsigned)(AB * 28 * sizeof(double)),
-                                                0x00020000);
-    rv.plane = (unsigned)(AB * sizeof(double));
+    const unsigned wg0 = (unsigned)(ty * kGpY) * (unsigned)B + (unsigned)(tx * kGpX); // workgroup's first row
+    const unsigned sbase = wg0 * (unsigned)sizeof(double), vlane = (unsigned)lane * 4u;
+    RowReader rv; // global reads for the positivity fallback
+    rv.rsrc = rsrc;
+    rv.plane = plane;
+    {
+        const unsigned a0 = DIR == 0 ? (unsigned)tc * B + face : (unsigned)face * B + tc;
+        const unsigned bstride = DIR == 0 ? (unsigned)B : 1u;
 #pragma unroll
-    for (int r = 0; r < 5; ++r) rv.voff[r] = (a0 + r * bstride) * (unsigned)sizeof(double);
+        for (int r = 0; r < 5; ++r) rv.voff[r] = (a0 + r * bstride) * (unsigned)sizeof(double);
+    }
+    using G = GpStage<DIR>;
+    __shared__ double slot0[G::doubles], slot1[G::doubles];
+    const int lofs = w * G::len + lane;
+    const StageReader<DIR> rd0{slot0 + lofs}, rd1{slot1 + lofs};
     const double ht = DIR == 0 ? P.dy : P.dx;
+    const double iht = 1.0 / ht;
     const double dt = S.dt;
     const PointPar par{P.gamma, P.K, P.mu, dt};
     const bool weno = P.recon != 0;
@@ -679,26 +780,53 @@ __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__
     // registers across the Gauss-point loop: slot m = 4 q + k, q = 0 FL,
     // 1 FdL, 2 S0, 3 S1, 4 S2 (stage 2: FdL and S2 only, slots 0..7)
     constexpr int NQ = STAGE == 1 ? 5 : 2;
-    __shared__ double sacc[NQ * 4][128];
-    const int lane = threadIdx.y * blockDim.x + threadIdx.x;
-    bool ok = true;
+    __shared__ double sacc[NQ * 4][kGpX * kGpY];
+    const int col = w * kGpX + lane;
+    bool ok = valid;
+    stage_component<DIR>(rsrc, slot0, sbase, plane, rstride, w, vlane);
 #pragma unroll 1
     for (int g = 0; g < 3; ++g) {
-        PointOut<double> o;
-        ok = ok && gauss_point<T>(rv, g, ht, weno, par, o);
-        const double wg = g == 1 ? 8.0 / 18.0 : 5.0 / 18.0;
+        PointIn<T> in;
+        double W0[4], Wl[4], Wr[4];
+        // component k is in slot k % 2; the copy of the next component (or
+        // of component 0 for the next Gauss point) overlaps this one's work
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            stage_sync();
+            if (k < 3) stage_component<DIR>(rsrc, (k & 1) ? slot0 : slot1, sbase + (k + 1) * plane, plane, rstride, w, vlane);
+            else if (g < 2) stage_component<DIR>(rsrc, slot0, sbase, plane, rstride, w, vlane);
+            if (k & 1) gp_inputs_k<T, double>(rd1, g, k, iht, weno, in, W0, Wl, Wr);
+            else gp_inputs_k<T, double>(rd0, g, k, iht, weno, in, W0, Wl, Wr);
+        }
         if (ok) {
-            const double* src[5] = {o.FL, o.FdL, o.S0, o.S1, o.S2};
+            gp_fallback<double>(rv, weno, par.gamma, Wl, Wr);
+            NonEq<double, 2, T> ne;
+            PointOut<double> o;
+            ok = noneq_states<double, 2, T>(Wl, Wr, par.gamma, par.K, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+            if (ok) {
+                // equilibrium state: the kinetic average (WENO-Z) or the linear
+                // value, selected per element so that every array stays in
+                // registers
+                double We[4];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q)
+                for (int k = 0; k < 4; ++k) We[k] = weno ? ne.Xs[k] : W0[k];
+                ok = gks_point<T, 2>(par, in, We, ne, o);
+            }
+            const double wg = g == 1 ? 8.0 / 18.0 : 5.0 / 18.0;
+            if (ok) {
+                const double* src[5] = {o.FL, o.FdL, o.S0, o.S1, o.S2};
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const double v = wg * src[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k];
-                    double& slot = sacc[q * 4 + k][lane];
-                    slot = g == 0 ? v : slot + v;
-                }
+                for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double v = wg * src[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k];
+                        double& sl = sacc[q * 4 + k][col];
+                        sl = g == 0 ? v : sl + v;
+                    }
+            }
         }
     }
+    if (!valid) return;
     if (!ok) {
         S.err = 1;
         return;
@@ -707,7 +835,7 @@ __global__ void __launch_bounds__(128) gp2d_kernel(const ProbParam* __restrict__
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k] = sacc[q * 4 + k][lane];
+        for (int k = 0; k < 4; ++k) acc[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k] = sacc[q * 4 + k][col];
     // back to the global frame
     const int gk[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
     const size_t nfa = DIR == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
