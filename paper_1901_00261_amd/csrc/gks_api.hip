@@ -144,7 +144,8 @@ int validate(const gks_problem* pr, int32_t nprob, int32_t precision)
         if (q.nx < 4 || (dim == 2 && q.ny < 4) || (dim == 1 && q.ny != 1 && q.ny != 0)) return bad("bad nx/ny");
         if ((long long)q.nx * (dim == 2 ? q.ny : 1) > (1ll << 31) - 1) return bad("too many cells");
         // 2-D face-row buffers are read through 32-bit byte offsets
-        if (dim == 2 && (28ll * (q.ny + 4) * (q.nx + 4) + gks::row_buffer_pad(q.nx)) * 8 > 0xffffffffll)
+        if (dim == 2 && std::max(gks::row_buffer_doubles(q.nx, q.ny, 0), gks::row_buffer_doubles(q.nx, q.ny, 1)) * 8 >
+                            0xffffffffll)
             return bad("2-D grid too large for one handle (at most about 4370 x 4370 cells)");
         if (!(q.xhi > q.xlo) || (dim == 2 && !(q.yhi > q.ylo))) return bad("empty domain");
         if (!(q.gamma > 1.0) || !std::isfinite(q.gamma)) return bad("gamma must be > 1");
@@ -607,8 +608,8 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
             HIP_TRY(h, dalloc(&h->FdLy, 4 * nfy));
             HIP_TRY(h, dalloc(&h->Wfsy, 4 * nfy));
             HIP_TRY(h, dalloc(&h->Pfy, 4 * nfy));
-            HIP_TRY(h, dalloc(&h->Rx, 28 * (ny + 4) * (nx + 1) + gks::row_buffer_pad((int)nx)));
-            HIP_TRY(h, dalloc(&h->Ry, 28 * (ny + 1) * (nx + 4) + gks::row_buffer_pad((int)nx)));
+            HIP_TRY(h, dalloc(&h->Rx, gks::row_buffer_doubles((int)nx, (int)ny, 0)));
+            HIP_TRY(h, dalloc(&h->Ry, gks::row_buffer_doubles((int)nx, (int)ny, 1)));
             return 0;
         })());
     }

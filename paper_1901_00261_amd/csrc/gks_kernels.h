@@ -492,12 +492,31 @@ __global__ void __launch_bounds__(kBlock1D) signal1d_kernel(const ProbParam* __r
     block_max_atomic(s, &S.smax);
 }
 
+// Row stride of the 2-D row buffers: the row length rounded up to even, so
+// that rows and planes start on 16-byte boundaries (the interface kernel
+// stages them with 16-byte copies).
+__host__ __device__ constexpr int row_stride(int len) { return (len + 1) & ~1; }
+
+// Doubles allocated past the end of a 2-D row buffer: the staging copies of
+// the workgroups at the grid's far edges read up to three rows (of at most
+// nx + 5 doubles) plus one 128-double segment beyond the last plane, so
+// every copy stays inside the allocation.
+__host__ __device__ constexpr long long row_buffer_pad(int nx) { return 3ll * (nx + 5) + 128; }
+
+// Doubles of the row buffer of direction dir: 28 planes of A rows of stride
+// row_stride(B), plus the pad.
+__host__ __device__ constexpr long long row_buffer_doubles(int nx, int ny, int dir)
+{
+    return 28ll * (dir == 0 ? ny + 4 : ny + 1) * row_stride(dir == 0 ? nx + 1 : nx + 4) + row_buffer_pad(nx);
+}
+
 // ---------------------------------------------------------------------------
 // 2-D.  DIR 0: x faces, DIR 1: y faces (local frame swaps slots 1 and 2).
 // Face-row kernel: one thread per (face, transverse row incl. two ghost rows
 // per side); stores the seven reconstructed vectors of face_recon.  ORDER
 // (6 or 8) is the problem's, chosen at launch.
-// Row buffer R[28][A][B], thread-x index b fastest:
+// Row buffer R[28][A][Bs], thread-x index b fastest, rows of B values
+// stored with stride Bs = row_stride(B):
 //   DIR 0: a = row + 2 (ny + 4 rows), b = face (nx + 1)
 //   DIR 1: a = face (ny + 1), b = column + 2 (nx + 4)
 // ---------------------------------------------------------------------------
@@ -548,7 +567,7 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
 #pragma unroll
         for (int k = 0; k < 4; ++k) { Wk[q][k] = w[k]; Dk[q][k] = d[k]; }
     }
-    const size_t AB = (size_t)A * B, ab = (size_t)a * B + b;
+    const size_t Bs = row_stride(B), AB = (size_t)A * Bs, ab = (size_t)a * Bs + b;
     auto put = [&](int q, int k, double v) { R[(q * 4 + k) * AB + ab] = v; };
     const bool ok = face_recon<T, 2, ORDER>(Wk, Dk, h, P.gamma, P.recon != 0, put);
     if (!ok) S.err = 1;
@@ -648,81 +667,68 @@ struct RowReader {
 };
 
 // Interface-kernel workgroup: 64 lanes along the contiguous index of the
-// row buffer (x faces: the face; y faces: the transverse cell) times 2 waves
-// (x faces: two transverse rows; y faces: two faces).
-constexpr int kGpX = 64, kGpY = 2;
+// row buffer (x faces: the face; y faces: the transverse cell) times 4 waves
+// (x faces: four transverse rows; y faces: four faces); its LDS (the staged
+// stencil and the Gauss sums) takes one workgroup per CU, one wave per SIMD.
+constexpr int kGpX = 64, kGpY = 4;
 
-// LDS staging of one component k of the workgroup's stencil (the 7
-// quantities of face_recon, each over the rows the workgroup needs), copied
-// by the waves themselves with direct-to-LDS dword loads, so the copy takes
-// no registers and runs while the previous component is computed.
-//   x faces: 6 transverse rows (2 waves + 4 stencil rows) x 64 faces;
-//   y faces: 2 face rows x 96 transverse entries (64 lanes + 4 stencil
-//            entries, rounded up to three 256-byte copies).
+// LDS staging of the workgroup's stencil: slot k holds component k of the 7
+// quantities of face_recon over the rows the workgroup needs.  The waves
+// copy it themselves, once, with 16-byte direct-to-LDS loads (no registers
+// held); the three Gauss points then read it from LDS.
+//   x faces: 8 transverse rows (4 waves + 4 stencil rows) x 64 faces, one
+//            1 KB copy per row pair (lanes 0-31 the first row, 32-63 the
+//            second);
+//   y faces: 4 face rows x 128 transverse entries (64 lanes + 4 stencil
+//            entries, rounded up to one 1 KB copy per row).
 template <int DIR>
 struct GpStage {
     static constexpr int rows = DIR == 0 ? kGpY + 4 : kGpY; // rows per quantity
-    static constexpr int len = DIR == 0 ? kGpX : 96;         // doubles per row
+    static constexpr int len = DIR == 0 ? kGpX : 2 * kGpX;   // doubles per row
     static constexpr int doubles = 7 * rows * len;
+    static constexpr int copies = 7;                          // per wave and component
 };
 
 // Reader of a staged component: lane's row r of quantity q.
 template <int DIR>
 struct StageReader {
-    const double* p; // x faces: slot + w*64 + lane; y faces: slot + w*96 + lane
+    const double* p; // slot + w * len + lane
     __device__ __forceinline__ double operator()(int q, int, int r) const
     {
-        return DIR == 0 ? p[(q * GpStage<DIR>::rows + r) * GpStage<DIR>::len] : p[q * GpStage<DIR>::rows * GpStage<DIR>::len + r];
+        using G = GpStage<DIR>;
+        return DIR == 0 ? p[(q * G::rows + r) * G::len] : p[q * G::rows * G::len + r];
     }
 };
 
-// Doubles allocated past the end of a 2-D row buffer: the staging copies
-// of the workgroups at the grid's far edges read up to one row (x faces:
-// nx + 1, y faces: nx + 4 doubles) plus a rounded-up row segment beyond the
-// last plane, so every copy stays inside the allocation.
-__host__ __device__ constexpr long long row_buffer_pad(int nx) { return (long long)nx + 128; }
-
-// Wave w's share of the copy of component k into slot dst.  sofs: byte
+// Wave w's copies of one component into slot dst: x faces, row pair w of
+// every quantity; y faces, its own face row of every quantity.  sofs: byte
 // offset in the row buffer of the workgroup's first row of quantity 0 at
-// component k; plane / rstride: bytes between quantity planes / rows.  The
-// uniform offsets go to the scalar offset, the lane's 4 bytes to the vector
-// offset.  The empty asm makes the scalar inputs opaque at each call, so
-// the compiler recomputes the 42 offsets and LDS addresses (a scalar add
-// each) instead of keeping every component's set live across the
-// Gauss-point loop.
+// this component; plane / rstride: bytes between quantity planes / rows;
+// voff: the lane's byte offset within a copy.
 template <int DIR>
 __device__ __forceinline__ void stage_component(__amdgpu_buffer_rsrc_t rs, double* dst, unsigned sofs,
-                                                unsigned plane, unsigned rstride, int w, unsigned vlane)
+                                                unsigned plane, unsigned rstride, int w, unsigned voff)
 {
     using G = GpStage<DIR>;
-    asm volatile("" : "+s"(sofs), "+s"(plane), "+s"(rstride), "+s"(w));
+    const int row = DIR == 0 ? 2 * w : w;
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        const unsigned qo = sofs + (unsigned)(q * 4) * plane;
-        if constexpr (DIR == 0) {
-            // wave w copies byte half w of each of the 6 rows
-#pragma unroll
-            for (int r = 0; r < G::rows; ++r)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    rs, (__attribute__((address_space(3))) void*)(dst + (q * G::rows + r) * G::len + w * 32), 4,
-                    vlane, qo + (unsigned)r * rstride + (unsigned)w * 256u, 0, 0);
-        } else {
-            // wave w copies its own face row
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    rs, (__attribute__((address_space(3))) void*)(dst + (q * G::rows + w) * G::len + c * 32), 4,
-                    vlane, qo + (unsigned)w * rstride + (unsigned)c * 256u, 0, 0);
-        }
-    }
+    for (int q = 0; q < 7; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)(dst + (q * G::rows + row) * G::len), 16, voff,
+            sofs + (unsigned)(q * 4) * plane + (unsigned)row * rstride, 0, 0);
 }
 
-// Wait for this wave's staging copies, then for the whole workgroup: after
-// it, the slot just copied is complete and the other slot is free.
-__device__ __forceinline__ void stage_sync()
+// Wait until this wave's copies of components 0..K have landed (the 7 copies
+// of each later component may still be in flight), then for the whole
+// workgroup, whose waves share the x-face rows.
+template <int K>
+__device__ __forceinline__ void stage_wait()
 {
-    __builtin_amdgcn_s_waitcnt(0x0F70); // vmcnt(0)
-    __syncthreads();
+    constexpr int n = GpStage<0>::copies * (3 - K);
+    static_assert(n < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | 0x0F70); // vmcnt(n), other counters free
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 template <typename T, int DIR, int STAGE>
@@ -738,6 +744,7 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
     const int nf = DIR == 0 ? nx + 1 : ny + 1;
     const int nt = DIR == 0 ? ny : nx;
     const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
+    const int Bs = row_stride(B);
     const int bw = DIR == 0 ? nf : nt; // extent of the lane index
     int tx, ty;
     tile_xy((bw + kGpX - 1) / kGpX, tx, ty);
@@ -749,28 +756,33 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
     // Lanes outside the grid take part in the staging and the barriers and
     // compute on whatever the slots hold there, but store nothing.
     const bool valid = face < nf && tc < nt;
-    const size_t AB = (size_t)A * B;
-    // the host guarantees (28 (nx + 4)(ny + 4) + row_buffer_pad(nx)) * 8 < 2^32
+    const size_t AB = (size_t)A * Bs;
+    // the host guarantees row_buffer_doubles(nx, ny, DIR) * 8 < 2^32
     const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)R, (short)0, (int)(unsigned)((AB * 28 + row_buffer_pad(nx)) * sizeof(double)), 0x00020000);
+        (void*)R, (short)0, (int)(unsigned)(row_buffer_doubles(nx, ny, DIR) * sizeof(double)), 0x00020000);
     const unsigned plane = (unsigned)(AB * sizeof(double));
-    const unsigned rstride = (unsigned)B * (unsigned)sizeof(double);
-    // row r of the stencil = transverse index tc - 2 + r, stored at (tc + r)
-    const unsigned wg0 = (unsigned)(ty * kGpY) * (unsigned)B + (unsigned)(tx * kGpX); // workgroup's first row
-    const unsigned sbase = wg0 * (unsigned)sizeof(double), vlane = (unsigned)lane * 4u;
+    const unsigned rstride = (unsigned)Bs * (unsigned)sizeof(double);
+    // row r of the stencil = transverse index tc - 2 + r, stored at (tc + r);
+    // the workgroup's first row starts at (ty kGpY, tx kGpX), 16-byte aligned
+    const unsigned sbase = ((unsigned)(ty * kGpY) * (unsigned)Bs + (unsigned)(tx * kGpX)) * (unsigned)sizeof(double);
+    const unsigned voff = DIR == 0 ? (unsigned)(lane & 31) * 16u + (unsigned)(lane >> 5) * rstride : (unsigned)lane * 16u;
     RowReader rv; // global reads for the positivity fallback
     rv.rsrc = rsrc;
     rv.plane = plane;
     {
-        const unsigned a0 = DIR == 0 ? (unsigned)tc * B + face : (unsigned)face * B + tc;
-        const unsigned bstride = DIR == 0 ? (unsigned)B : 1u;
+        const unsigned a0 = DIR == 0 ? (unsigned)tc * Bs + face : (unsigned)face * Bs + tc;
+        const unsigned bstride = DIR == 0 ? (unsigned)Bs : 1u;
 #pragma unroll
         for (int r = 0; r < 5; ++r) rv.voff[r] = (a0 + r * bstride) * (unsigned)sizeof(double);
     }
     using G = GpStage<DIR>;
-    __shared__ double slot0[G::doubles], slot1[G::doubles];
+    __shared__ double slot0[G::doubles], slot1[G::doubles], slot2[G::doubles], slot3[G::doubles];
+    stage_component<DIR>(rsrc, slot0, sbase, plane, rstride, w, voff);
+    stage_component<DIR>(rsrc, slot1, sbase + plane, plane, rstride, w, voff);
+    stage_component<DIR>(rsrc, slot2, sbase + 2 * plane, plane, rstride, w, voff);
+    stage_component<DIR>(rsrc, slot3, sbase + 3 * plane, plane, rstride, w, voff);
     const int lofs = w * G::len + lane;
-    const StageReader<DIR> rd0{slot0 + lofs}, rd1{slot1 + lofs};
+    const StageReader<DIR> rd[4] = {{slot0 + lofs}, {slot1 + lofs}, {slot2 + lofs}, {slot3 + lofs}};
     const double ht = DIR == 0 ? P.dy : P.dx;
     const double iht = 1.0 / ht;
     const double dt = S.dt;
@@ -783,20 +795,20 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
     __shared__ double sacc[NQ * 4][kGpX * kGpY];
     const int col = w * kGpX + lane;
     bool ok = valid;
-    stage_component<DIR>(rsrc, slot0, sbase, plane, rstride, w, vlane);
 #pragma unroll 1
     for (int g = 0; g < 3; ++g) {
         PointIn<T> in;
         double W0[4], Wl[4], Wr[4];
-        // component k is in slot k % 2; the copy of the next component (or
-        // of component 0 for the next Gauss point) overlaps this one's work
+        // the first Gauss point waits for each component's copies in turn
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            stage_sync();
-            if (k < 3) stage_component<DIR>(rsrc, (k & 1) ? slot0 : slot1, sbase + (k + 1) * plane, plane, rstride, w, vlane);
-            else if (g < 2) stage_component<DIR>(rsrc, slot0, sbase, plane, rstride, w, vlane);
-            if (k & 1) gp_inputs_k<T, double>(rd1, g, k, iht, weno, in, W0, Wl, Wr);
-            else gp_inputs_k<T, double>(rd0, g, k, iht, weno, in, W0, Wl, Wr);
+            if (g == 0) {
+                if (k == 0) stage_wait<0>();
+                else if (k == 1) stage_wait<1>();
+                else if (k == 2) stage_wait<2>();
+                else stage_wait<3>();
+            }
+            gp_inputs_k<T, double>(rd[k], g, k, iht, weno, in, W0, Wl, Wr);
         }
         if (ok) {
             gp_fallback<double>(rv, weno, par.gamma, Wl, Wr);
