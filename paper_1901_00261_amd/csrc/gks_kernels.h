@@ -377,6 +377,7 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
             PointIn<T> in;
             PointOut<double> out;
             NonEq<double, 1, T> ne;
+            const PointPar par = point_par<1>(P.gamma, P.K, P.mu, dt);
             if (ok) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -385,12 +386,9 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
                     in.Wlx[k] = T(o[5][k]); in.Wrx[k] = T(o[6][k]);
                     in.Wly[k] = in.Wry[k] = T(0);
                 }
-                ok = noneq_states<double, 1, T>(o[3], o[4], P.gamma, P.K, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+                ok = noneq_states<double, 1, T>(o[3], o[4], P.gamma, P.K, par.iN, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
             }
-            if (ok) {
-                const PointPar par{P.gamma, P.K, P.mu, dt};
-                ok = gks_point<T, 1>(par, in, P.recon ? ne.Xs : o[0], ne, out);
-            }
+            if (ok) ok = gks_point<T, 1>(par, in, P.recon ? ne.Xs : o[0], ne, out);
             if (!ok) {
                 atomicOr(&S.err, 1);
 #pragma unroll
@@ -623,8 +621,10 @@ GKS_HD void gp_inputs_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T
         D ql[5], qr[5];
 #pragma unroll
         for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
-        wl = base + tan_weno<D>(ql, g);
-        wr = base + tan_weno<D>(qr, g);
+        D vl, vr;
+        tan_weno_pair<D>(ql, qr, g, vl, vr);
+        wl = base + vl;
+        wr = base + vr;
     }
     Wl[k] = wl;
     Wr[k] = wr;
@@ -786,7 +786,7 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
     const double ht = DIR == 0 ? P.dy : P.dx;
     const double iht = 1.0 / ht;
     const double dt = S.dt;
-    const PointPar par{P.gamma, P.K, P.mu, dt};
+    const PointPar par = point_par<2>(P.gamma, P.K, P.mu, dt);
     const bool weno = P.recon != 0;
     // Gauss sums of the outputs live in LDS (this lane's column), not in
     // registers across the Gauss-point loop: slot m = 4 q + k, q = 0 FL,
@@ -814,7 +814,7 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
             gp_fallback<double>(rv, weno, par.gamma, Wl, Wr);
             NonEq<double, 2, T> ne;
             PointOut<double> o;
-            ok = noneq_states<double, 2, T>(Wl, Wr, par.gamma, par.K, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+            ok = noneq_states<double, 2, T>(Wl, Wr, par.gamma, par.K, par.iN, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
             if (ok) {
                 // equilibrium state: the kinetic average (WENO-Z) or the linear
                 // value, selected per element so that every array stays in

@@ -269,11 +269,12 @@ __device__ constexpr double kTanLinW[3][3] = {
     {-0.1125, 1.2250000000000001, -0.1125},
     {0.13988896611054835, 0.61526717557251909, 0.24484385831693256}};
 
-// 5th-order WENO-Z value at Gauss point g from rows q[0..4]; the centre
-// point's negative linear weights are split into two positive groups
-// (Shi, Hu, Shu, J. Comput. Phys. 175 (2002), theta = 3).
+// 5th-order WENO-Z value at Gauss point g from rows q[0..4], as a quotient
+// num / den; the centre point's negative linear weights are split into two
+// positive groups (Shi, Hu, Shu, J. Comput. Phys. 175 (2002), theta = 3),
+// whose two quotients are brought over one denominator.
 template <typename T>
-GKS_HD T tan_weno(const T* q, int g)
+GKS_HD void tan_weno_frac(const T* q, int g, T& num, T& den)
 {
     T cand[3];
 #pragma unroll
@@ -292,21 +293,38 @@ GKS_HD T tan_weno(const T* q, int g)
     const T e0 = be[0] + eps, e1 = be[1] + eps, e2 = be[2] + eps;
     const T r[3] = {(e0 + Z) * (e1 * e2), (e1 + Z) * (e0 * e2), (e2 + Z) * (e0 * e1)};
     if (g != 1) {
-        T a[3], sum = T(0), v = T(0);
+        T a[3];
+        num = den = T(0);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { a[k] = T(kTanLinW[g][k]) * r[k]; sum += a[k]; }
+        for (int k = 0; k < 3; ++k) { a[k] = T(kTanLinW[g][k]) * r[k]; den += a[k]; }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) v += a[k] * cand[k];
-        return v / sum;
+        for (int k = 0; k < 3; ++k) num += a[k] * cand[k];
+        return;
     }
-    // gamma+ = (g + 3|g|)/2, gamma- = gamma+ - g
+    // gamma+ = (g + 3|g|)/2, gamma- = gamma+ - g; value sp vp - sm vm
     constexpr double gp0 = 0.1125, gp1 = 2.45, gp2 = 0.1125, sp = 2.675;
     constexpr double gm0 = 0.225, gm1 = 1.225, gm2 = 0.225, sm = 1.675;
     const T ap0 = T(gp0) * r[0], ap1 = T(gp1) * r[1], ap2 = T(gp2) * r[2];
     const T am0 = T(gm0) * r[0], am1 = T(gm1) * r[1], am2 = T(gm2) * r[2];
-    const T vp = (ap0 * cand[0] + ap1 * cand[1] + ap2 * cand[2]) / (ap0 + ap1 + ap2);
-    const T vm = (am0 * cand[0] + am1 * cand[1] + am2 * cand[2]) / (am0 + am1 + am2);
-    return T(sp) * vp - T(sm) * vm;
+    const T np = ap0 * cand[0] + ap1 * cand[1] + ap2 * cand[2], dp = ap0 + ap1 + ap2;
+    const T nm = am0 * cand[0] + am1 * cand[1] + am2 * cand[2], dm = am0 + am1 + am2;
+    num = T(sp) * np * dm - T(sm) * nm * dp;
+    den = dp * dm;
+}
+
+// WENO-Z values at Gauss point g of two row sets (the left and right
+// non-equilibrium rows) with one division.  The denominators are sums of
+// products of three (beta + eps) factors, eps = 1e-6, so their product stays
+// far inside the double range for any bounded data.
+template <typename T>
+GKS_HD void tan_weno_pair(const T* ql, const T* qr, int g, T& vl, T& vr)
+{
+    T nl, dl, nr, dr;
+    tan_weno_frac<T>(ql, g, nl, dl);
+    tan_weno_frac<T>(qr, g, nr, dr);
+    const T r = T(1) / (dl * dr);
+    vl = nl * dr * r;
+    vr = nr * dl * r;
 }
 
 // ---------------------------------------------------------------------------
@@ -325,16 +343,17 @@ struct Moments {
 
 // half: 0 full, +1 u > 0, -1 u < 0
 template <typename T, int DIM, int NU>
-GKS_HD void make_moments(T U, T V, T lam, T K, int half, Moments<T, DIM, NU>& m)
+GKS_HD void make_moments(T U, T V, T lam, T h, T K, int half, Moments<T, DIM, NU>& m)
 {
+    // h = 1 / (2 lam), passed in (the caller has it without a division)
     m.U = U; m.V = V; m.lam = lam;
-    const T h = T(0.5) / lam;
     if (half == 0) {
         m.mu[0] = T(1);
         m.mu[1] = U;
     } else {
         const T sl = sqrt(lam);
-        const T e = exp(-lam * U * U) * T(0.5) / sqrt(T(3.14159265358979323846) * lam);
+        // (1/2) / sqrt(pi lam) = h sqrt(lam) / sqrt(pi)
+        const T e = exp(-lam * U * U) * (h * sl) * T(0.56418958354775628695);
         if (half > 0) {
             m.mu[0] = T(0.5) * erfc(-sl * U);
             m.mu[1] = U * m.mu[0] + e;
@@ -470,22 +489,23 @@ GKS_HD void bil(const M& m, const T* a, const T* b, T* out)
 // (U, V, lam) with unit density: the closed-form inverse of the moment
 // matrix (textbook gas-kinetic solve).  K: internal degrees of freedom.
 template <typename T, int DIM>
-GKS_HD void micro_solve(T U, T V, T lam, T K, const T* b, T* a)
+GKS_HD void micro_solve(T U, T V, T lam, T h, T N, T iN, const T* b, T* a)
 {
+    // h = 1 / (2 lam), N = K + DIM, iN = 1 / N
     if constexpr (DIM == 2) {
-        const T e = U * U + V * V + (K + T(2)) / (T(2) * lam);
+        const T e = U * U + V * V + N * h;
         const T R4 = T(2) * b[3] - e * b[0];
         const T R3 = b[2] - V * b[0];
         const T R2 = b[1] - U * b[0];
-        a[3] = T(4) * lam * lam / (K + T(2)) * (R4 - T(2) * U * R2 - T(2) * V * R3);
+        a[3] = T(4) * iN * lam * lam * (R4 - T(2) * U * R2 - T(2) * V * R3);
         a[2] = T(2) * lam * R3 - V * a[3];
         a[1] = T(2) * lam * R2 - U * a[3];
         a[0] = b[0] - U * a[1] - V * a[2] - T(0.5) * a[3] * e;
     } else {
-        const T e = U * U + (K + T(1)) / (T(2) * lam);
+        const T e = U * U + N * h;
         const T R3 = T(2) * b[3] - e * b[0];
         const T R2 = b[1] - U * b[0];
-        a[3] = T(4) * lam * lam / (K + T(1)) * (R3 - T(2) * U * R2);
+        a[3] = T(4) * iN * lam * lam * (R3 - T(2) * U * R2);
         a[1] = T(2) * lam * R2 - U * a[3];
         a[2] = T(0);
         a[0] = b[0] - U * a[1] - T(0.5) * a[3] * e;
@@ -494,14 +514,16 @@ GKS_HD void micro_solve(T U, T V, T lam, T K, const T* b, T* a)
 
 // primitive variables of a conservative state; false if not physical
 template <typename T, int DIM>
-GKS_HD bool primitive(const T* W, T gamma, T& rho, T& U, T& V, T& lam, T& p)
+GKS_HD bool primitive(const T* W, T gamma, T& rho, T& U, T& V, T& lam, T& p, T& ir, T& ip)
 {
+    // ir = 1 / rho and ip = 1 / p are returned for reuse
     rho = W[0];
-    const T ir = T(1) / rho;
+    ir = T(1) / rho;
     U = W[1] * ir;
     V = (DIM == 2) ? W[2] * ir : T(0);
     p = (gamma - T(1)) * (W[3] - T(0.5) * rho * (U * U + V * V));
-    lam = T(0.5) * rho / p;
+    ip = T(1) / p;
+    lam = T(0.5) * rho * ip;
     return (rho > T(0)) && (p > T(0));
 }
 
@@ -519,7 +541,7 @@ template <typename T> GKS_HD bool physical(const T* W, T gamma, int dim)
 // ke, kte: value coefficients of the e and t*e parts; kde, kdte: slopes.
 // ---------------------------------------------------------------------------
 template <typename D>
-GKS_HD void exp_fit(D tau_n, D dt, D& ke, D& kte, D& kde, D& kdte)
+GKS_HD void exp_fit(D tau_n, D dt, D idt, D& ke, D& kte, D& kde, D& kdte)
 {
     const D x2 = dt / tau_n, x1 = D(0.5) * x2;
     const D q1 = exp(-x1), q2 = exp(-x2);
@@ -527,7 +549,6 @@ GKS_HD void exp_fit(D tau_n, D dt, D& ke, D& kte, D& kde, D& kdte)
     const D Ie1 = tau_n * om1, Ie2 = tau_n * om2;
     const D It1 = tau_n * tau_n * om1 - tau_n * (D(0.5) * dt) * q1;
     const D It2 = tau_n * tau_n * om2 - tau_n * dt * q2;
-    const D idt = D(1) / dt;
     ke = (D(4) * Ie1 - Ie2) * idt;
     kde = D(4) * (Ie2 - D(2) * Ie1) * idt * idt;
     kte = (D(4) * It1 - It2) * idt;
@@ -698,9 +719,16 @@ struct PointOut {
     D FL[4], FdL[4], S0[4], S1[4], S2[4];
 };
 
+// Per-launch constants of the interface point, with the reciprocals formed
+// once per launch instead of at every point: idt = 1 / dt, iN = 1 / (K + DIM).
 struct PointPar {
-    double gamma, K, mu, dt;
+    double gamma, K, mu, dt, idt, iN;
 };
+template <int DIM>
+GKS_HD PointPar point_par(double gamma, double K, double mu, double dt)
+{
+    return PointPar{gamma, K, mu, dt, 1.0 / dt, 1.0 / (K + DIM)};
+}
 
 template <typename D, int NU, int DIM, typename T>
 GKS_HD void cast_moments(const Moments<D, DIM, NU>& a, Moments<T, DIM, NU>& b)
@@ -729,19 +757,20 @@ struct NonEq {
 };
 
 template <typename D, int DIM, typename T = D>
-GKS_HD bool noneq_states(const D* Wl, const D* Wr, D gamma, D K, NonEq<D, DIM, T>& ne, const T* Wlx = nullptr,
+GKS_HD bool noneq_states(const D* Wl, const D* Wr, D gamma, D K, D iN, NonEq<D, DIM, T>& ne, const T* Wlx = nullptr,
                          const T* Wly = nullptr, const T* Wrx = nullptr, const T* Wry = nullptr)
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) { ne.Xs[k] = D(0); ne.Xf[k] = D(0); ne.Hn[k] = T(0); ne.Hm[k] = T(0); }
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-        D rs, Us, Vs, ls, ps;
-        if (!primitive<D, DIM>(side ? Wr : Wl, gamma, rs, Us, Vs, ls, ps)) return false;
+        D rs, Us, Vs, ls, ps, irs_d, ips;
+        if (!primitive<D, DIM>(side ? Wr : Wl, gamma, rs, Us, Vs, ls, ps, irs_d, ips)) return false;
+        const D hs = ps * irs_d; // 1 / (2 lam) = p / rho
         if (side) ne.pr = ps;
         else ne.pl = ps;
         Moments<D, DIM, 7> m;
-        make_moments<D, DIM, 7>(Us, Vs, ls, K, side ? -1 : +1, m);
+        make_moments<D, DIM, 7>(Us, Vs, ls, hs, K, side ? -1 : +1, m);
         D h[4] = {D(0), D(0), D(0), D(0)};
         psi_mom<0, 0, DIM>(m, h);
 #pragma unroll
@@ -754,15 +783,15 @@ GKS_HD bool noneq_states(const D* Wl, const D* Wr, D gamma, D K, NonEq<D, DIM, T
             const T* Wt = side ? Wry : Wly;
             Moments<T, DIM, 7> mt;
             cast_moments<D, 7, DIM, T>(m, mt);
-            const T rt = T(rs), irs = T(1) / T(rs), K_t = T(K);
+            const T rt = T(rs), irs = T(irs_d), h_t = T(hs), N_t = T(K) + T(DIM), iN_t = T(iN);
             T b[4], as1[4], as2[4] = {T(0), T(0), T(0), T(0)}, h2[4], h3[4], t1[4], t2[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) b[k] = Wn[k] * irs;
-            micro_solve<T, DIM>(mt.U, mt.V, mt.lam, K_t, b, as1);
+            micro_solve<T, DIM>(mt.U, mt.V, mt.lam, h_t, N_t, iN_t, b, as1);
             if constexpr (DIM == 2) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) b[k] = Wt[k] * irs;
-                micro_solve<T, DIM>(mt.U, mt.V, mt.lam, K_t, b, as2);
+                micro_solve<T, DIM>(mt.U, mt.V, mt.lam, h_t, N_t, iN_t, b, as2);
             }
             lin<1, 0, DIM>(mt, as1, h2); // <a1 u psi>_half
             lin<2, 0, DIM>(mt, as1, h3); // <a1 u^2 psi>_half
@@ -784,7 +813,7 @@ template <typename D, int DIM>
 GKS_HD bool kinetic_average(const D* Wl, const D* Wr, D gamma, D K, D* W0)
 {
     NonEq<D, DIM> ne;
-    if (!noneq_states<D, DIM>(Wl, Wr, gamma, K, ne)) return false;
+    if (!noneq_states<D, DIM>(Wl, Wr, gamma, K, D(0), ne)) return false; // no slopes: iN unused
 #pragma unroll
     for (int k = 0; k < 4; ++k) W0[k] = ne.Xs[k];
     return true;
@@ -797,29 +826,29 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
                       PointOut<D>& out)
 {
     const D gammad = D(par.gamma);
-    D r0d, U0d, V0d, l0d, p0d;
-    if (!primitive<D, DIM>(W0d, gammad, r0d, U0d, V0d, l0d, p0d)) return false;
+    D r0d, U0d, V0d, l0d, p0d, ir0d, ip0d;
+    if (!primitive<D, DIM>(W0d, gammad, r0d, U0d, V0d, l0d, p0d, ir0d, ip0d)) return false;
 
     // collision times (Sec. 4): physical tau in the Navier-Stokes terms,
     // numerical tau_n (with the pressure-jump term) in the exponentials
     const D dtd = D(par.dt);
     const D jump = tabs((ne.pl - ne.pr) / (ne.pl + ne.pr)) * dtd;
-    const D tau_d = par.mu > 0.0 ? D(par.mu) / p0d : D(0);
+    const D tau_d = par.mu > 0.0 ? D(par.mu) * ip0d : D(0);
     const D tau_n = par.mu > 0.0 ? tau_d + jump : D(0.01) * dtd + jump;
     D ke, kte, kde, kdte;
-    exp_fit<D>(tau_n, dtd, ke, kte, kde, kdte);
+    exp_fit<D>(tau_n, dtd, D(par.idt), ke, kte, kde, kdte);
 
     // ---- equilibrium part in central velocities (type T) ----
     Central<T> C;
-    const T r0 = T(r0d), ir0 = T(1) / T(r0d);
+    const T r0 = T(r0d), ir0 = T(ir0d);
     C.U = T(U0d);
     C.V = T(V0d);
     C.E0 = T(0.5) * (C.U * C.U + C.V * C.V);
     C.N = T(par.K) + T(DIM);
     C.h[0] = T(1);
-    C.h[1] = T(p0d / r0d);
-    C.ih = T(r0d / p0d);
-    C.iN = T(1) / C.N;
+    C.h[1] = T(p0d * ir0d);
+    C.ih = T(r0d * ip0d);
+    C.iN = T(par.iN);
 #pragma unroll
     for (int n = 2; n < 7; ++n) C.h[n] = C.h[n - 1] * C.h[1];
     const T U = C.U, V = C.V;

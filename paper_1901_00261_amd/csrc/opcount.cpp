@@ -143,7 +143,7 @@ int main()
             }
         }
         auto rv = [&](int q, int k, int r) { return rows[q][k][r]; };
-        const gks::PointPar par{gamma, K2, ns ? 1e-4 : 0.0, 1e-3};
+        const gks::PointPar par = gks::point_par<2>(gamma, K2, ns ? 1e-4 : 0.0, 1e-3);
         const size_t first = cnt::g.size();
         bool ok = true;
         std::vector<Cnt> all, s2;
@@ -153,7 +153,7 @@ int main()
             Cnt W0[4], Wl[4], Wr[4];
             gks::gp_inputs<Cnt, Cnt>(rv, G, Cnt(0.01), true, Cnt(gamma), in, W0, Wl, Wr);
             gks::NonEq<Cnt, 2> ne;
-            ok = ok && gks::noneq_states<Cnt, 2>(Wl, Wr, Cnt(gamma), Cnt(K2), ne, in.Wlx, in.Wly, in.Wrx, in.Wry) &&
+            ok = ok && gks::noneq_states<Cnt, 2>(Wl, Wr, Cnt(gamma), Cnt(K2), Cnt(par.iN), ne, in.Wlx, in.Wly, in.Wrx, in.Wry) &&
                  gks::gks_point<Cnt, 2, Cnt>(par, in, ne.Xs, ne, out);
             push4(all, out.FL); push4(all, out.FdL); push4(all, out.S0); push4(all, out.S1); push4(all, out.S2);
             push4(s2, out.FdL); push4(s2, out.S2);
@@ -185,8 +185,8 @@ int main()
             in.Wly[k] = in.Wry[k] = 0.0;
         }
         gks::NonEq<Cnt, 1> ne;
-        ok = ok && gks::noneq_states<Cnt, 1>(o[3], o[4], Cnt(gamma), Cnt(K1), ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
-        const gks::PointPar par{gamma, K1, 0.0, 1e-3};
+        const gks::PointPar par = gks::point_par<1>(gamma, K1, 0.0, 1e-3);
+        ok = ok && gks::noneq_states<Cnt, 1>(o[3], o[4], Cnt(gamma), Cnt(K1), Cnt(par.iN), ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
         ok = ok && gks::gks_point<Cnt, 1, Cnt>(par, in, ne.Xs, ne, out);
         if (!ok) {
             fprintf(stderr, "opcount: unexpected non-physical sample\n");
