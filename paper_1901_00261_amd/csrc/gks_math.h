@@ -203,17 +203,17 @@ struct CharFrame {
     T U, V, c, H, b1, b2, ic;
     GKS_HD bool init(const T* W, T gamma)
     {
-        const T rho = W[0];
-        U = W[1] / rho;
-        V = (DIM == 2) ? W[2] / rho : T(0);
+        const T rho = W[0], ir = T(1) / rho;
+        U = W[1] * ir;
+        V = (DIM == 2) ? W[2] * ir : T(0);
         const T q2 = U * U + V * V;
         const T p = (gamma - T(1)) * (W[3] - T(0.5) * rho * q2);
         if (!(rho > T(0)) || !(p > T(0))) return false;
-        c = sqrt(gamma * p / rho);
-        H = (W[3] + p) / rho;
-        b1 = (gamma - T(1)) / (c * c);
-        b2 = T(0.5) * q2 * b1;
+        c = sqrt(gamma * p * ir);
+        H = (W[3] + p) * ir;
         ic = T(1) / c;
+        b1 = (gamma - T(1)) * ic * ic;
+        b2 = T(0.5) * q2 * b1;
         return true;
     }
     // row a of L = R^{-1}
