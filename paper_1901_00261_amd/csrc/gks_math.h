@@ -544,8 +544,9 @@ template <typename D>
 GKS_HD void exp_fit(D tau_n, D dt, D idt, D& ke, D& kte, D& kde, D& kdte)
 {
     const D x2 = dt / tau_n, x1 = D(0.5) * x2;
-    const D q1 = exp(-x1), q2 = exp(-x2);
-    const D om1 = -expm1(-x1), om2 = -expm1(-x2); // 1 - e^{-x}
+    // e^{-x2} = (e^{-x1})^2 and 1 - e^{-x2} = (1 - e^{-x1})(1 + e^{-x1})
+    const D q1 = exp(-x1), q2 = q1 * q1;
+    const D om1 = -expm1(-x1), om2 = om1 * (D(1) + q1); // 1 - e^{-x}
     const D Ie1 = tau_n * om1, Ie2 = tau_n * om2;
     const D It1 = tau_n * tau_n * om1 - tau_n * (D(0.5) * dt) * q1;
     const D It2 = tau_n * tau_n * om2 - tau_n * dt * q2;
