@@ -578,14 +578,57 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
 // value).  rv(q, k, r): quantity q (face_recon order), component k, row
 // r = 0..4 (rows j-2..j+2).  Values in type D: W0 (linear), Wl, Wr.
 //
-// gp_inputs_k forms component k alone (it reads only rv(., k, .)), so a
-// caller can stage the stencil one component at a time; gp_fallback then
-// applies the positivity fallback, which reads the centre row of all four.
+// The inputs of component k come in two independent groups: gp_noneq_k
+// forms the non-equilibrium values and derivatives (quantities 3-6 of
+// face_recon), gp_equil_k the equilibrium value and derivatives
+// (quantities 0-2); each reads only rv(., k, .), so a caller can stage the
+// stencil one component at a time and form the second group after the
+// non-equilibrium states have been evaluated.  gp_fallback then applies the
+// positivity fallback, which reads the centre row of all four components.
 template <typename T, typename D, typename Acc>
-GKS_HD void gp_inputs_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T>& in, D* W0, D* Wl, D* Wr)
+GKS_HD void gp_noneq_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T>& in, D* Wl, D* Wr)
 {
-    D v0 = D(0), v1 = D(0), v2 = D(0), v5 = D(0), v6 = D(0), d0 = D(0), d1 = D(0), d3 = D(0), d4 = D(0),
-      dd0 = D(0);
+    D v5 = D(0), v6 = D(0), d3 = D(0), d4 = D(0);
+    const D base = rv(0, k, 2);
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        const D c0 = D(kTanLin[g][0][r]), c1 = D(kTanLin[g][1][r]);
+        v5 += c0 * rv(5, k, r);
+        v6 += c0 * rv(6, k, r);
+        d3 += c1 * (rv(3, k, r) - base);
+        d4 += c1 * (rv(4, k, r) - base);
+    }
+    in.Wlx[k] = T(v5);
+    in.Wrx[k] = T(v6);
+    in.Wly[k] = T(d3 * iht);
+    in.Wry[k] = T(d4 * iht);
+    // both values formed first and stored once: stores to different arrays
+    // in the two branches would otherwise be merged into one store through a
+    // selected pointer, which keeps the arrays in scratch memory
+    D wl, wr;
+    if (weno) {
+        D ql[5], qr[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
+        D vl, vr;
+        tan_weno_pair<D>(ql, qr, g, vl, vr);
+        wl = base + vl;
+        wr = base + vr;
+    } else {
+        // linear mode: both states are the equilibrium value
+        D v0 = D(0);
+#pragma unroll
+        for (int r = 0; r < 5; ++r) v0 += D(kTanLin[g][0][r]) * (rv(0, k, r) - base);
+        wl = wr = base + v0;
+    }
+    Wl[k] = wl;
+    Wr[k] = wr;
+}
+
+template <typename T, typename D, typename Acc>
+GKS_HD void gp_equil_k(const Acc& rv, int g, int k, D iht, PointIn<T>& in, D* W0)
+{
+    D v0 = D(0), v1 = D(0), v2 = D(0), d0 = D(0), d1 = D(0), dd0 = D(0);
     const D base = rv(0, k, 2);
 #pragma unroll
     for (int r = 0; r < 5; ++r) {
@@ -598,10 +641,6 @@ GKS_HD void gp_inputs_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T
         v1 += c0 * q1;
         d1 += c1 * q1;
         v2 += c0 * rv(2, k, r);
-        v5 += c0 * rv(5, k, r);
-        v6 += c0 * rv(6, k, r);
-        d3 += c1 * (rv(3, k, r) - base);
-        d4 += c1 * (rv(4, k, r) - base);
     }
     W0[k] = base + v0;
     in.W0x[k] = T(v1);
@@ -609,25 +648,6 @@ GKS_HD void gp_inputs_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T
     in.W0y[k] = T(d0 * iht);
     in.W0xy[k] = T(d1 * iht);
     in.W0yy[k] = T(dd0 * iht * iht);
-    in.Wlx[k] = T(v5);
-    in.Wrx[k] = T(v6);
-    in.Wly[k] = T(d3 * iht);
-    in.Wry[k] = T(d4 * iht);
-    // both values formed first and stored once: stores to different arrays
-    // in the two branches would otherwise be merged into one store through a
-    // selected pointer, which keeps the arrays in scratch memory
-    D wl = W0[k], wr = W0[k];
-    if (weno) {
-        D ql[5], qr[5];
-#pragma unroll
-        for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
-        D vl, vr;
-        tan_weno_pair<D>(ql, qr, g, vl, vr);
-        wl = base + vl;
-        wr = base + vr;
-    }
-    Wl[k] = wl;
-    Wr[k] = wr;
 }
 
 template <typename D, typename Acc>
@@ -648,7 +668,10 @@ GKS_HD void gp_inputs(const Acc& rv, int g, D ht, bool weno, D gamma, PointIn<T>
 {
     const D iht = D(1) / ht;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) gp_inputs_k<T, D>(rv, g, k, iht, weno, in, W0, Wl, Wr);
+    for (int k = 0; k < 4; ++k) {
+        gp_equil_k<T, D>(rv, g, k, iht, in, W0);
+        gp_noneq_k<T, D>(rv, g, k, iht, weno, in, Wl, Wr);
+    }
     gp_fallback<D>(rv, weno, gamma, Wl, Wr);
 }
 
@@ -808,13 +831,17 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
                 else if (k == 2) stage_wait<2>();
                 else stage_wait<3>();
             }
-            gp_inputs_k<T, double>(rd[k], g, k, iht, weno, in, W0, Wl, Wr);
+            gp_noneq_k<T, double>(rd[k], g, k, iht, weno, in, Wl, Wr);
         }
         if (ok) {
             gp_fallback<double>(rv, weno, par.gamma, Wl, Wr);
             NonEq<double, 2, T> ne;
             PointOut<double> o;
             ok = noneq_states<double, 2, T>(Wl, Wr, par.gamma, par.K, par.iN, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+            // the equilibrium inputs only now, so they are not held across
+            // the non-equilibrium states
+#pragma unroll
+            for (int k = 0; k < 4; ++k) gp_equil_k<T, double>(rd[k], g, k, iht, in, W0);
             if (ok) {
                 // equilibrium state: the kinetic average (WENO-Z) or the linear
                 // value, selected per element so that every array stays in

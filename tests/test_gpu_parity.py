@@ -384,11 +384,15 @@ def test_2d_gamma(gamma):
     check(p, got, oracle_run(p, max_steps=4))
 
 
-@pytest.mark.parametrize("nx,ny,bc,steps", [(4, 4, (0, 0, 0, 0), 5), (4, 5, (2, 2, 2, 2), 5), (130, 70, (2, 1, 0, 0), 3)])
+@pytest.mark.parametrize("nx,ny,bc,steps", [(4, 4, (0, 0, 0, 0), 5), (4, 5, (2, 2, 2, 2), 5), (130, 70, (2, 1, 0, 0), 3),
+                                             (67, 11, (1, 1, 0, 0), 3), (5, 131, (0, 0, 2, 1), 3)])
 def test_2d_smallest_and_ragged_grids(nx, ny, bc, steps):
     """The smallest grid the library accepts (4 cells a side, every stencil
-    wraps or mirrors several times) and a ragged grid larger than one tile in
-    both directions (partial tiles in every kernel), against the oracle."""
+    wraps or mirrors several times) and ragged grids larger than one tile
+    (partial tiles in every kernel), against the oracle.  Odd row lengths of
+    the face-row buffers (nx + 1 or nx + 4 odd, stored with an even stride),
+    tile rows of 1, 2 and 3 face rows, and a tall grid whose interface
+    workgroups at the far edge copy rows past the last plane."""
     p = wl.pulse_box_2d(nx, ny=ny, bc=bc)
     g = gks()
     S = g.Solver(p)
