@@ -127,10 +127,14 @@ def time_2d(prob, prec, steps, warmup):
 def roofline_2d(prob, res, ops, prec):
     """Interface (Gauss-point) kernel: algorithmic flops per launch = face
     rows per launch x 3 Gauss points x flops per Gauss point (stage 1 and
-    stage 2 launches alternate, so the mean of the two stage counts)."""
+    stage 2 launches alternate, so the mean of the two stage counts).  A
+    direction with n cells has n + 1 distinct faces, n when periodic (its
+    last face is its first)."""
     key = "gauss_point_ns" if prob.mu > 0 else "gauss_point_euler"
     fpg = 0.5 * (ops[key]["flops"] + ops[key + "_s2"]["flops"])
-    rows = ((prob.nx + 1) * prob.ny + (prob.ny + 1) * prob.nx) / 2.0
+    nfx = prob.nx + (0 if prob.bc[0] == 0 else 1)
+    nfy = prob.ny + (0 if prob.bc[2] == 0 else 1)
+    rows = (nfx * prob.ny + nfy * prob.nx) / 2.0
     flops = rows * 3 * fpg
     ms, n = res["kernels"]["interface"]
     avg_s = ms / max(n, 1) / 1e3

@@ -75,6 +75,12 @@ __device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi, int
     return c;
 }
 
+// Faces of a 2-D direction with n cells that the interface kernel
+// computes: with periodic ends the last face (index n) is the first one
+// (the same stencil after the wrap, so the same result), so it is computed
+// once and the cell update reads it as face 0.
+__host__ __device__ inline int faces_computed(int n, int bc_lo) { return bc_lo == 0 ? n : n + 1; }
+
 // Local-frame stencil entry (slot 1 = normal momentum, slot 2 = tangential
 // momentum in 2-D) of a cell reached through map_index along the normal
 // (kn) and the transverse (kt) direction: values w, normal slopes d.
@@ -768,7 +774,8 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
     const int nt = DIR == 0 ? ny : nx;
     const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
     const int Bs = row_stride(B);
-    const int bw = DIR == 0 ? nf : nt; // extent of the lane index
+    const int nfc = faces_computed(nf - 1, DIR == 0 ? P.bc[0] : P.bc[2]);
+    const int bw = DIR == 0 ? nfc : nt; // extent of the lane index
     int tx, ty;
     tile_xy((bw + kGpX - 1) / kGpX, tx, ty);
     const int lane = threadIdx.x;
@@ -778,7 +785,7 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
     const int face = DIR == 0 ? b : a, tc = DIR == 0 ? a : b;
     // Lanes outside the grid take part in the staging and the barriers and
     // compute on whatever the slots hold there, but store nothing.
-    const bool valid = face < nf && tc < nt;
+    const bool valid = face < nfc && tc < nt;
     const size_t AB = (size_t)A * Bs;
     // the host guarantees row_buffer_doubles(nx, ny, DIR) * 8 < 2^32
     const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(
@@ -920,13 +927,16 @@ __global__ void __launch_bounds__(256) cell2d_kernel(const ProbParam* __restrict
     if (live) {
         const size_t c = (size_t)j * nx + i;
         const size_t fx = (size_t)j * (nx + 1) + i, fy = (size_t)j * nx + i;
+        // right and top faces; a periodic direction's last face is its first
+        const size_t fxr = (P.bc[0] == 0 && i == nx - 1) ? fx - i : fx + 1;
+        const size_t fyt = (P.bc[2] == 0 && j == ny - 1) ? (size_t)i : fy + nx;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double dL = -(FdLx[k * nfx + fx + 1] - FdLx[k * nfx + fx]) * idx -
-                              (FdLy[k * nfy + fy + nx] - FdLy[k * nfy + fy]) * idy;
+            const double dL = -(FdLx[k * nfx + fxr] - FdLx[k * nfx + fx]) * idx -
+                              (FdLy[k * nfy + fyt] - FdLy[k * nfy + fy]) * idy;
             if (STAGE == 1) {
-                const double L = -(FLx[k * nfx + fx + 1] - FLx[k * nfx + fx]) * idx -
-                                 (FLy[k * nfy + fy + nx] - FLy[k * nfy + fy]) * idy;
+                const double L = -(FLx[k * nfx + fxr] - FLx[k * nfx + fx]) * idx -
+                                 (FLy[k * nfy + fyt] - FLy[k * nfy + fy]) * idy;
                 const double w = W[((size_t)cur * 4 + k) * plane + c];
                 W[((size_t)nxt * 4 + k) * plane + c] = msmd_half(w, L, dL, dt);
                 PW[k * plane + c] = msmd_pred(w, L, dL, dt);
@@ -934,8 +944,8 @@ __global__ void __launch_bounds__(256) cell2d_kernel(const ProbParam* __restrict
                 wn[k] = msmd_corr(PW[k * plane + c], dL, dt);
                 W[((size_t)nxt * 4 + k) * plane + c] = wn[k];
             }
-            Wx[((size_t)nxt * 4 + k) * plane + c] = (Wfx[k * nfx + fx + 1] - Wfx[k * nfx + fx]) * idx;
-            Wy[((size_t)nxt * 4 + k) * plane + c] = (Wfy[k * nfy + fy + nx] - Wfy[k * nfy + fy]) * idy;
+            Wx[((size_t)nxt * 4 + k) * plane + c] = (Wfx[k * nfx + fxr] - Wfx[k * nfx + fx]) * idx;
+            Wy[((size_t)nxt * 4 + k) * plane + c] = (Wfy[k * nfy + fyt] - Wfy[k * nfy + fy]) * idy;
         }
     }
     if (STAGE == 2) {
