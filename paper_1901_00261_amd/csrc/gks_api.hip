@@ -241,7 +241,7 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
     // 1-D grids of 2-D tiles; the kernels map workgroups to tiles per XCD.
     // x faces: rows (ny + 4) x faces (nx + 1); y faces: faces (ny + 1) x columns (nx + 4)
     auto tiles = [](int ext_x, int ext_y, dim3 b) { return ((ext_x + b.x - 1) / b.x) * ((ext_y + b.y - 1) / b.y); };
-    const int grx = tiles(nx + 1, ny + 4, br), gry = tiles(nx + 4, ny + 1, br);
+    const int grx = tiles(gks::faces_computed(nx, P.bc[0]), ny + 4, br), gry = tiles(nx + 4, gks::faces_computed(ny, P.bc[2]), br);
     const int ggx = tiles(gks::faces_computed(nx, P.bc[0]), ny, bg), ggy = tiles(nx, gks::faces_computed(ny, P.bc[2]), bg);
     const int gc = tiles(nx, ny, bc);
     for (int stage = 1; stage <= 2; ++stage) {

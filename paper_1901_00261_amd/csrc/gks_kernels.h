@@ -536,11 +536,14 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
     const int nf = DIR == 0 ? nx + 1 : ny + 1;
     const int nt = DIR == 0 ? ny : nx;
     const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
+    // rows computed: the faces the interface kernel uses (faces_computed)
+    const int nfc = faces_computed(nf - 1, DIR == 0 ? P.bc[0] : P.bc[2]);
+    const int Ac = DIR == 0 ? A : nfc, Bc = DIR == 0 ? nfc : B;
     int tx, ty;
-    tile_xy((B + blockDim.x - 1) / blockDim.x, tx, ty);
+    tile_xy((Bc + blockDim.x - 1) / blockDim.x, tx, ty);
     const int b = tx * blockDim.x + threadIdx.x;
     const int a = ty * blockDim.y + threadIdx.y;
-    if (a >= A || b >= B) return;
+    if (a >= Ac || b >= Bc) return;
     const int face = DIR == 0 ? b : a;
     const int tr = (DIR == 0 ? a : b) - 2; // transverse index, -2 .. nt+1
     const int buf = stage == 1 ? S.cur : 1 - S.cur;
