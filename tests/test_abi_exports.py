@@ -73,6 +73,13 @@ def test_host_validation_without_gpu():
                      np.zeros(1), np.zeros(1), np.zeros(1))
     st, msg = init([big], [(big.W, big.Wx, big.Wy)])
     assert st == gks.GKS_EINVAL and "too large" in msg
+    # the exact padded buffer size decides: with nx = 5 the y-face rows of 9
+    # values are stored with stride 10, so at ny = 1917395 that buffer passes
+    # 2^32 bytes although 28 (nx + 4)(ny + 4) doubles would still fit
+    tall = wl.Problem(2, 5, 1917395, 0.0, 1.0, 0.0, 1.0, 1.4, 0.0, 0.3, 0.0, 1.0, 8, 1, (1, 1, 1, 1),
+                      np.zeros(1), np.zeros(1), np.zeros(1))
+    st, msg = init([tall], [(tall.W, tall.Wx, tall.Wy)])
+    assert st == gks.GKS_EINVAL and "too large" in msg
     two2d = [wl.isentropic_vortex_2d(8), wl.isentropic_vortex_2d(8)]
     st, msg = init(two2d, [(q.W, q.Wx, q.Wy) for q in two2d])
     assert st == gks.GKS_EINVAL and "exactly one" in msg
