@@ -240,12 +240,13 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
 //               after an error, the problem stops with W^n kept.
 //   Then the next dt follows from the maximum signal speed of the state.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void finish_problem(const ProbParam& P, ProbState& S, int commit)
+// Returns true when the problem stops here (error or t_end reached).
+__device__ __forceinline__ bool finish_problem(const ProbParam& P, ProbState& S, int commit)
 {
-    if (!S.active) return;
+    if (!S.active) return false;
     if (S.err) {
         S.active = 0;
-        return;
+        return true;
     }
     if (commit) {
         S.cur = 1 - S.cur;
@@ -256,7 +257,7 @@ __device__ __forceinline__ void finish_problem(const ProbParam& P, ProbState& S,
     S.smax = 0ull;
     if (!(S.t < P.t_end)) {
         S.active = 0;
-        return;
+        return true;
     }
     double dt = P.dt_fixed > 0.0 ? P.dt_fixed : P.cfl / smax;
     int last = 0;
@@ -266,6 +267,7 @@ __device__ __forceinline__ void finish_problem(const ProbParam& P, ProbState& S,
     }
     S.dt = dt;
     S.last = last;
+    return false;
 }
 
 // one thread per problem (initial dt, and the 2-D step); ctr: work counters
@@ -330,8 +332,8 @@ __global__ void __launch_bounds__(kCompactThreads) compact_items_kernel(const Pr
 // workgroup reaches the exit.  The item list holds only the problems still
 // active; its length is read from device memory.  The last workgroup of the
 // second stage to finish (a done-counter, ctr[2]) commits the step for every
-// problem, resets the counters and rebuilds the list for the next step, so
-// a step is two launches.  Faces owned by the tile (all but its last face, plus the
+// problem, resets the counters and, when a problem has stopped, rebuilds the
+// list for the next step, so a step is two launches.  Faces owned by the tile (all but its last face, plus the
 // problem's last face) carry the MSMD partial Pf from stage 1 to stage 2.
 // ---------------------------------------------------------------------------
 template <typename T, int STAGE, int BLK>
@@ -456,21 +458,27 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
     if (STAGE == 2) {
         // the last workgroup to finish commits the step for every problem,
         // sets the next dt and builds the next step's work list
-        __shared__ int sh_last;
+        __shared__ int sh_last, sh_stopped;
         __shared__ int sh_scan[BLK];
         // (the last workgroup reads only what other workgroups wrote with
         // device-scope atomics: the error flags and the signal-speed maxima;
         // the barrier waits for this workgroup's atomics to complete)
         __syncthreads();
-        if (t == 0) sh_last = atomicAdd(&ctr[2], 1u) == gridDim.x - 1;
+        if (t == 0) {
+            sh_last = atomicAdd(&ctr[2], 1u) == gridDim.x - 1;
+            sh_stopped = 0;
+        }
         __syncthreads();
         if (sh_last) {
             __threadfence(); // acquire: no stale cached copies of the problem states
-            for (int p = t; p < nprob; p += BLK) finish_problem(PP[p], PS[p], 1);
+            bool stopped = false;
+            for (int p = t; p < nprob; p += BLK) stopped |= finish_problem(PP[p], PS[p], 1);
+            if (stopped) atomicOr(&sh_stopped, 1);
             if (t < 3) ctr[t] = 0u;
             __threadfence();
             __syncthreads();
-            compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
+            // the list changes only when a problem has stopped
+            if (sh_stopped) compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
         }
     }
 }
