@@ -346,6 +346,7 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
                                                       const int* __restrict__ first, const int* __restrict__ count)
 {
     __shared__ double sh_FL[3][BLK], sh_FdL[3][BLK], sh_Wf[3][BLK];
+    __shared__ double sh_cell[3][BLK], sh_face[3][BLK]; // the item's staged cell and face values
     __shared__ int sh_item;
     const int t = threadIdx.x;
     const int nitems = *nitems_p;
@@ -361,6 +362,34 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
         if (!S.active) continue; // uniform over the workgroup
         const int cur = S.cur, nxt = 1 - cur;
         const double dt = S.dt;
+        // The item's values that the end of the stage needs (stage 1: W^n of
+        // its cells; stage 2: the partials PW of its cells and Pf of its
+        // faces) are copied into LDS with direct-to-LDS loads issued with the
+        // stencil loads, so their latency overlaps.  Each wave copies its own
+        // lanes' values (dword copies: lane l moves half l & 1 of value
+        // l >> 1 of a 32-value run), so no other wave waits for them;
+        // indices are clamped into the problem (values of lanes without a
+        // cell or face are not used).
+        {
+            const int wv = t & ~63, l = t & 63;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int v = wv + 32 * c + (l >> 1);
+                const long long cell = P.coff + min(tl.start + v, P.nx - 1);
+                const long long face = P.foff + min(tl.start + v, P.nx);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double* src = STAGE == 1 ? W + ((size_t)cur * 3 + k) * Ntot + cell : PW + k * Ntot + cell;
+                    __builtin_amdgcn_global_load_lds((const void*)((const char*)src + (l & 1) * 4),
+                                                     (__attribute__((address_space(3))) void*)&sh_cell[k][wv + 32 * c],
+                                                     4, 0, 0);
+                    if (STAGE == 2)
+                        __builtin_amdgcn_global_load_lds((const void*)((const char*)(Pf + k * F + face) + (l & 1) * 4),
+                                                         (__attribute__((address_space(3))) void*)&sh_face[k][wv + 32 * c],
+                                                         4, 0, 0);
+                }
+            }
+        }
         // ---- faces c0 .. c0 + BLK - 1
         const int f = tl.start + t;
         if (f <= P.nx) {
@@ -415,7 +444,7 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
                     sh_Wf[k][t] = msmd_half(s0, s1, s2, dt);
                     if (own) Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
                 } else {
-                    sh_Wf[k][t] = msmd_corr(Pf[k * F + g], out.S2[sl], dt);
+                    sh_Wf[k][t] = msmd_corr(sh_face[k][t], out.S2[sl], dt);
                 }
             }
         }
@@ -433,11 +462,11 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
                 const double slope = (sh_Wf[k][t + 1] - sh_Wf[k][t]) * idx;
                 if (STAGE == 1) {
                     const double L = -(sh_FL[k][t + 1] - sh_FL[k][t]) * idx;
-                    const double w = W[((size_t)cur * 3 + k) * Ntot + c];
+                    const double w = sh_cell[k][t];
                     W[((size_t)nxt * 3 + k) * Ntot + c] = msmd_half(w, L, dL, dt);
                     PW[k * Ntot + c] = msmd_pred(w, L, dL, dt);
                 } else {
-                    wn[k] = msmd_corr(PW[k * Ntot + c], dL, dt);
+                    wn[k] = msmd_corr(sh_cell[k][t], dL, dt);
                     W[((size_t)nxt * 3 + k) * Ntot + c] = wn[k];
                 }
                 Wx[((size_t)nxt * 3 + k) * Ntot + c] = slope;
