@@ -69,8 +69,8 @@ struct gks_handle {
     // step graph
     bool use_graph = true;
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr, graphK = nullptr;
+    hipGraphExec_t gexec = nullptr, gexecK = nullptr; // one step, kGraphSteps steps
 };
 
 namespace {
@@ -296,11 +296,20 @@ void drop_graph(gks_handle* h)
 {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
-    h->gexec = nullptr;
-    h->graph = nullptr;
+    if (h->gexecK) (void)hipGraphExecDestroy(h->gexecK);
+    if (h->graphK) (void)hipGraphDestroy(h->graphK);
+    h->gexec = h->gexecK = nullptr;
+    h->graph = h->graphK = nullptr;
 }
 
-// capture one MSMD step (kernel nodes only) on the private capture stream
+// steps per replay of the long graph: fewer graph launches, so fewer gaps
+// between steps and less host work per step
+constexpr int kGraphSteps = 8;
+
+// capture one MSMD step, and kGraphSteps steps in a row, (kernel nodes
+// only) on the private capture stream; a step's launches depend only on
+// device state, so a replay of the long graph equals kGraphSteps replays of
+// the short one
 int build_graph(gks_handle* h)
 {
     drop_graph(h);
@@ -309,6 +318,10 @@ int build_graph(gks_handle* h)
     launch_step(h, h->cap);
     HIP_TRY(h, hipStreamEndCapture(h->cap, &h->graph));
     HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    HIP_TRY(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    for (int s = 0; s < kGraphSteps; ++s) launch_step(h, h->cap);
+    HIP_TRY(h, hipStreamEndCapture(h->cap, &h->graphK));
+    HIP_TRY(h, hipGraphInstantiate(&h->gexecK, h->graphK, nullptr, nullptr, 0));
     return GKS_OK;
 }
 
@@ -690,7 +703,10 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
         const int st = build_graph(h);
         if (st) return st;
     }
-    for (int s = 0; s < max_steps; ++s) {
+    int s = 0;
+    if (graph)
+        for (; s + kGraphSteps <= max_steps; s += kGraphSteps) HIP_TRY(h, hipGraphLaunch(h->gexecK, h->stream));
+    for (; s < max_steps; ++s) {
         if (graph) HIP_TRY(h, hipGraphLaunch(h->gexec, h->stream));
         else launch_step(h, h->stream);
     }
