@@ -809,17 +809,6 @@ GKS_HD bool noneq_states(const D* Wl, const D* Wr, D gamma, D K, D iN, NonEq<D, 
     return true;
 }
 
-// Kinetic average of two states: int psi [g_l H(u) + g_r (1 - H(u))]
-template <typename D, int DIM>
-GKS_HD bool kinetic_average(const D* Wl, const D* Wr, D gamma, D K, D* W0)
-{
-    NonEq<D, DIM> ne;
-    if (!noneq_states<D, DIM>(Wl, Wr, gamma, K, D(0), ne)) return false; // no slopes: iN unused
-#pragma unroll
-    for (int k = 0; k < 4; ++k) W0[k] = ne.Xs[k];
-    return true;
-}
-
 // W0d: equilibrium state (type D); ne: the two non-equilibrium states.
 // Returns false for a non-physical equilibrium state.
 template <typename T, int DIM, typename D = double>

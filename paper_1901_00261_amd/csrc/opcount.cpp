@@ -1,7 +1,7 @@
 // opcount.cpp -- algorithmic operation count of the interface arithmetic.
 //
 // Host program: instantiates the same templates the kernels use
-// (face_recon, gp_inputs, kinetic_average, gks_point) with a counting scalar
+// (face_recon, gp_inputs, noneq_states, gks_point) with a counting scalar
 // type and tallies the +, -, *, / and sqrt / exp / expm1 / erfc on which
 // the unit's outputs depend, for one representative smooth input.  Sign
 // changes and comparisons are not counted; a fused multiply-add counts as
