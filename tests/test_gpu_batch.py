@@ -104,8 +104,9 @@ def test_graph_replays_match_eager_with_host_reads(batch):
         os.environ.pop("GKS_GRAPH", None)
         os.environ.pop("GKS_TUNE", None)
     for rep in range(6):
-        A.step(3)
-        B.step(3)
+        n = 3 if rep % 2 == 0 else 11  # 11: one eight-step replay and three one-step replays
+        A.step(n)
+        B.step(n)
         for p in (0, 5, 11):  # host reads between replays
             a, b = A.state(p), B.state(p)
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4], (rep, p)
@@ -135,8 +136,9 @@ def test_2d_graph_matches_eager():
         os.environ.pop("GKS_GRAPH")
     A = g.Solver(p)
     for rep in range(3):
-        A.step(2)
-        B.step(2)
+        n = 2 if rep != 1 else 9  # 9: one eight-step replay and one one-step replay
+        A.step(n)
+        B.step(n)
         a, b = A.state(0), B.state(0)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
     A.close()
