@@ -278,7 +278,7 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
                                                       h->FLy, h->FdLy, h->Wfsy);
         record(h, st, 2, false);
     }
-    gks::finish_kernel<<<1, 64, 0, st>>>(h->dP, h->dS, 1, 1, nullptr);
+    gks::finish_kernel<<<1, 64, 0, st>>>(h->dP, h->dS, 1, 1, nullptr, 2);
 }
 
 void launch_step(gks_handle* h, hipStream_t st)
@@ -384,8 +384,8 @@ int autotune(gks_handle* h)
             if (!h->tune_note.empty()) return GKS_OK;
         }
     }
-    // save state (both buffers) and bookkeeping
-    const size_t nW = (size_t)2 * 3 * h->Ntot;
+    // save state (all three slots) and bookkeeping
+    const size_t nW = (size_t)3 * 3 * h->Ntot;
     double *sW = nullptr, *sX = nullptr;
     std::vector<ProbState> s0(h->nprob);
     HIP_TRY(h, dalloc(&sW, nW));
@@ -599,8 +599,10 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
         TRY(([&]() -> int {
             HIP_TRY(h, dalloc(&h->dTilesC, tc.size()));
             HIP_TRY(h, hipMemcpy(h->dTilesC, tc.data(), sizeof(Tile) * tc.size(), hipMemcpyHostToDevice));
-            HIP_TRY(h, dalloc(&h->W, 2 * 3 * N));
-            HIP_TRY(h, dalloc(&h->Wx, 2 * 3 * N));
+            // three state slots: W^n, W^{n+1/2}, W^{n+1} (the batched stage
+            // kernel never writes a slot that another item reads in the same launch)
+            HIP_TRY(h, dalloc(&h->W, 3 * 3 * N));
+            HIP_TRY(h, dalloc(&h->Wx, 3 * 3 * N));
             HIP_TRY(h, dalloc(&h->PW, 3 * N));
             HIP_TRY(h, dalloc(&h->Pf, 3 * h->F));
             return 0;
@@ -653,7 +655,7 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     else
         gks::signal2d_kernel<<<dim3((probs[0].nx + 63) / 64, (probs[0].ny + 3) / 4), dim3(64, 4), 0, h->stream>>>(
             h->dP, h->dS, h->W);
-    gks::finish_kernel<<<(nprob + 63) / 64, 64, 0, h->stream>>>(h->dP, h->dS, nprob, 0, h->ctr);
+    gks::finish_kernel<<<(nprob + 63) / 64, 64, 0, h->stream>>>(h->dP, h->dS, nprob, 0, h->ctr, dim == 1 ? 3 : 2);
     std::vector<ProbState> s(nprob);
     TRY(([&]() -> int {
         HIP_TRY(h, hipGetLastError());

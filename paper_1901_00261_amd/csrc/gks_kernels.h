@@ -34,7 +34,7 @@ struct ProbState {
     unsigned long long smax; // bits of a non-negative double (max signal speed / dx)
     int active;              // still short of t_end and no error
     int err;                 // a non-physical state was met in this step
-    int cur;                 // buffer holding W^n
+    int cur;                 // state slot holding W^n (2-D: slots 0, 1; 1-D: slots 0, 1, 2)
     int last;                // this step ends at t_end
 };
 
@@ -236,12 +236,14 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
 
 // ---------------------------------------------------------------------------
 // Per-problem step bookkeeping.
-//   commit = 1: the step just run is accepted (flip buffers, advance t) or,
-//               after an error, the problem stops with W^n kept.
+//   commit = 1: the step just run is accepted (W^{n+1} becomes the state:
+//               slot cur + nslot - 1 modulo nslot, so the next slot with two
+//               slots and the slot after the half-step state with three;
+//               advance t) or, after an error, the problem stops with W^n kept.
 //   Then the next dt follows from the maximum signal speed of the state.
 // ---------------------------------------------------------------------------
 // Returns true when the problem stops here (error or t_end reached).
-__device__ __forceinline__ bool finish_problem(const ProbParam& P, ProbState& S, int commit)
+__device__ __forceinline__ bool finish_problem(const ProbParam& P, ProbState& S, int commit, int nslot)
 {
     if (!S.active) return false;
     if (S.err) {
@@ -249,7 +251,7 @@ __device__ __forceinline__ bool finish_problem(const ProbParam& P, ProbState& S,
         return true;
     }
     if (commit) {
-        S.cur = 1 - S.cur;
+        S.cur = S.cur == 0 ? nslot - 1 : S.cur - 1;
         S.t = S.last ? P.t_end : S.t + S.dt;
         S.nsteps += 1;
     }
@@ -271,13 +273,13 @@ __device__ __forceinline__ bool finish_problem(const ProbParam& P, ProbState& S,
 }
 
 // one thread per problem (initial dt, and the 2-D step); ctr: work counters
-// of the batched 1-D kernels, reset here (null for 2-D)
+// of the batched 1-D kernels, reset here (null for 2-D); nslot: state slots
 __global__ void finish_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob, int commit,
-                              unsigned* __restrict__ ctr)
+                              unsigned* __restrict__ ctr, int nslot)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (ctr && p < 3) ctr[p] = 0u;
-    if (p < nprob) finish_problem(PP[p], PS[p], commit);
+    if (p < nprob) finish_problem(PP[p], PS[p], commit, nslot);
 }
 
 // Work list of the next step: the items of the problems still active, in
@@ -360,7 +362,12 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
         const ProbParam& P = PP[tl.p];
         ProbState& S = PS[tl.p];
         if (!S.active) continue; // uniform over the workgroup
-        const int cur = S.cur, nxt = 1 - cur;
+        // state slots: stage 1 reads W^n (slot cur) and writes W^{n+1/2} to
+        // the next slot; stage 2 reads W^{n+1/2} and writes W^{n+1} to the
+        // third, so no item overwrites values a neighbouring item's stencil
+        // still reads in the same launch, and W^n survives a failed step
+        const int cur = S.cur, half = cur == 2 ? 0 : cur + 1, next = cur == 0 ? 2 : cur - 1;
+        const int rd = STAGE == 1 ? cur : half, wr = STAGE == 1 ? half : next;
         const double dt = S.dt;
         // The item's values that the end of the stage needs (stage 1: W^n of
         // its cells; stage 2: the partials PW of its cells and Pf of its
@@ -393,9 +400,8 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
         // ---- faces c0 .. c0 + BLK - 1
         const int f = tl.start + t;
         if (f <= P.nx) {
-            const int buf = (STAGE == 1) ? cur : nxt;
-            const double* Wb = W + (size_t)buf * 3 * Ntot + P.coff;
-            const double* Xb = Wx + (size_t)buf * 3 * Ntot + P.coff;
+            const double* Wb = W + (size_t)rd * 3 * Ntot + P.coff;
+            const double* Xb = Wx + (size_t)rd * 3 * Ntot + P.coff;
             double Wk[4][4], Dk[4][4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -463,13 +469,13 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
                 if (STAGE == 1) {
                     const double L = -(sh_FL[k][t + 1] - sh_FL[k][t]) * idx;
                     const double w = sh_cell[k][t];
-                    W[((size_t)nxt * 3 + k) * Ntot + c] = msmd_half(w, L, dL, dt);
+                    W[((size_t)wr * 3 + k) * Ntot + c] = msmd_half(w, L, dL, dt);
                     PW[k * Ntot + c] = msmd_pred(w, L, dL, dt);
                 } else {
                     wn[k] = msmd_corr(sh_cell[k][t], dL, dt);
-                    W[((size_t)nxt * 3 + k) * Ntot + c] = wn[k];
+                    W[((size_t)wr * 3 + k) * Ntot + c] = wn[k];
                 }
-                Wx[((size_t)nxt * 3 + k) * Ntot + c] = slope;
+                Wx[((size_t)wr * 3 + k) * Ntot + c] = slope;
             }
         }
         if (STAGE == 2) {
@@ -501,7 +507,7 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
         if (sh_last) {
             __threadfence(); // acquire: no stale cached copies of the problem states
             bool stopped = false;
-            for (int p = t; p < nprob; p += BLK) stopped |= finish_problem(PP[p], PS[p], 1);
+            for (int p = t; p < nprob; p += BLK) stopped |= finish_problem(PP[p], PS[p], 1, 3);
             if (stopped) atomicOr(&sh_stopped, 1);
             if (t < 3) ctr[t] = 0u;
             __threadfence();

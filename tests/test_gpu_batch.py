@@ -92,6 +92,41 @@ def test_batch_matches_oracle(batch):
         assert g[4] == want[4] and err < 1e-10, (p.nx, err)
 
 
+@pytest.fixture(scope="module")
+def long_smooth():
+    """Two smooth problems large enough for many work items; the oracle after 6 steps."""
+    probs = [wl.sine_wave_1d(40000, order=8, recon=1), wl.sine_wave_1d(30000, order=6, recon=1)]
+    want = [oracle.run(1, p.W, p.Wx, **{**p.oracle_kwargs(), "max_steps": 6}) for p in probs]
+    return probs, want
+
+
+@pytest.mark.parametrize("tune", ["256:1", "64:1"])
+def test_items_over_several_rounds_match_oracle(long_smooth, tune):
+    """More work items than workgroups (one workgroup per CU: 275 items of 255
+    cells, or 1 112 items of 63 cells), so items start after neighbouring items
+    of the same problem have finished.  Such an item must still read its
+    neighbours' edge cells at the half step (reading them after the update
+    would shift W by about dt |W_t| ~ 1e-5): every cell of both problems
+    matches the oracle.  Values: relative L-inf <= 1e-11.  Gradients are
+    differences of neighbouring face values divided by dx, so rounding
+    differences of the face values (a few hundred eps |W| between the two
+    implementations) grow by 1/dx: the bar is 256 eps max|W| / dx on top of
+    1e-11 max|W_x| (4e-9 absolute at 40 000 cells)."""
+    probs, want = long_smooth
+    got, cfg = run(probs, steps=6, tune=tune)
+    assert cfg.startswith("forced")
+    eps = np.finfo(np.float64).eps
+    for p, g, w in zip(probs, got, want):
+        assert g[4] == w[4] == 6
+        err = np.abs(g[0] - w[0]).max() / np.abs(w[0]).max()
+        assert err <= 1e-11, (p.nx, err)
+        dx = (p.xhi - p.xlo) / p.nx
+        bar = 1e-11 * np.abs(w[1]).max() + 256 * eps * np.abs(w[0]).max() / dx
+        errx = np.abs(g[1] - w[1]).max()
+        print(f"N={p.nx} {tune}: W {err:.2e}, W_x {errx:.2e} (bar {bar:.2e})")
+        assert errx <= bar, (p.nx, errx, bar)
+
+
 def test_graph_replays_match_eager_with_host_reads(batch):
     g = gks()
     os.environ["GKS_TUNE"] = "128:2"
