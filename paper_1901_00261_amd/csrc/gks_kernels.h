@@ -75,6 +75,20 @@ __device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi, int
     return c;
 }
 
+// map_index with selects instead of branches (the boundary types are
+// uniform, the side of the stencil per lane): the same results, and no
+// divergent branch between a lane's stencil loads.
+__device__ __forceinline__ int map_index_sel(int c, int n, int bc_lo, int bc_hi, int& kind)
+{
+    const int lm = bc_lo == 0 ? c + n : (bc_lo == 2 ? -1 - c : 0);
+    const int lk = bc_lo == 0 ? kGhostNone : (bc_lo == 2 ? kGhostMirror : kGhostCopy);
+    const int hm = bc_hi == 0 ? c - n : (bc_hi == 2 ? 2 * n - 1 - c : n - 1);
+    const int hk = bc_hi == 0 ? kGhostNone : (bc_hi == 2 ? kGhostMirror : kGhostCopy);
+    const bool lo = c < 0, hi = c >= n;
+    kind = lo ? lk : (hi ? hk : kGhostNone);
+    return lo ? lm : (hi ? hm : c);
+}
+
 // Faces of a 2-D direction with n cells that the interface kernel
 // computes: with periodic ends the last face (index n) is the first one
 // (the same stencil after the wrap, so the same result), so it is computed
@@ -95,6 +109,16 @@ __device__ __forceinline__ void ghost_frame(int kn, int kt, double (&w)[4], doub
         w[2] = -w[2];
         d[2] = -d[2];
     }
+}
+
+// ghost_frame along the normal of a 1-D stencil (slot 2 unused), with selects
+__device__ __forceinline__ void ghost_frame_1d(int kn, double (&w)[4], double (&d)[4])
+{
+    const bool copy = kn == kGhostCopy, mir = kn == kGhostMirror;
+    w[1] = mir ? -w[1] : w[1];
+    d[0] = copy ? 0.0 : (mir ? -d[0] : d[0]);
+    d[1] = copy ? 0.0 : d[1];
+    d[3] = copy ? 0.0 : (mir ? -d[3] : d[3]);
 }
 
 // Two-stage MSMD combinations (Sec. 2.2) with the fused multiply-adds
@@ -402,16 +426,22 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
         if (f <= P.nx) {
             const double* Wb = W + (size_t)rd * 3 * Ntot + P.coff;
             const double* Xb = Wx + (size_t)rd * 3 * Ntot + P.coff;
+            // the four stencil cells through the boundary condition, all 24
+            // loads issued together
             double Wk[4][4], Dk[4][4];
+            int kind[4], c[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = map_index_sel(f - 2 + q, P.nx, P.bc[0], P.bc[1], kind[q]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                int kind;
-                const int c = map_index(f - 2 + q, P.nx, P.bc[0], P.bc[1], kind);
-                double w[4] = {Wb[c], Wb[Ntot + c], 0.0, Wb[2 * Ntot + c]};
-                double d[4] = {P.dx * Xb[c], P.dx * Xb[Ntot + c], 0.0, P.dx * Xb[2 * Ntot + c]};
-                ghost_frame(kind, kGhostNone, w, d);
+                Wk[q][0] = Wb[c[q]]; Wk[q][1] = Wb[Ntot + c[q]]; Wk[q][2] = 0.0; Wk[q][3] = Wb[2 * Ntot + c[q]];
+                Dk[q][0] = Xb[c[q]]; Dk[q][1] = Xb[Ntot + c[q]]; Dk[q][2] = 0.0; Dk[q][3] = Xb[2 * Ntot + c[q]];
+            }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) { Wk[q][k] = w[k]; Dk[q][k] = d[k]; }
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) Dk[q][k] *= P.dx;
+                ghost_frame_1d(kind[q], Wk[q], Dk[q]);
             }
             double o[7][4];
             auto put = [&](int q, int k, double v) { o[q][k] = v; };
