@@ -134,7 +134,9 @@ int gks_cell_updates(const gks_handle* h, int64_t* count);
    of BLK-1 cells (BLK = 64, 128 or 256 threads), with GMUL persistent
    workgroups per compute unit or, for GMUL = 0, one workgroup per item.
    The first gks_step of a 1-D handle autotunes (BLK, GMUL) by timing a few
-   steps from the initial state, which is restored afterwards; every
+   steps from the initial state, which is restored afterwards (larger tiles
+   and fewer workgroups are tried first and kept unless another candidate
+   is more than 3 % faster); every
    configuration performs the same arithmetic, so results do not depend on
    the choice.  Environment: GKS_TUNE="BLK:GMUL" forces a configuration,
    GKS_TUNE_CACHE=<file> caches tuning results by problem-set signature,
