@@ -784,8 +784,11 @@ constexpr int kGpX = 64, kGpY = 4;
 //   x faces: 8 transverse rows (4 waves + 4 stencil rows) x 64 faces, one
 //            1 KB copy per row pair (lanes 0-31 the first row, 32-63 the
 //            second);
-//   y faces: 4 face rows x 128 transverse entries (64 lanes + 4 stencil
-//            entries, rounded up to one 1 KB copy per row).
+//   y faces: 4 face rows x 128 transverse entries, of which the 68 read (64
+//            lanes + 4 stencil entries) are copied: one copy per row with
+//            lanes 0-33 active (544 bytes; the copies are bound by the
+//            memory system's throughput, so the unread 60 entries are not
+//            fetched).
 template <int DIR>
 struct GpStage {
     static constexpr int rows = DIR == 0 ? kGpY + 4 : kGpY; // rows per quantity
@@ -816,11 +819,14 @@ __device__ __forceinline__ void stage_component(__amdgpu_buffer_rsrc_t rs, doubl
 {
     using G = GpStage<DIR>;
     const int row = DIR == 0 ? 2 * w : w;
+    // y faces: lanes 34-63 would copy entries 68-127, which no lane reads
+    if (DIR == 0 || (threadIdx.x & 63) < 34) {
 #pragma unroll
-    for (int q = 0; q < 7; ++q)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            rs, (__attribute__((address_space(3))) void*)(dst + (q * G::rows + row) * G::len), 16, voff,
-            sofs + (unsigned)(q * 4) * plane + (unsigned)row * rstride, 0, 0);
+        for (int q = 0; q < 7; ++q)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rs, (__attribute__((address_space(3))) void*)(dst + (q * G::rows + row) * G::len), 16, voff,
+                sofs + (unsigned)(q * 4) * plane + (unsigned)row * rstride, 0, 0);
+    }
 }
 
 // Wait until this wave's copies of components 0..K have landed (the 7 copies
