@@ -352,6 +352,31 @@ def mirror_pair_1d(n, *, gamma=1.4, order=8, recon=1, cfl=0.3, t_end=0.5):
     return full, half
 
 
+def axis_wave_2d(n, axis, *, order=8, recon=0, gamma=1.4, amp=0.1, k=math.pi, dt_fixed=1e-7, t_end=None):
+    """Entropy wave along one axis of [0, 2]^2 (periodic): rho = 1 + amp sin(k s)
+    with s = x and (U, V) = (1, 0) for axis 0, s = y and (0, 1) for axis 1;
+    p = 1.  Uniform across the other axis; exact cell averages and gradients
+    (the conservative variables are affine in rho)."""
+    d = 2.0 / n
+    sf = d * np.arange(n + 1)
+    rho_f = 1.0 + amp * np.sin(k * sf)
+    rho_avg = 1.0 + amp * (np.cos(k * sf[:-1]) - np.cos(k * sf[1:])) / (k * d)
+    U, V = (1.0, 0.0) if axis == 0 else (0.0, 1.0)
+    wa = prim_to_cons(rho_avg, U, 1.0, gamma, V=V)
+    wf = prim_to_cons(rho_f, U, 1.0, gamma, V=V)
+    ws = (wf[1:] - wf[:-1]) / d
+    if axis == 0:
+        W = np.ascontiguousarray(np.broadcast_to(wa[None, :, :], (n, n, 4)))
+        Wx = np.ascontiguousarray(np.broadcast_to(ws[None, :, :], (n, n, 4)))
+        Wy = np.zeros_like(W)
+    else:
+        W = np.ascontiguousarray(np.broadcast_to(wa[:, None, :], (n, n, 4)))
+        Wy = np.ascontiguousarray(np.broadcast_to(ws[:, None, :], (n, n, 4)))
+        Wx = np.zeros_like(W)
+    return Problem(2, n, n, 0.0, 2.0, 0.0, 2.0, gamma, 0.0, 0.3, dt_fixed, dt_fixed if t_end is None else t_end,
+                   order, recon, (0, 0, 0, 0), W, Wx, Wy, name=f"axis_wave_{axis}_n{n}")
+
+
 def sine_wave_2d(n, *, order=6, recon=0, gamma=1.4, cfl=0.3, dt_fixed=0.0, t_end=2.0, amp=0.2):
     """2-D analogue of the accuracy test of Sec. 4.1: rho = 1 + amp sin(pi (x + y)),
     U = V = 1, p = 1 on the periodic [0, 2]^2; the exact solution translates

@@ -1,5 +1,6 @@
 """The GPU path's semi-discrete symbol against the printed modified
-wavenumbers (Sec. 3.2, eqs. wavenumber-6th and wavenumber-8th).
+wavenumbers (Sec. 3.2, eqs. wavenumber-6th and wavenumber-8th), in 1-D and
+along either axis of the 2-D path (x faces and y faces).
 
 For an entropy wave (density varies, U = 1 and p uniform) with the linear
 reconstruction, the left and right states equal the equilibrium state, the
@@ -47,5 +48,35 @@ def test_symbol_matches_printed_modified_wavenumber(order):
         ratio = np.fft.fft((rho1 - rho0) / dt)[m] / np.fft.fft(rho0 - rho0.mean())[m]
         lam = modified_wavenumber(order, k * dx) / dx
         print(f"order {order} w={k * dx:.3f}: symbol {ratio:.10g}, -i w'/dx = {-lam:.10g}i")
+        assert abs(ratio.imag + lam) <= 1e-7 * lam, (m, ratio, lam)
+        assert abs(ratio.real) <= lam * lam * dt, (m, ratio, lam)
+
+
+@pytest.mark.parametrize("order", [6, 8])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_symbol_2d_axis_waves(order, axis):
+    """A wave along x (U = 1) runs through the x-face kernels only, one along
+    y (V = 1) through the y-face kernels; uniform across the other axis, so
+    the tangential reconstruction returns the row values and the symbol is
+    the 1-D one."""
+    from paper_1901_00261_amd import gks as g
+    n, dt = 32, 1e-7
+    d = 2.0 / n
+    for m in (2, 8, 15):
+        k = math.pi * m
+        p = wl.axis_wave_2d(n, axis, order=order, k=k, dt_fixed=dt)
+        S = g.Solver(p, 0)
+        S.step(1)
+        W1, _, _, t, nsteps = S.state(0)
+        S.close()
+        assert nsteps == 1 and t == dt
+        D = (W1[..., 0] - p.W[..., 0]) / dt
+        ref = D[0:1, :] if axis == 0 else D[:, 0:1]
+        assert np.abs(D - ref).max() <= 1e-9 * np.abs(D).max()  # uniform across the wave
+        line0 = p.W[0, :, 0] if axis == 0 else p.W[:, 0, 0]
+        line = D[0, :] if axis == 0 else D[:, 0]
+        ratio = np.fft.fft(line)[m] / np.fft.fft(line0 - line0.mean())[m]
+        lam = modified_wavenumber(order, k * d) / d
+        print(f"2-D axis {axis} order {order} w={k * d:.3f}: symbol {ratio:.10g}, -i w'/dx = {-lam:.10g}i")
         assert abs(ratio.imag + lam) <= 1e-7 * lam, (m, ratio, lam)
         assert abs(ratio.real) <= lam * lam * dt, (m, ratio, lam)
