@@ -43,8 +43,8 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1901_00261_amd", "csrc", f)
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=0, help="cells per direction (2-D workloads)")
     ap.add_argument("--workload", choices=["vortex2d", "batch1d", "riemann2d"], default="vortex2d")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
