@@ -95,7 +95,10 @@ int gks_init_device(const gks_problem* probs, int32_t nprob, int32_t precision, 
    its own dt (Sec. 2.2).  *n_active (may be NULL) receives the number of
    problems still short of t_end.  Returns GKS_ENONPHYS if any problem met a
    non-physical state; that problem stops and keeps the state it had at the
-   start of the failing step. */
+   start of the failing step.  All max_steps steps are launched (finished
+   problems skip their work but the launches still cost time), so a caller
+   running to t_end steps in chunks; multiples of 8 keep the eight-step graph
+   replays. */
 int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active);
 
 /* Copy problem p to host buffers (layout as in gks_init; Wy ignored when

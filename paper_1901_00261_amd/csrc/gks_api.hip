@@ -69,6 +69,10 @@ struct gks_handle {
     // step graph
     bool use_graph = true;
     hipStream_t cap = nullptr;
+    // 2-D: the y-face kernels run on a second stream, forked from and joined
+    // to the step's stream around them (not while kernels are being timed)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr, graphK = nullptr;
     hipGraphExec_t gexec = nullptr, gexecK = nullptr; // one step, kGraphSteps steps
 };
@@ -244,7 +248,17 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
     const int grx = tiles(gks::faces_computed(nx, P.bc[0]), ny + 4, br), gry = tiles(nx + 4, gks::faces_computed(ny, P.bc[2]), br);
     const int ggx = tiles(gks::faces_computed(nx, P.bc[0]), ny, bg), ggy = tiles(nx, gks::faces_computed(ny, P.bc[2]), bg);
     const int gc = tiles(nx, ny, bc);
+    // The x-face and y-face kernels of a stage are independent until the cell
+    // update: the y-face pair runs on the side stream, so that the two chains
+    // overlap (each fills the other's partly idle last wave of workgroups).
+    // Kernel timing keeps every launch on the handle's stream.
+    const bool fork = h->side && !h->timing;
+    hipStream_t sy = fork ? h->side : st;
     for (int stage = 1; stage <= 2; ++stage) {
+        if (fork) {
+            (void)hipEventRecord(h->ev_fork, st);
+            (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+        }
         record(h, st, 1, true);
         if (P.order == 8)
             gks::row2d_kernel<T, 0, 8><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
@@ -257,18 +271,22 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
         else
             gks::gp2d_kernel<T, 0, 2><<<ggx, bg, 0, st>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
         record(h, st, 0, false);
-        record(h, st, 1, true);
+        record(h, sy, 1, true);
         if (P.order == 8)
-            gks::row2d_kernel<T, 1, 8><<<gry, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
+            gks::row2d_kernel<T, 1, 8><<<gry, br, 0, sy>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
         else
-            gks::row2d_kernel<T, 1, 6><<<gry, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
-        record(h, st, 1, false);
-        record(h, st, 0, true);
+            gks::row2d_kernel<T, 1, 6><<<gry, br, 0, sy>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
+        record(h, sy, 1, false);
+        record(h, sy, 0, true);
         if (stage == 1)
-            gks::gp2d_kernel<T, 1, 1><<<ggy, bg, 0, st>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
+            gks::gp2d_kernel<T, 1, 1><<<ggy, bg, 0, sy>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
         else
-            gks::gp2d_kernel<T, 1, 2><<<ggy, bg, 0, st>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
-        record(h, st, 0, false);
+            gks::gp2d_kernel<T, 1, 2><<<ggy, bg, 0, sy>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
+        record(h, sy, 0, false);
+        if (fork) {
+            (void)hipEventRecord(h->ev_join, h->side);
+            (void)hipStreamWaitEvent(st, h->ev_join, 0);
+        }
         record(h, st, 2, true);
         if (stage == 1)
             gks::cell2d_kernel<1><<<gc, bc, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL, h->Wfs,
@@ -468,6 +486,9 @@ void release(gks_handle* h)
         dfree(p);
     drop_graph(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->side) (void)hipStreamDestroy(h->side);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     dfree(h->ctr);
     for (int b = 0; b < 3; ++b) {
         dfree(h->dItems[b]);
@@ -571,6 +592,11 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     if (const char* g = getenv("GKS_GRAPH")) h->use_graph = atoi(g) != 0;
     TRY(([&]() -> int {
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        if (dim == 2) {
+            HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+            HIP_TRY(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+            HIP_TRY(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        }
         HIP_TRY(h, dalloc(&h->ctr, 3));
         HIP_TRY(h, dalloc(&h->dNact, 1));
         HIP_TRY(h, hipMemset(h->ctr, 0, 3 * sizeof(unsigned)));
