@@ -37,8 +37,16 @@
  *   A1  time coefficients: polynomial part of f(t) by its exact Taylor
  *       coefficients at t = 0; the exp(-t/tau_n) part by the two-point fit of
  *       its time integrals over [0, dt/2] and [0, dt].
- *   A2  physical tau (mu/p, 0 for Euler) multiplies the Navier-Stokes terms;
- *       the numerical tau_n of Sec. 4 sits in the exponentials.
+ *   A2  two collision times.  The -tau[...] (Navier-Stokes) terms use the
+ *       physical mu/p (0 for Euler) plus the pressure-jump term
+ *       C |p_l - p_r| / (p_l + p_r) dt of Sec. 4, which is the artificial
+ *       dissipation that Sec. 4 puts into the collision time for
+ *       discontinuities; the exponentials use tau_n, the full collision time
+ *       of Sec. 4 (epsilon dt + jump term for Euler, mu/p + jump term for
+ *       Navier-Stokes).  The epsilon dt part stays out of the -tau[...]
+ *       terms: there it would act as a viscosity 0.01 dt p and limit
+ *       Tables 1-2 (smooth data have no pressure jump, so the jump term
+ *       leaves them unchanged).
  *   A3  abar_xx, abar_xt, abar_tt are exact second Taylor coefficients of
  *       the Maxwellian divided by g0 (they include the products abar^2,
  *       abar*Abar, Abar^2).
@@ -248,6 +256,13 @@ static int build_candidates(void)
 static const double D6[7] = {33.0 / 700, 11.0 / 140, 22.0 / 175, 11.0 / 100, 11.0 / 100, 37.0 / 140, 37.0 / 140};
 static const double D8[7] = {3.0 / 98, 5.0 / 98, 4.0 / 49, 7.0 / 98, 7.0 / 98, 17.0 / 49, 17.0 / 49};
 static double weno_eps = 1e-6;
+
+/* Number of positivity fallbacks (reading A21) taken since the last orc_run
+   started: face-row states counted once per stage and face row (the 2-D
+   sweeps rebuild each face row for five neighbouring Gauss-point stencils;
+   only its own stencil, the centre row, counts), Gauss-point states once per
+   stage and Gauss point. */
+static long a21_count = 0;
 
 /* Smoothness indicator, eq. (smooth-indicator): sum over q = 1..deg of
    dx^(2q-1) * integral over I_i of (d^q w / dx^q)^2, which in the unit
@@ -606,7 +621,7 @@ static int gks_point(const kin_par_t *kp, const gp_in_t *in, gp_out_t *out)
     /* collision times (Sec. 4, readings A2, A10) */
     double p0 = g0.rho / (2.0 * g0.lam), pl = gl.rho / (2.0 * gl.lam), pr = gr.rho / (2.0 * gr.lam);
     double jump = fabs((pl - pr) / (pl + pr)) * kp->dt;
-    double tau = (kp->mu > 0.0) ? kp->mu / p0 : 0.0;
+    double tau = ((kp->mu > 0.0) ? kp->mu / p0 : 0.0) + jump;
     double tau_n = (kp->mu > 0.0) ? kp->mu / p0 + jump : 0.01 * kp->dt + jump;
 
     /* spatial micro-slopes of g0: <abar_1 psi> = W_x, <abar_2 psi> = W_y */
@@ -821,7 +836,7 @@ static void to_local(int dim, int dir, const double *a, double *b)
    index t.  Output, in the local frame: [0] W0, [1] dn W0, [2] dnn W0,
    [3] Wl, [4] Wr, [5] dn Wl, [6] dn Wr. */
 static int face_row(const prob_t *P, const double *W, const double *Wx, const double *Wy,
-                    int dir, int c, int t, double out[7][4])
+                    int dir, int c, int t, double out[7][4], int count_fb)
 {
     int nv = P->nv;
     double h = dir == 0 ? P->dx : P->dy;
@@ -886,8 +901,13 @@ static int face_row(const prob_t *P, const double *W, const double *Wx, const do
         out[6][k] = srx / h;
     }
     /* positivity fallback (reading A21) */
-    if (!physical(P->dim, P->gamma, out[3])) for (int k = 0; k < nv; ++k) out[3][k] = Wk[1][k];
-    if (!physical(P->dim, P->gamma, out[4])) for (int k = 0; k < nv; ++k) out[4][k] = Wk[2][k];
+    int nfb = 0;
+    if (!physical(P->dim, P->gamma, out[3])) { for (int k = 0; k < nv; ++k) out[3][k] = Wk[1][k]; ++nfb; }
+    if (!physical(P->dim, P->gamma, out[4])) { for (int k = 0; k < nv; ++k) out[4][k] = Wk[2][k]; ++nfb; }
+    if (nfb && count_fb) {
+#pragma omp atomic
+        a21_count += nfb;
+    }
     return ORC_OK;
 }
 
@@ -1032,7 +1052,7 @@ static int sweep(const prob_t *P, const double *W, const double *Wx, const doubl
             int st = ORC_OK;
             if (dim == 1) {
                 double row[7][4];
-                st = face_row(P, W, Wx, Wy, dir, c, t, row);
+                st = face_row(P, W, Wx, Wy, dir, c, t, row, 1);
                 if (!st) {
                     gp_in_t in;
                     memset(&in, 0, sizeof in);
@@ -1052,7 +1072,7 @@ static int sweep(const prob_t *P, const double *W, const double *Wx, const doubl
                 }
             } else {
                 double rows[5][7][4];
-                for (int r = 0; r < 5 && !st; ++r) st = face_row(P, W, Wx, Wy, dir, c, t - 2 + r, rows[r]);
+                for (int r = 0; r < 5 && !st; ++r) st = face_row(P, W, Wx, Wy, dir, c, t - 2 + r, rows[r], r == 2);
                 for (int g = 0; g < 3 && !st; ++g) {
                     gp_in_t in;
                     memset(&in, 0, sizeof in);
@@ -1078,8 +1098,11 @@ static int sweep(const prob_t *P, const double *W, const double *Wx, const doubl
                                 for (int r = 0; r < 5; ++r) q[r] = rows[r][3 + side][k];
                                 dst[k] = tan_weno_value(g, q);
                             }
-                            if (!physical(dim, P->gamma, dst))
+                            if (!physical(dim, P->gamma, dst)) {
                                 for (int k = 0; k < nv; ++k) dst[k] = rows[2][3 + side][k];
+#pragma omp atomic
+                                a21_count += 1;
+                            }
                         }
                     }
                     if (P->recon) st = kinetic_average(dim, P->gamma, P->K, in.Wl, in.Wr, in.W0);
@@ -1191,6 +1214,7 @@ int orc_run(int dim, int nx, int ny, double xlo, double xhi, double ylo, double 
             double *W, double *Wx, double *Wy, double *t_io, long *nsteps_out)
 {
     if (init_tables()) return ORC_EINVAL;
+    a21_count = 0;
     if ((dim != 1 && dim != 2) || nx < 4 || (dim == 2 && ny < 4) || !(gamma > 1.0) || (order != 6 && order != 8))
         return ORC_EINVAL;
     prob_t P;
@@ -1426,6 +1450,29 @@ int orc_tangential_weno(int g, const double *q, double *out)
 {
     if (init_tables() || g < 0 || g > 2) return ORC_EINVAL;
     *out = tan_weno_value(g, q);
+    return 0;
+}
+
+/* Positivity fallbacks (reading A21) taken by the last orc_run. */
+long orc_fallbacks(void) { return a21_count; }
+
+/* Tangential WENO-Z details at Gauss point g: out[0] value, out[1..3] the
+   smoothness indicators of the three quadratic candidates, out[4..6] the
+   candidates' values at the point. */
+int orc_tangential_weno_detail(int g, const double *q, double *out)
+{
+    if (init_tables() || g < 0 || g > 2) return ORC_EINVAL;
+    out[0] = tan_weno_value(g, q);
+    for (int k = 0; k < 3; ++k) {
+        double c[3] = {0, 0, 0};
+        double v = 0.0;
+        for (int r = 0; r < 5; ++r) {
+            v += tw_cand[g][k][r] * q[r];
+            for (int m = 0; m < 3; ++m) c[m] += tw_coef[k][m][r] * q[r];
+        }
+        out[1 + k] = beta_of(c, 2);
+        out[4 + k] = v;
+    }
     return 0;
 }
 

@@ -17,9 +17,11 @@ LINEAR, WENOZ = 0, 1
 
 
 class OracleError(RuntimeError):
-    def __init__(self, code, msg):
+    def __init__(self, code, msg, t=None, nsteps=None):
         super().__init__(msg)
         self.code = code
+        self.t = t            # time reached (run() failures)
+        self.nsteps = nsteps  # steps completed before the failure
 
 
 def lib():
@@ -48,6 +50,9 @@ def lib():
         _lib.orc_kinetic_average.argtypes = [C.c_int, C.c_double, d, d, d]
         _lib.orc_tangential_weno.argtypes = [C.c_int, d, d]
         _lib.orc_tangential_weno_weights.argtypes = [d]
+        _lib.orc_tangential_weno_detail.argtypes = [C.c_int, d, d]
+        _lib.orc_fallbacks.argtypes = []
+        _lib.orc_fallbacks.restype = C.c_long
     return _lib
 
 
@@ -81,7 +86,8 @@ def run(dim, W, Wx, Wy=None, *, xlo, xhi, ylo=0.0, yhi=1.0, gamma=1.4, mu=0.0, c
     st = lib().orc_run(dim, nx, ny, xlo, xhi, ylo, yhi, gamma, mu, cfl, dt_fixed, t_end, max_steps,
                        order, recon, bca, _p(W), _p(Wx), _p(Wy), C.byref(t), C.byref(n))
     if st != 0:
-        raise OracleError(st, f"oracle run failed with status {st} at t={t.value} after {n.value} steps")
+        raise OracleError(st, f"oracle run failed with status {st} at t={t.value} after {n.value} steps",
+                          t=t.value, nsteps=n.value)
     return W, Wx, (Wy if dim == 2 else None), t.value, n.value
 
 
@@ -214,3 +220,18 @@ def tangential_weno_weights():
     out = np.zeros((3, 3))
     lib().orc_tangential_weno_weights(_p(out))
     return out
+
+
+def tangential_weno_detail(g, q):
+    """Tangential WENO-Z at Gauss point g: (value, beta[3], candidate values[3])."""
+    q = _f64(q, 5)
+    out = np.zeros(7)
+    lib().orc_tangential_weno_detail(g, _p(q), _p(out))
+    return out[0], out[1:4].copy(), out[4:7].copy()
+
+
+def fallbacks():
+    """Positivity fallbacks (reading A21) taken by the last run(): face-row
+    WENO-Z states replaced by the adjacent cell average plus Gauss-point
+    states replaced by their face-row line value."""
+    return int(lib().orc_fallbacks())

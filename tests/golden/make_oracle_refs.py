@@ -1,0 +1,117 @@
+"""Write the oracle reference results that the GPU parity tests compare with.
+
+Calls only the CPU oracle (oracle/) on the seeded inputs of
+paper_1901_00261_amd.workloads; nothing here touches the HIP library.  Run
+from the repository root after any change to the oracle's arithmetic:
+
+    python tests/golden/make_oracle_refs.py [name ...]
+
+Outputs (numpy .npz, float64, no pickled objects) next to this script:
+
+  riemann_set_n400.npz   the 32 seeded 1-D Riemann problems (N = 400, 8th-order
+                         WENO-Z, t = 0.14, seeds 20190101 + k) and Sod: full
+                         end states W, Wx, the time and step count reached,
+                         and whether the oracle stopped on a non-physical
+                         state (then the state is the one at the start of the
+                         failing step, as the library keeps it).
+  riemann2d_256_s500.npz four-quadrant Riemann problem (seed 5), 256 x 256,
+                         8th-order WENO-Z, 500 CFL-0.3 steps: sampled cells
+                         (every 8th row and column, plus the 24 x 24 block
+                         around the quadrant corner) of W, Wx, Wy, the
+                         per-component sums of W, time and step count.
+  vortex128_t02.npz      Navier-Stokes vortex + acoustic perturbation (the
+                         1024^2 benchmark's workload on 128 x 128 cells),
+                         8th-order WENO-Z, mu = 1e-4, CFL 0.3, to t = 0.2:
+                         every 4th row and column of W, Wx, Wy, the sums,
+                         time and step count.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1901_00261_amd import workloads as wl  # noqa: E402
+
+
+def _run(p, **over):
+    kw = {**p.oracle_kwargs(), **over}
+    return oracle.run(p.dim, p.W, p.Wx, p.Wy, **kw)
+
+
+def _nonphysical(W, gamma):
+    rho = W[..., 0]
+    mom2 = (W[..., 1:-1] ** 2).sum(axis=-1)
+    p = (gamma - 1.0) * (W[..., -1] - 0.5 * mom2 / np.where(rho > 0, rho, 1.0))
+    return bool((~(rho > 0)).any() or (~(p > 0)).any())
+
+
+def riemann_set():
+    probs = wl.riemann_set_1d(32, n=400) + [wl.riemann_1d(400, *wl.SOD)]
+    W, Wx, t, n, failed, fb = [], [], [], [], [], []
+    for k, p in enumerate(probs):
+        try:
+            r = _run(p)
+            bad = False
+        except oracle.OracleError as e:
+            # The oracle stops after e.nsteps good steps, either inside the
+            # next step or, when the last state is itself non-physical, when
+            # it sizes the next step.  The library stops on the step that
+            # produces a non-physical state and keeps the state at its start.
+            m = e.nsteps
+            if m > 0 and _nonphysical(_run(p, max_steps=m)[0], p.gamma):
+                m -= 1
+            r = _run(p, max_steps=m) if m > 0 else (p.W.copy(), p.Wx.copy(), None, 0.0, 0)
+            bad = True
+        W.append(r[0]); Wx.append(r[1]); t.append(r[3]); n.append(r[4]); failed.append(bad)
+        fb.append(oracle.fallbacks())
+        print(f"riemann {k}: t={r[3]:.6f} steps={r[4]} failed={bad} fallbacks={fb[-1]}", flush=True)
+    return dict(W=np.array(W), Wx=np.array(Wx), t=np.array(t), nsteps=np.array(n),
+                failed=np.array(failed), fallbacks=np.array(fb))
+
+
+def _sample_2d(W, Wx, Wy, stride, block):
+    ny, nx = W.shape[:2]
+    rows = np.unique(np.concatenate([np.arange(0, ny, stride), np.arange(*block[0])]))
+    cols = np.unique(np.concatenate([np.arange(0, nx, stride), np.arange(*block[1])]))
+    sl = np.ix_(rows, cols)
+    return dict(rows=rows, cols=cols, W=W[sl], Wx=Wx[sl], Wy=Wy[sl], sums=W.sum(axis=(0, 1)))
+
+
+def riemann2d():
+    p = wl.riemann_2d(256, seed=5, order=8, recon=1, cfl=0.3)
+    W, Wx, Wy, t, n = _run(p, max_steps=500)
+    print(f"riemann2d 256: t={t:.6f} steps={n} fallbacks={oracle.fallbacks()}", flush=True)
+    out = _sample_2d(W, Wx, Wy, 8, ((116, 140), (116, 140)))
+    out.update(t=t, nsteps=n, fallbacks=oracle.fallbacks())
+    return out
+
+
+def vortex():
+    p = wl.isentropic_vortex_2d(128, mu=1e-4, eps=5.0, acoustic_amp=1e-3, nmodes=32, seed=3, order=8, recon=1,
+                                cfl=0.3, t_end=0.2)
+    W, Wx, Wy, t, n = _run(p)
+    print(f"vortex 128: t={t:.6f} steps={n}", flush=True)
+    out = _sample_2d(W, Wx, Wy, 4, ((60, 68), (60, 68)))
+    out.update(t=t, nsteps=n)
+    return out
+
+
+JOBS = {"riemann_set_n400": riemann_set, "riemann2d_256_s500": riemann2d, "vortex128_t02": vortex}
+
+
+def main(names):
+    for name in names or JOBS:
+        t0 = time.time()
+        res = JOBS[name]()
+        np.savez_compressed(os.path.join(HERE, name + ".npz"), **res)
+        print(f"{name}: written in {time.time() - t0:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

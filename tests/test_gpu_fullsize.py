@@ -195,8 +195,13 @@ def check_failure_matches_oracle(S, k, tol=1e-11):
     the oracle on the same step, from the same state."""
     p = S.problems[k]
     W, Wx, _, t, n = S.state(k)
-    want = oracle.run(1, p.W, p.Wx, **{**p.oracle_kwargs(), "max_steps": n})
-    assert want[4] == n and rel(W, want[0]) <= tol and rel(Wx, want[1]) <= max(tol, 1e-11)
+    if n == 0:
+        # stopped on its first step: the initial data are kept unchanged
+        # (max_steps = 0 would mean "no limit" to the oracle)
+        assert np.array_equal(W, p.W) and np.array_equal(Wx, p.Wx) and t == 0.0
+    else:
+        want = oracle.run(1, p.W, p.Wx, **{**p.oracle_kwargs(), "max_steps": n})
+        assert want[4] == n and rel(W, want[0]) <= tol and rel(Wx, want[1]) <= max(tol, 1e-11)
     assert oracle_fails_on_step(p, n + 1)
     print(f"problem {k} (N={p.nx}, order {p.order}) stops after {n} steps in both")
 
