@@ -39,7 +39,7 @@ struct gks_handle {
     double *W = nullptr, *Wx = nullptr, *Wy = nullptr, *PW = nullptr;
     double *FL = nullptr, *FdL = nullptr, *Wfs = nullptr, *Pf = nullptr;
     double *FLy = nullptr, *FdLy = nullptr, *Wfsy = nullptr, *Pfy = nullptr;
-    double *Rx = nullptr, *Ry = nullptr;
+    void *Rx = nullptr, *Ry = nullptr; // face-row buffers: double (FP64) or float (FP32-mixed)
     double* stage = nullptr; // transpose staging
     size_t stage_len = 0;
     std::string err;
@@ -148,7 +148,7 @@ int validate(const gks_problem* pr, int32_t nprob, int32_t precision)
         if (q.nx < 4 || (dim == 2 && q.ny < 4) || (dim == 1 && q.ny != 1 && q.ny != 0)) return bad("bad nx/ny");
         if ((long long)q.nx * (dim == 2 ? q.ny : 1) > (1ll << 31) - 1) return bad("too many cells");
         // 2-D face-row buffers are read through 32-bit byte offsets
-        if (dim == 2 && std::max(gks::row_buffer_doubles(q.nx, q.ny, 0), gks::row_buffer_doubles(q.nx, q.ny, 1)) * 8 >
+        if (dim == 2 && std::max(gks::row_buffer_elems(q.nx, q.ny, 0), gks::row_buffer_elems(q.nx, q.ny, 1)) * 8 >
                             0xffffffffll)
             return bad("2-D grid too large for one handle (at most about 4370 x 4370 cells)");
         if (!(q.xhi > q.xlo) || (dim == 2 && !(q.yhi > q.ylo))) return bad("empty domain");
@@ -261,27 +261,27 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
         }
         record(h, st, 1, true);
         if (P.order == 8)
-            gks::row2d_kernel<T, 0, 8><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
+            gks::row2d_kernel<T, 0, 8><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, (T*)h->Rx);
         else
-            gks::row2d_kernel<T, 0, 6><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Rx);
+            gks::row2d_kernel<T, 0, 6><<<grx, br, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, (T*)h->Rx);
         record(h, st, 1, false);
         record(h, st, 0, true);
         if (stage == 1)
-            gks::gp2d_kernel<T, 0, 1><<<ggx, bg, 0, st>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
+            gks::gp2d_kernel<T, 0, 1><<<ggx, bg, 0, st>>>(h->dP, h->dS, (const T*)h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
         else
-            gks::gp2d_kernel<T, 0, 2><<<ggx, bg, 0, st>>>(h->dP, h->dS, h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
+            gks::gp2d_kernel<T, 0, 2><<<ggx, bg, 0, st>>>(h->dP, h->dS, (const T*)h->Rx, h->FL, h->FdL, h->Wfs, h->Pf);
         record(h, st, 0, false);
         record(h, sy, 1, true);
         if (P.order == 8)
-            gks::row2d_kernel<T, 1, 8><<<gry, br, 0, sy>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
+            gks::row2d_kernel<T, 1, 8><<<gry, br, 0, sy>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, (T*)h->Ry);
         else
-            gks::row2d_kernel<T, 1, 6><<<gry, br, 0, sy>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, h->Ry);
+            gks::row2d_kernel<T, 1, 6><<<gry, br, 0, sy>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, stage, (T*)h->Ry);
         record(h, sy, 1, false);
         record(h, sy, 0, true);
         if (stage == 1)
-            gks::gp2d_kernel<T, 1, 1><<<ggy, bg, 0, sy>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
+            gks::gp2d_kernel<T, 1, 1><<<ggy, bg, 0, sy>>>(h->dP, h->dS, (const T*)h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
         else
-            gks::gp2d_kernel<T, 1, 2><<<ggy, bg, 0, sy>>>(h->dP, h->dS, h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
+            gks::gp2d_kernel<T, 1, 2><<<ggy, bg, 0, sy>>>(h->dP, h->dS, (const T*)h->Ry, h->FLy, h->FdLy, h->Wfsy, h->Pfy);
         record(h, sy, 0, false);
         if (fork) {
             (void)hipEventRecord(h->ev_join, h->side);
@@ -656,8 +656,9 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
             HIP_TRY(h, dalloc(&h->FdLy, 4 * nfy));
             HIP_TRY(h, dalloc(&h->Wfsy, 4 * nfy));
             HIP_TRY(h, dalloc(&h->Pfy, 4 * nfy));
-            HIP_TRY(h, dalloc(&h->Rx, gks::row_buffer_doubles((int)nx, (int)ny, 0)));
-            HIP_TRY(h, dalloc(&h->Ry, gks::row_buffer_doubles((int)nx, (int)ny, 1)));
+            const int es = precision == GKS_PREC_FP64 ? 8 : 4;
+            HIP_TRY(h, hipMalloc(&h->Rx, (size_t)gks::row_buffer_elems((int)nx, (int)ny, 0, es) * es));
+            HIP_TRY(h, hipMalloc(&h->Ry, (size_t)gks::row_buffer_elems((int)nx, (int)ny, 1, es) * es));
             return 0;
         })());
     }
@@ -856,7 +857,7 @@ const char* gks_launch_config(const gks_handle* hc)
     if (!hc) return "";
     gks_handle* h = const_cast<gks_handle*>(hc);
     if (h->dim == 2) {
-        h->cfg_text = "2-D: fixed tiles (face rows 64x4, Gauss points 64x2, cells 64x4)";
+        h->cfg_text = "2-D: fixed tiles (face rows 64x4, Gauss points 64x4, cells 64x4)";
     } else if (!h->tuned) {
         h->cfg_text = "1-D: not tuned yet (tunes on the first gks_step)";
     } else {

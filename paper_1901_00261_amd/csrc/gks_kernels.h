@@ -178,8 +178,11 @@ __device__ __forceinline__ void tile_xy(int gx, int& tx, int& ty)
 // cells i-1..i+2.  emit(q, k, value) receives, in the local frame: q = 0 W0,
 // 1 dn W0 (per unit length), 2 dnn W0, 3 Wl, 4 Wr, 5 dn Wl, 6 dn Wr.
 // Non-physical WENO states fall back to the adjacent cell average.
+// Types: D the stencil data and the emitted values; T the compact and WENO-Z
+// arithmetic (on differences from the cell left of the face, formed in D);
+// F the characteristic frame and the projections (FP32 in the mixed path).
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, int ORDER, typename D = double, typename Emit>
+template <typename T, int DIM, int ORDER, typename D = double, typename F = D, typename Emit>
 GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, bool weno, Emit&& emit)
 {
     const D ih = D(1) / h;
@@ -209,25 +212,25 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
     }
     if (!weno) return true;
     // characteristic frame at the mean of the two interface cells
-    D Wm[4];
+    F Wm[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Wm[k] = D(0.5) * (Wk[1][k] + Wk[2][k]);
-    CharFrame<D, DIM> fr;
-    if (!fr.init(Wm, gamma)) return false;
-    D ql[4], qr[4], qlx[4], qrx[4];
+    for (int k = 0; k < 4; ++k) Wm[k] = F(D(0.5) * (Wk[1][k] + Wk[2][k]));
+    CharFrame<F, DIM> fr;
+    if (!fr.init(Wm, F(gamma))) return false;
+    F ql[4], qr[4], qlx[4], qrx[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        if (DIM == 1 && a == 2) { ql[a] = qr[a] = qlx[a] = qrx[a] = D(0); continue; }
-        D l[4];
+        if (DIM == 1 && a == 2) { ql[a] = qr[a] = qlx[a] = qrx[a] = F(0); continue; }
+        F l[4];
         fr.left(a, l);
         T w[4], d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            D sw = D(0), sd = D(0);
+            F sw = F(0), sd = F(0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                sw += l[k] * (Wk[q][k] - Wk[1][k]);
-                sd += l[k] * Dk[q][k];
+                sw += l[k] * F(Wk[q][k] - Wk[1][k]);
+                sd += l[k] * F(Dk[q][k]);
             }
             w[q] = T(sw);
             d[q] = T(sd);
@@ -235,17 +238,20 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
         T vl, dl, vr, dr;
         weno_left<T, ORDER>(w, d, vl, dl);
         weno_right<T, ORDER>(w, d, vr, dr);
-        ql[a] = D(vl); qlx[a] = D(dl); qr[a] = D(vr); qrx[a] = D(dr);
+        ql[a] = F(vl); qlx[a] = F(dl); qr[a] = F(vr); qrx[a] = F(dr);
     }
+    F Wlf[4], Wrf[4], Wlxf[4], Wrxf[4];
+    fr.right(ql, Wlf);
+    fr.right(qr, Wrf);
+    fr.right(qlx, Wlxf);
+    fr.right(qrx, Wrxf);
     D Wl[4], Wr[4], Wlx[4], Wrx[4];
-    fr.right(ql, Wl);
-    fr.right(qr, Wr);
-    fr.right(qlx, Wlx);
-    fr.right(qrx, Wrx);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        Wl[k] += Wk[1][k];
-        Wr[k] += Wk[1][k];
+        Wl[k] = D(Wlf[k]) + Wk[1][k];
+        Wr[k] = D(Wrf[k]) + Wk[1][k];
+        Wlx[k] = D(Wlxf[k]);
+        Wrx[k] = D(Wrxf[k]);
     }
     const bool okl = physical<D>(Wl, gamma, DIM), okr = physical<D>(Wr, gamma, DIM);
 #pragma unroll
@@ -443,29 +449,32 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
                 for (int k = 0; k < 4; ++k) Dk[q][k] *= P.dx;
                 ghost_frame_1d(kind[q], Wk[q], Dk[q]);
             }
-            double o[7][4];
-            auto put = [&](int q, int k, double v) { o[q][k] = v; };
-            bool ok = (P.order == 8) ? face_recon<T, 1, 8>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
-                                     : face_recon<T, 1, 6>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put);
+            // face reconstruction emitted in T (the FP32-mixed path stores
+            // and evaluates the interface point in FP32)
+            T o[7][4];
+            auto put = [&](int q, int k, double v) { o[q][k] = T(v); };
+            bool ok = (P.order == 8) ? face_recon<T, 1, 8, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
+                                     : face_recon<T, 1, 6, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put);
             PointIn<T> in;
-            PointOut<double> out;
-            NonEq<double, 1, T> ne;
+            PointOut<T> out;
+            NonEq<T, 1, T> ne;
             const PointPar par = point_par<1>(P.gamma, P.K, P.mu, dt);
             if (ok) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    in.W0x[k] = T(o[1][k]); in.W0xx[k] = T(o[2][k]);
+                    in.W0x[k] = o[1][k]; in.W0xx[k] = o[2][k];
                     in.W0y[k] = in.W0xy[k] = in.W0yy[k] = T(0);
-                    in.Wlx[k] = T(o[5][k]); in.Wrx[k] = T(o[6][k]);
+                    in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
                     in.Wly[k] = in.Wry[k] = T(0);
                 }
-                ok = noneq_states<double, 1, T>(o[3], o[4], P.gamma, P.K, par.iN, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+                ok = noneq_states<T, 1, T>(o[3], o[4], T(P.gamma), T(P.K), T(par.iN), ne, in.Wlx, in.Wly, in.Wrx,
+                                           in.Wry);
             }
-            if (ok) ok = gks_point<T, 1>(par, in, P.recon ? ne.Xs : o[0], ne, out);
+            if (ok) ok = gks_point<T, 1, T>(par, in, P.recon ? ne.Xs : o[0], ne, out);
             if (!ok) {
                 atomicOr(&S.err, 1);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = 0.0;
+                for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = T(0);
             }
             const bool own = (t < BLK - 1) || (f == P.nx);
             const long long g = P.foff + f;
@@ -473,14 +482,14 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const int sl = slot[k];
-                sh_FdL[k][t] = out.FdL[sl];
+                sh_FdL[k][t] = double(out.FdL[sl]);
                 if (STAGE == 1) {
-                    const double s0 = out.S0[sl], s1 = out.S1[sl], s2 = out.S2[sl];
-                    sh_FL[k][t] = out.FL[sl];
+                    const double s0 = double(out.S0[sl]), s1 = double(out.S1[sl]), s2 = double(out.S2[sl]);
+                    sh_FL[k][t] = double(out.FL[sl]);
                     sh_Wf[k][t] = msmd_half(s0, s1, s2, dt);
                     if (own) Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
                 } else {
-                    sh_Wf[k][t] = msmd_corr(sh_face[k][t], out.S2[sl], dt);
+                    sh_Wf[k][t] = msmd_corr(sh_face[k][t], double(out.S2[sl]), dt);
                 }
             }
         }
@@ -525,11 +534,15 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
         // sets the next dt and builds the next step's work list
         __shared__ int sh_last, sh_stopped;
         __shared__ int sh_scan[BLK];
-        // (the last workgroup reads only what other workgroups wrote with
-        // device-scope atomics: the error flags and the signal-speed maxima;
-        // the barrier waits for this workgroup's atomics to complete)
+        // Release/acquire pairing of the "last workgroup" pattern: every
+        // workgroup's writes of this launch (cell states, the error flags,
+        // the signal-speed maxima) are made visible device-wide by the
+        // release fence before its done-counter increment; the workgroup
+        // that sees the final count issues the acquire fence below before
+        // it reads them.
         __syncthreads();
         if (t == 0) {
+            __threadfence(); // release
             sh_last = atomicAdd(&ctr[2], 1u) == gridDim.x - 1;
             sh_stopped = 0;
         }
@@ -569,22 +582,26 @@ __global__ void __launch_bounds__(kBlock1D) signal1d_kernel(const ProbParam* __r
     block_max_atomic(s, &S.smax);
 }
 
-// Row stride of the 2-D row buffers: the row length rounded up to even, so
-// that rows and planes start on 16-byte boundaries (the interface kernel
-// stages them with 16-byte copies).
-__host__ __device__ constexpr int row_stride(int len) { return (len + 1) & ~1; }
+// Row stride of the 2-D row buffers (elements of size ES bytes: 8 in FP64,
+// 4 in the FP32-mixed path): the row length rounded up to a multiple of 16
+// bytes, so that rows and planes start on 16-byte boundaries (the interface
+// kernel stages them with 16-byte copies).
+__host__ __device__ constexpr int row_stride(int len, int ES = 8)
+{
+    return ES == 8 ? (len + 1) & ~1 : (len + 3) & ~3;
+}
 
-// Doubles allocated past the end of a 2-D row buffer: the staging copies of
+// Elements allocated past the end of a 2-D row buffer: the staging copies of
 // the workgroups at the grid's far edges read up to three rows (of at most
-// nx + 5 doubles) plus one 128-double segment beyond the last plane, so
+// nx + 5 elements) plus one 128-element segment beyond the last plane, so
 // every copy stays inside the allocation.
 __host__ __device__ constexpr long long row_buffer_pad(int nx) { return 3ll * (nx + 5) + 128; }
 
-// Doubles of the row buffer of direction dir: 28 planes of A rows of stride
-// row_stride(B), plus the pad.
-__host__ __device__ constexpr long long row_buffer_doubles(int nx, int ny, int dir)
+// Elements of the row buffer of direction dir: 28 planes of A rows of
+// stride row_stride(B, ES), plus the pad.
+__host__ __device__ constexpr long long row_buffer_elems(int nx, int ny, int dir, int ES = 8)
 {
-    return 28ll * (dir == 0 ? ny + 4 : ny + 1) * row_stride(dir == 0 ? nx + 1 : nx + 4) + row_buffer_pad(nx);
+    return 28ll * (dir == 0 ? ny + 4 : ny + 1) * row_stride(dir == 0 ? nx + 1 : nx + 4, ES) + row_buffer_pad(nx);
 }
 
 // ---------------------------------------------------------------------------
@@ -600,7 +617,7 @@ __host__ __device__ constexpr long long row_buffer_doubles(int nx, int ny, int d
 template <typename T, int DIR, int ORDER>
 __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
                                                     const double* __restrict__ W, const double* __restrict__ Wx,
-                                                    const double* __restrict__ Wy, int stage, double* __restrict__ R)
+                                                    const double* __restrict__ Wy, int stage, T* __restrict__ R)
 {
     const ProbParam& P = PP[0];
     ProbState& S = PS[0];
@@ -647,9 +664,9 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
 #pragma unroll
         for (int k = 0; k < 4; ++k) { Wk[q][k] = w[k]; Dk[q][k] = d[k]; }
     }
-    const size_t Bs = row_stride(B), AB = (size_t)A * Bs, ab = (size_t)a * Bs + b;
-    auto put = [&](int q, int k, double v) { R[(q * 4 + k) * AB + ab] = v; };
-    const bool ok = face_recon<T, 2, ORDER>(Wk, Dk, h, P.gamma, P.recon != 0, put);
+    const size_t Bs = row_stride(B, sizeof(T)), AB = (size_t)A * Bs, ab = (size_t)a * Bs + b;
+    auto put = [&](int q, int k, double v) { R[(q * 4 + k) * AB + ab] = T(v); };
+    const bool ok = face_recon<T, 2, ORDER, double, T>(Wk, Dk, h, P.gamma, P.recon != 0, put);
     if (!ok) S.err = 1;
 }
 
@@ -693,7 +710,12 @@ GKS_HD void gp_noneq_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T>
 #pragma unroll
         for (int r = 0; r < 5; ++r) { ql[r] = rv(3, k, r) - base; qr[r] = rv(4, k, r) - base; }
         D vl, vr;
-        tan_weno_pair<D>(ql, qr, g, vl, vr);
+        if constexpr (std::is_same_v<D, float>) {
+            vl = tan_weno_f32(ql, g);
+            vr = tan_weno_f32(qr, g);
+        } else {
+            tan_weno_pair<D>(ql, qr, g, vl, vr);
+        }
         wl = base + vl;
         wr = base + vr;
     } else {
@@ -760,50 +782,60 @@ GKS_HD void gp_inputs(const Acc& rv, int g, D ht, bool weno, D gamma, PointIn<T>
 // Row-buffer reads through a buffer resource: 32-bit per-lane offsets for
 // the five stencil rows, the quantity plane as a scalar offset.  The
 // interface kernel uses it only for the rare positivity fallback.
+template <typename S>
 struct RowReader {
     __amdgpu_buffer_rsrc_t rsrc;
     unsigned voff[5];  // byte offset of row r (lane dependent)
     unsigned plane;    // bytes between quantity planes
-    __device__ __forceinline__ double operator()(int q, int k, int r) const
+    __device__ __forceinline__ S operator()(int q, int k, int r) const
     {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff[r], (unsigned)(q * 4 + k) * plane, 0);
-        return __builtin_bit_cast(double, v);
+        if constexpr (sizeof(S) == 8) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff[r], (unsigned)(q * 4 + k) * plane, 0);
+            return __builtin_bit_cast(S, v);
+        } else {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff[r], (unsigned)(q * 4 + k) * plane, 0);
+            return __builtin_bit_cast(S, v);
+        }
     }
 };
 
 // Interface-kernel workgroup: 64 lanes along the contiguous index of the
 // row buffer (x faces: the face; y faces: the transverse cell) times 4 waves
-// (x faces: four transverse rows; y faces: four faces); its LDS (the staged
-// stencil and the Gauss sums) takes one workgroup per CU, one wave per SIMD.
+// (x faces: four transverse rows; y faces: four faces).  FP64: its LDS (the
+// staged stencil and the Gauss sums) takes one workgroup per CU, one wave
+// per SIMD; FP32-mixed: half the LDS, two workgroups per CU.
 constexpr int kGpX = 64, kGpY = 4;
 
-// LDS staging of the workgroup's stencil: slot k holds component k of the 7
-// quantities of face_recon over the rows the workgroup needs.  The waves
-// copy it themselves, once, with 16-byte direct-to-LDS loads (no registers
-// held); the three Gauss points then read it from LDS.
+// LDS staging of the workgroup's stencil (elements of type S): slot k holds
+// component k of the 7 quantities of face_recon over the rows the
+// workgroup needs.  The waves copy it themselves, once, with 16-byte
+// direct-to-LDS loads (no registers held); the three Gauss points then read
+// it from LDS.
 //   x faces: 8 transverse rows (4 waves + 4 stencil rows) x 64 faces, one
-//            1 KB copy per row pair (lanes 0-31 the first row, 32-63 the
-//            second);
+//            copy per row pair (FP64: lanes 0-31 the first row, 32-63 the
+//            second; FP32: lanes 0-15 and 16-31, lanes 32-63 idle);
 //   y faces: 4 face rows x 128 transverse entries, of which the 68 read (64
-//            lanes + 4 stencil entries) are copied: one copy per row with
-//            lanes 0-33 active (544 bytes; the copies are bound by the
-//            memory system's throughput, so the unread 60 entries are not
-//            fetched).
-template <int DIR>
+//            lanes + 4 stencil entries) are copied: one copy per row (FP64
+//            lanes 0-33, FP32 lanes 0-16; the copies are bound by the memory
+//            system's throughput, so the unread 60 entries are not fetched).
+template <int DIR, typename S>
 struct GpStage {
     static constexpr int rows = DIR == 0 ? kGpY + 4 : kGpY; // rows per quantity
-    static constexpr int len = DIR == 0 ? kGpX : 2 * kGpX;   // doubles per row
-    static constexpr int doubles = 7 * rows * len;
+    static constexpr int len = DIR == 0 ? kGpX : 2 * kGpX;   // elements per row
+    static constexpr int elems = 7 * rows * len;
     static constexpr int copies = 7;                          // per wave and component
+    static constexpr int per16 = 16 / (int)sizeof(S);         // elements per 16-byte lane copy
+    // lanes taking part in one copy
+    static constexpr int lanes = DIR == 0 ? 2 * kGpX / per16 : (kGpX + 4 + per16 - 1) / per16;
 };
 
 // Reader of a staged component: lane's row r of quantity q.
-template <int DIR>
+template <int DIR, typename S>
 struct StageReader {
-    const double* p; // slot + w * len + lane
-    __device__ __forceinline__ double operator()(int q, int, int r) const
+    const S* p; // slot + w * len + lane
+    __device__ __forceinline__ S operator()(int q, int, int r) const
     {
-        using G = GpStage<DIR>;
+        using G = GpStage<DIR, S>;
         return DIR == 0 ? p[(q * G::rows + r) * G::len] : p[q * G::rows * G::len + r];
     }
 };
@@ -813,14 +845,14 @@ struct StageReader {
 // offset in the row buffer of the workgroup's first row of quantity 0 at
 // this component; plane / rstride: bytes between quantity planes / rows;
 // voff: the lane's byte offset within a copy.
-template <int DIR>
-__device__ __forceinline__ void stage_component(__amdgpu_buffer_rsrc_t rs, double* dst, unsigned sofs,
-                                                unsigned plane, unsigned rstride, int w, unsigned voff)
+template <int DIR, typename S>
+__device__ __forceinline__ void stage_component(__amdgpu_buffer_rsrc_t rs, S* dst, unsigned sofs, unsigned plane,
+                                                unsigned rstride, int w, unsigned voff)
 {
-    using G = GpStage<DIR>;
+    using G = GpStage<DIR, S>;
     const int row = DIR == 0 ? 2 * w : w;
-    // y faces: lanes 34-63 would copy entries 68-127, which no lane reads
-    if (DIR == 0 || (threadIdx.x & 63) < 34) {
+    // lanes past G::lanes would copy entries that no lane reads
+    if ((int)(threadIdx.x & 63) < G::lanes) {
 #pragma unroll
         for (int q = 0; q < 7; ++q)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
@@ -835,27 +867,32 @@ __device__ __forceinline__ void stage_component(__amdgpu_buffer_rsrc_t rs, doubl
 template <int K>
 __device__ __forceinline__ void stage_wait()
 {
-    constexpr int n = GpStage<0>::copies * (3 - K);
+    constexpr int n = 7 * (3 - K);
     static_assert(n < 64, "vmcnt range");
     __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | 0x0F70); // vmcnt(n), other counters free
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Interface kernel.  T: the arithmetic and storage type of the face-row
+// buffer, the staged stencil, the Gauss-point evaluation and the Gauss sums
+// (double in FP64, float in the FP32-mixed path); the time-integration
+// coefficients are FP64 in both, and so are the MSMD face partials written
+// at the end.
 template <typename T, int DIR, int STAGE>
-__global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
-                                                          const double* __restrict__ R, double* __restrict__ FL,
-                                                          double* __restrict__ FdL, double* __restrict__ Wfs,
-                                                          double* __restrict__ Pf)
+__global__ void __launch_bounds__(kGpX * kGpY, sizeof(T) == 4 ? 2 : 1)
+    gp2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const T* __restrict__ R,
+                double* __restrict__ FL, double* __restrict__ FdL, double* __restrict__ Wfs, double* __restrict__ Pf)
 {
     const ProbParam& P = PP[0];
     ProbState& S = PS[0];
     if (!S.active) return;
+    constexpr unsigned ES = sizeof(T);
     const int nx = P.nx, ny = P.ny;
     const int nf = DIR == 0 ? nx + 1 : ny + 1;
     const int nt = DIR == 0 ? ny : nx;
     const int A = DIR == 0 ? nt + 4 : nf, B = DIR == 0 ? nf : nt + 4;
-    const int Bs = row_stride(B);
+    const int Bs = row_stride(B, ES);
     const int nfc = faces_computed(nf - 1, DIR == 0 ? P.bc[0] : P.bc[2]);
     const int bw = DIR == 0 ? nfc : nt; // extent of the lane index
     int tx, ty;
@@ -869,48 +906,52 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
     // compute on whatever the slots hold there, but store nothing.
     const bool valid = face < nfc && tc < nt;
     const size_t AB = (size_t)A * Bs;
-    // the host guarantees row_buffer_doubles(nx, ny, DIR) * 8 < 2^32
+    // the host guarantees row_buffer_elems(nx, ny, DIR, 8) * 8 < 2^32 (the
+    // FP32 buffer is half that size)
     const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)R, (short)0, (int)(unsigned)(row_buffer_doubles(nx, ny, DIR) * sizeof(double)), 0x00020000);
-    const unsigned plane = (unsigned)(AB * sizeof(double));
-    const unsigned rstride = (unsigned)Bs * (unsigned)sizeof(double);
+        (void*)R, (short)0, (int)(unsigned)(row_buffer_elems(nx, ny, DIR, ES) * ES), 0x00020000);
+    const unsigned plane = (unsigned)(AB * ES);
+    const unsigned rstride = (unsigned)Bs * ES;
     // row r of the stencil = transverse index tc - 2 + r, stored at (tc + r);
     // the workgroup's first row starts at (ty kGpY, tx kGpX), 16-byte aligned
-    const unsigned sbase = ((unsigned)(ty * kGpY) * (unsigned)Bs + (unsigned)(tx * kGpX)) * (unsigned)sizeof(double);
-    const unsigned voff = DIR == 0 ? (unsigned)(lane & 31) * 16u + (unsigned)(lane >> 5) * rstride : (unsigned)lane * 16u;
-    RowReader rv; // global reads for the positivity fallback
+    const unsigned sbase = ((unsigned)(ty * kGpY) * (unsigned)Bs + (unsigned)(tx * kGpX)) * ES;
+    using G = GpStage<DIR, T>;
+    constexpr int L = kGpX / G::per16; // lanes per 64-element row segment
+    const unsigned voff =
+        DIR == 0 ? (unsigned)(lane % L) * 16u + (unsigned)(lane / L) * rstride : (unsigned)lane * 16u;
+    RowReader<T> rv; // global reads for the positivity fallback
     rv.rsrc = rsrc;
     rv.plane = plane;
     {
         const unsigned a0 = DIR == 0 ? (unsigned)tc * Bs + face : (unsigned)face * Bs + tc;
         const unsigned bstride = DIR == 0 ? (unsigned)Bs : 1u;
 #pragma unroll
-        for (int r = 0; r < 5; ++r) rv.voff[r] = (a0 + r * bstride) * (unsigned)sizeof(double);
+        for (int r = 0; r < 5; ++r) rv.voff[r] = (a0 + r * bstride) * ES;
     }
-    using G = GpStage<DIR>;
-    __shared__ double slot0[G::doubles], slot1[G::doubles], slot2[G::doubles], slot3[G::doubles];
-    stage_component<DIR>(rsrc, slot0, sbase, plane, rstride, w, voff);
-    stage_component<DIR>(rsrc, slot1, sbase + plane, plane, rstride, w, voff);
-    stage_component<DIR>(rsrc, slot2, sbase + 2 * plane, plane, rstride, w, voff);
-    stage_component<DIR>(rsrc, slot3, sbase + 3 * plane, plane, rstride, w, voff);
+    __shared__ T slot0[G::elems], slot1[G::elems], slot2[G::elems], slot3[G::elems];
+    stage_component<DIR, T>(rsrc, slot0, sbase, plane, rstride, w, voff);
+    stage_component<DIR, T>(rsrc, slot1, sbase + plane, plane, rstride, w, voff);
+    stage_component<DIR, T>(rsrc, slot2, sbase + 2 * plane, plane, rstride, w, voff);
+    stage_component<DIR, T>(rsrc, slot3, sbase + 3 * plane, plane, rstride, w, voff);
     const int lofs = w * G::len + lane;
-    const StageReader<DIR> rd[4] = {{slot0 + lofs}, {slot1 + lofs}, {slot2 + lofs}, {slot3 + lofs}};
+    const StageReader<DIR, T> rd[4] = {{slot0 + lofs}, {slot1 + lofs}, {slot2 + lofs}, {slot3 + lofs}};
     const double ht = DIR == 0 ? P.dy : P.dx;
-    const double iht = 1.0 / ht;
+    const T iht = T(1.0 / ht);
     const double dt = S.dt;
     const PointPar par = point_par<2>(P.gamma, P.K, P.mu, dt);
+    const T gam = T(par.gamma), Kt = T(par.K), iNt = T(par.iN);
     const bool weno = P.recon != 0;
     // Gauss sums of the outputs live in LDS (this lane's column), not in
     // registers across the Gauss-point loop: slot m = 4 q + k, q = 0 FL,
     // 1 FdL, 2 S0, 3 S1, 4 S2 (stage 2: FdL and S2 only, slots 0..7)
     constexpr int NQ = STAGE == 1 ? 5 : 2;
-    __shared__ double sacc[NQ * 4][kGpX * kGpY];
+    __shared__ T sacc[NQ * 4][kGpX * kGpY];
     const int col = w * kGpX + lane;
     bool ok = valid;
 #pragma unroll 1
     for (int g = 0; g < 3; ++g) {
         PointIn<T> in;
-        double W0[4], Wl[4], Wr[4];
+        T W0[4], Wl[4], Wr[4];
         // the first Gauss point waits for each component's copies in turn
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -920,35 +961,35 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
                 else if (k == 2) stage_wait<2>();
                 else stage_wait<3>();
             }
-            gp_noneq_k<T, double>(rd[k], g, k, iht, weno, in, Wl, Wr);
+            gp_noneq_k<T, T>(rd[k], g, k, iht, weno, in, Wl, Wr);
         }
         if (ok) {
-            gp_fallback<double>(rv, weno, par.gamma, Wl, Wr);
-            NonEq<double, 2, T> ne;
-            PointOut<double> o;
-            ok = noneq_states<double, 2, T>(Wl, Wr, par.gamma, par.K, par.iN, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+            gp_fallback<T>(rv, weno, gam, Wl, Wr);
+            NonEq<T, 2, T> ne;
+            PointOut<T> o;
+            ok = noneq_states<T, 2, T>(Wl, Wr, gam, Kt, iNt, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
             // the equilibrium inputs only now, so they are not held across
             // the non-equilibrium states
 #pragma unroll
-            for (int k = 0; k < 4; ++k) gp_equil_k<T, double>(rd[k], g, k, iht, in, W0);
+            for (int k = 0; k < 4; ++k) gp_equil_k<T, T>(rd[k], g, k, iht, in, W0);
             if (ok) {
                 // equilibrium state: the kinetic average (WENO-Z) or the linear
                 // value, selected per element so that every array stays in
                 // registers
-                double We[4];
+                T We[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) We[k] = weno ? ne.Xs[k] : W0[k];
-                ok = gks_point<T, 2>(par, in, We, ne, o);
+                ok = gks_point<T, 2, T>(par, in, We, ne, o);
             }
-            const double wg = g == 1 ? 8.0 / 18.0 : 5.0 / 18.0;
+            const T wg = g == 1 ? T(8.0 / 18.0) : T(5.0 / 18.0);
             if (ok) {
-                const double* src[5] = {o.FL, o.FdL, o.S0, o.S1, o.S2};
+                const T* src[5] = {o.FL, o.FdL, o.S0, o.S1, o.S2};
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const double v = wg * src[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k];
-                        double& sl = sacc[q * 4 + k][col];
+                        const T v = wg * src[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k];
+                        T& sl = sacc[q * 4 + k][col];
                         sl = g == 0 ? v : sl + v;
                     }
             }
@@ -959,11 +1000,12 @@ __global__ void __launch_bounds__(kGpX * kGpY) gp2d_kernel(const ProbParam* __re
         S.err = 1;
         return;
     }
+    // Gauss sums into FP64; the MSMD face partials accumulate in FP64
     double acc[5][4];
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k] = sacc[q * 4 + k][col];
+        for (int k = 0; k < 4; ++k) acc[STAGE == 1 ? q : (q == 0 ? 1 : 4)][k] = double(sacc[q * 4 + k][col]);
     // back to the global frame
     const int gk[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
     const size_t nfa = DIR == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;

@@ -22,6 +22,19 @@ constexpr double kWenoEps = 1e-6;
 
 template <typename T> GKS_HD T tabs(T x) { return x < T(0) ? -x : x; }
 
+// Reciprocal.  FP64 (and any other type): a division.  FP32: the hardware
+// reciprocal v_rcp_f32 on the device (about 1 ulp), the unit roundoff of
+// the FP32 path anyway; a plain division on the host.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__host__ inline float frcp(float x) { return 1.0f / x; }
+template <typename T> GKS_HD T rcp(T x) { return T(1) / x; }
+template <> GKS_HD float rcp<float>(float x) { return frcp(x); }
+template <typename T> GKS_HD T quot(T a, T b) { return a / b; }
+template <> GKS_HD float quot<float>(float a, float b) { return a * frcp(b); }
+// Type of the time-integration coefficients: FP64 when the point is
+// evaluated in FP32 (their formulas cancel for tau_n comparable to dt).
+template <typename D> using ExpT = std::conditional_t<std::is_same_v<D, float>, double, D>;
+
 // ---------------------------------------------------------------------------
 // Compact linear reconstruction at x_{i+1/2} (Sec. 3.1, printed formulas).
 // w[0..3] = W_{i-1..i+2} (any common offset removed), d[0..3] = dx * W'.
@@ -118,28 +131,32 @@ GKS_HD void weno_left(const T* w, const T* d, T& val, T& der)
         d0 = T(3.0 / 98.0); d1 = T(5.0 / 98.0); d2 = T(4.0 / 49.0); d3 = T(7.0 / 98.0);
         d4 = T(7.0 / 98.0); d5 = T(17.0 / 49.0); d6 = T(17.0 / 49.0);
     }
-    // alpha_k = d_k (1 + Z / e_k), e_k = beta_k + eps.  All seven are scaled by
-    // prod_j e_j, which cancels in the normalisation:
-    //   alpha'_k = d_k (e_k + Z) prod_{j != k} e_j,
-    // formed with prefix and suffix products (in FP64 also for FP32 data:
-    // e_k >= eps keeps the products in range), so one division serves all.
-    using R = std::conditional_t<std::is_same_v<T, float>, double, T>;
-    const R e[7] = {R(b0 + eps), R(b1 + eps), R(b2 + eps), R(b3 + eps), R(b4 + eps), R(b5 + eps), R(b6 + eps)};
-    R pre[7], suf[7];
-    pre[0] = R(1);
-    suf[6] = R(1);
+    // alpha_k = d_k (1 + Z / e_k), e_k = beta_k + eps.
+    const T e[7] = {b0 + eps, b1 + eps, b2 + eps, b3 + eps, b4 + eps, b5 + eps, b6 + eps};
+    const T dk[7] = {d0, d1, d2, d3, d4, d5, d6};
+    T al[7];
+    if constexpr (std::is_same_v<T, float>) {
+        // FP32: one hardware reciprocal per candidate (a product of seven
+        // factors >= eps could leave the FP32 range)
 #pragma unroll
-    for (int k = 1; k < 7; ++k) pre[k] = pre[k - 1] * e[k - 1];
+        for (int k = 0; k < 7; ++k) al[k] = dk[k] * (T(1) + Z * rcp(e[k]));
+    } else {
+        // All seven scaled by prod_j e_j, which cancels in the normalisation:
+        //   alpha'_k = d_k (e_k + Z) prod_{j != k} e_j,
+        // formed with prefix and suffix products, so one division serves all.
+        T pre[7], suf[7];
+        pre[0] = T(1);
+        suf[6] = T(1);
 #pragma unroll
-    for (int k = 5; k >= 0; --k) suf[k] = suf[k + 1] * e[k + 1];
-    const R Zr = R(Z);
-    const R dk[7] = {R(d0), R(d1), R(d2), R(d3), R(d4), R(d5), R(d6)};
-    R al[7];
+        for (int k = 1; k < 7; ++k) pre[k] = pre[k - 1] * e[k - 1];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) al[k] = dk[k] * (e[k] + Zr) * (pre[k] * suf[k]);
-    const R invr = R(1) / (al[0] + al[1] + al[2] + al[3] + al[4] + al[5] + al[6]);
-    const T al0 = T(al[0] * invr), al1 = T(al[1] * invr), al2 = T(al[2] * invr), al3 = T(al[3] * invr),
-            al4 = T(al[4] * invr), al5 = T(al[5] * invr), al6 = T(al[6] * invr);
+        for (int k = 5; k >= 0; --k) suf[k] = suf[k + 1] * e[k + 1];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) al[k] = dk[k] * (e[k] + Z) * (pre[k] * suf[k]);
+    }
+    const T invr = rcp(al[0] + al[1] + al[2] + al[3] + al[4] + al[5] + al[6]);
+    const T al0 = al[0] * invr, al1 = al[1] * invr, al2 = al[2] * invr, al3 = al[3] * invr, al4 = al[4] * invr,
+            al5 = al[5] * invr, al6 = al[6] * invr;
     val = al0 * c0 + (al1 + al3) * c1 + al2 * c2 + al4 * c4 + al5 * c5 + al6 * c6;
     // dx * derivative of each candidate at x = dx/2: b1 + b2/2 + b3/8 + b4/48
     const T g0 = a01 + T(0.5) * a02;
@@ -203,7 +220,7 @@ struct CharFrame {
     T U, V, c, H, b1, b2, ic;
     GKS_HD bool init(const T* W, T gamma)
     {
-        const T rho = W[0], ir = T(1) / rho;
+        const T rho = W[0], ir = rcp(rho);
         U = W[1] * ir;
         V = (DIM == 2) ? W[2] * ir : T(0);
         const T q2 = U * U + V * V;
@@ -211,7 +228,7 @@ struct CharFrame {
         if (!(rho > T(0)) || !(p > T(0))) return false;
         c = sqrt(gamma * p * ir);
         H = (W[3] + p) * ir;
-        ic = T(1) / c;
+        ic = rcp(c);
         b1 = (gamma - T(1)) * ic * ic;
         b2 = T(0.5) * q2 * b1;
         return true;
@@ -310,6 +327,40 @@ GKS_HD void tan_weno_frac(const T* q, int g, T& num, T& den)
     const T nm = am0 * cand[0] + am1 * cand[1] + am2 * cand[2], dm = am0 + am1 + am2;
     num = T(sp) * np * dm - T(sm) * nm * dp;
     den = dp * dm;
+}
+
+// The same value in FP32 arithmetic: each candidate's weight from one
+// hardware reciprocal of (beta + eps), each group normalised by one more
+// (products of three such factors could leave the FP32 range).
+GKS_HD float tan_weno_f32(const float* q, int g)
+{
+    float cand[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        cand[k] = float(kTanCand[g][k][0]) * q[k] + float(kTanCand[g][k][1]) * q[k + 1] +
+                  float(kTanCand[g][k][2]) * q[k + 2];
+    const float s0a = q[0] - 2.0f * q[1] + q[2], s0b = q[0] - 4.0f * q[1] + 3.0f * q[2];
+    const float s1a = q[1] - 2.0f * q[2] + q[3], s1b = q[1] - q[3];
+    const float s2a = q[2] - 2.0f * q[3] + q[4], s2b = 3.0f * q[2] - 4.0f * q[3] + q[4];
+    const float be[3] = {float(13.0 / 12.0) * s0a * s0a + 0.25f * s0b * s0b,
+                         float(13.0 / 12.0) * s1a * s1a + 0.25f * s1b * s1b,
+                         float(13.0 / 12.0) * s2a * s2a + 0.25f * s2b * s2b};
+    const float Z = tabs(be[0] - be[2]);
+    const float eps = float(kWenoEps);
+    float w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k] = 1.0f + Z * rcp(be[k] + eps); // alpha_k / gamma_k
+    if (g != 1) {
+        const float a0 = float(kTanLinW[g][0]) * w[0], a1 = float(kTanLinW[g][1]) * w[1],
+                    a2 = float(kTanLinW[g][2]) * w[2];
+        return (a0 * cand[0] + a1 * cand[1] + a2 * cand[2]) * rcp(a0 + a1 + a2);
+    }
+    // centre point: gamma+ = (g + 3|g|)/2, gamma- = gamma+ - g; value sp vp - sm vm
+    const float ap0 = 0.1125f * w[0], ap1 = 2.45f * w[1], ap2 = 0.1125f * w[2];
+    const float am0 = 0.225f * w[0], am1 = 1.225f * w[1], am2 = 0.225f * w[2];
+    const float vp = (ap0 * cand[0] + ap1 * cand[1] + ap2 * cand[2]) * rcp(ap0 + ap1 + ap2);
+    const float vm = (am0 * cand[0] + am1 * cand[1] + am2 * cand[2]) * rcp(am0 + am1 + am2);
+    return 2.675f * vp - 1.675f * vm;
 }
 
 // WENO-Z values at Gauss point g of two row sets (the left and right
@@ -518,18 +569,18 @@ GKS_HD bool primitive(const T* W, T gamma, T& rho, T& U, T& V, T& lam, T& p, T& 
 {
     // ir = 1 / rho and ip = 1 / p are returned for reuse
     rho = W[0];
-    ir = T(1) / rho;
+    ir = rcp(rho);
     U = W[1] * ir;
     V = (DIM == 2) ? W[2] * ir : T(0);
     p = (gamma - T(1)) * (W[3] - T(0.5) * rho * (U * U + V * V));
-    ip = T(1) / p;
+    ip = rcp(p);
     lam = T(0.5) * rho * ip;
     return (rho > T(0)) && (p > T(0));
 }
 
 template <typename T> GKS_HD bool physical(const T* W, T gamma, int dim)
 {
-    const T rho = W[0], ir = T(1) / rho;
+    const T rho = W[0], ir = rcp(rho);
     const T U = W[1] * ir, V = dim == 2 ? W[2] * ir : T(0);
     const T p = (gamma - T(1)) * (W[3] - T(0.5) * rho * (U * U + V * V));
     return (rho > T(0)) && (p > T(0));
@@ -819,14 +870,21 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
     D r0d, U0d, V0d, l0d, p0d, ir0d, ip0d;
     if (!primitive<D, DIM>(W0d, gammad, r0d, U0d, V0d, l0d, p0d, ir0d, ip0d)) return false;
 
-    // collision times (Sec. 4): physical tau in the Navier-Stokes terms,
-    // numerical tau_n (with the pressure-jump term) in the exponentials
+    // collision times (Sec. 4): the Navier-Stokes terms take mu/p (0 for
+    // Euler) plus the pressure-jump term, the artificial dissipation of
+    // discontinuities; the exponentials take the full tau_n (epsilon dt for
+    // Euler, mu/p for Navier-Stokes, plus the jump term)
     const D dtd = D(par.dt);
-    const D jump = tabs((ne.pl - ne.pr) / (ne.pl + ne.pr)) * dtd;
-    const D tau_d = par.mu > 0.0 ? D(par.mu) * ip0d : D(0);
-    const D tau_n = par.mu > 0.0 ? tau_d + jump : D(0.01) * dtd + jump;
+    const D jump = tabs(quot(ne.pl - ne.pr, ne.pl + ne.pr)) * dtd;
+    const D tau_d = (par.mu > 0.0 ? D(par.mu) * ip0d : D(0)) + jump;
+    const D tau_n = par.mu > 0.0 ? tau_d : D(0.01) * dtd + jump;
     D ke, kte, kde, kdte;
-    exp_fit<D>(tau_n, dtd, D(par.idt), ke, kte, kde, kdte);
+    {
+        using E = ExpT<D>;
+        E ke_, kte_, kde_, kdte_;
+        exp_fit<E>(E(tau_n), E(par.dt), E(par.idt), ke_, kte_, kde_, kdte_);
+        ke = D(ke_); kte = D(kte_); kde = D(kde_); kdte = D(kdte_);
+    }
 
     // ---- equilibrium part in central velocities (type T) ----
     Central<T> C;
@@ -915,7 +973,7 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
             out.S1[k] += D(S1n[k]) - kdte * D(S1n[k]);
         }
         // Navier-Stokes: <u (a1 u + a2 v + Abar) psi> = Mc + F1c
-        if (par.mu > 0.0)
+        if (tau_d != D(0))
 #pragma unroll
             for (int k = 0; k < 4; ++k) out.FL[k] -= D(tau * (Mte[k] + F1[k]));
     }
@@ -989,7 +1047,7 @@ GKS_HD bool gks_point(const PointPar& par, const PointIn<T>& in, const D* W0d, c
 #pragma unroll
         for (int k = 0; k < 4; ++k) out.S2[k] = D(S2n[k]);
     }
-    if (par.mu > 0.0) {
+    if (tau_d != D(0)) {
         // <u (G_xt u + G_yt v + G_tt) psi>
         T F1t[4], att[4];
         cbil<0, 0, DIM>(C, At, At, t1);

@@ -20,13 +20,24 @@
 #include <cstdio>
 #include <cstring>
 #include <vector>
+#include <string>
+#include <unordered_map>
+#include <utility>
 
 // Every arithmetic result is a node of an expression graph (operation kind
 // and operands); a unit's count is the number of nodes its outputs depend
 // on, so work whose result is not used by the requested outputs (for
 // example the flux value in the second MSMD stage, which needs only the
 // flux time derivative and the second time derivative of the interface
-// state) is not counted.
+// state) is not counted.  The graph counts what a compiler must execute:
+//   - operations on compile-time constants and launch parameters only are
+//     folded (no node);
+//   - multiplications and divisions by an exact +-1, multiplications by 0
+//     and additions of 0 are folded;
+//   - a sign change is free (an operand modifier) and is carried as a sign
+//     bit, so x - y and x + (-y) are the same node;
+//   - an operation identical to an earlier one (same kind, same operands up
+//     to order for + and *) is the same node (common subexpressions).
 namespace cnt {
 enum Kind : unsigned char { ADD, MUL, DIV, TRANS };
 struct Node {
@@ -34,38 +45,91 @@ struct Node {
     int a, b;
 };
 std::vector<Node> g;
-int make(Kind k, int a, int b)
+std::unordered_map<std::string, int> memo;
+int make(Kind k, int sub, int a, bool na, int b, bool nb)
 {
+    char key[96];
+    snprintf(key, sizeof key, "%d:%d:%d%c:%d%c", (int)k, sub, a, na ? '-' : '+', b, nb ? '-' : '+');
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
     g.push_back({k, a, b});
-    return (int)g.size() - 1;
+    const int id = (int)g.size() - 1;
+    memo.emplace(key, id);
+    return id;
 }
 } // namespace cnt
 
+// id >= 0: a node; -1: a compile-time constant or launch parameter; <= -3:
+// an input datum (each its own leaf)
 struct Cnt {
     double v;
-    int id; // -1: input or constant
-    Cnt() : v(0), id(-1) {}
-    Cnt(double x) : v(x), id(-1) {}
-    Cnt(double x, int i) : v(x), id(i) {}
+    int id;
+    bool neg; // the value is minus that of node id
+    Cnt() : v(0), id(-1), neg(false) {}
+    Cnt(double x) : v(x), id(-1), neg(false) {}
+    Cnt(double x, int i, bool n = false) : v(x), id(i), neg(n) {}
     explicit operator double() const { return v; }
     explicit operator float() const { return (float)v; }
 };
-inline Cnt op(cnt::Kind k, double v, Cnt a, Cnt b) { return Cnt(v, cnt::make(k, a.id, b.id)); }
-inline Cnt operator+(Cnt a, Cnt b) { return op(cnt::ADD, a.v + b.v, a, b); }
-inline Cnt operator-(Cnt a, Cnt b) { return op(cnt::ADD, a.v - b.v, a, b); }
-inline Cnt operator*(Cnt a, Cnt b) { return op(cnt::MUL, a.v * b.v, a, b); }
-inline Cnt operator/(Cnt a, Cnt b) { return op(cnt::DIV, a.v / b.v, a, b); }
-inline Cnt operator-(Cnt a) { return Cnt(-a.v, a.id); }
+inline int& next_data()
+{
+    static int n = -3;
+    return n;
+}
+inline Cnt data(double x) { return Cnt(x, next_data()--); }
+inline bool is_const(const Cnt& a) { return a.id == -1; }
+inline int key_id(const Cnt& a) { return a.id; }
+
+inline Cnt operator-(Cnt a) { return Cnt(-a.v, a.id, a.id != -1 ? !a.neg : false); }
+inline Cnt add(Cnt a, Cnt b, double v)
+{
+    if (is_const(a) && is_const(b)) return Cnt(v);
+    if (is_const(a) && a.v == 0.0) return b;
+    if (is_const(b) && b.v == 0.0) return a;
+    // (-a) + (-b) = -(a + b); order the operands (commutative)
+    bool flip = false;
+    if (a.neg && b.neg) { a.neg = b.neg = false; flip = true; }
+    if (a.id > b.id || (a.id == b.id && a.neg > b.neg)) std::swap(a, b);
+    const int n = cnt::make(cnt::ADD, 0, a.id, a.neg, b.id, b.neg);
+    return Cnt(v, n, flip);
+}
+inline Cnt mul(Cnt a, Cnt b, double v, bool div)
+{
+    if (is_const(a) && is_const(b)) return Cnt(v);
+    if (!div && ((is_const(a) && a.v == 0.0) || (is_const(b) && b.v == 0.0))) return Cnt(0.0);
+    if (is_const(b) && (b.v == 1.0 || b.v == -1.0)) return b.v < 0 ? -a : a;
+    if (!div && is_const(a) && (a.v == 1.0 || a.v == -1.0)) return a.v < 0 ? -b : b;
+    // signs factor out of products and quotients; a constant operand is
+    // keyed by its magnitude
+    const bool flip = (a.neg != b.neg) != ((is_const(a) && a.v < 0) != (is_const(b) && b.v < 0));
+    int ia = a.id, ib = b.id;
+    long long ca = 0, cb = 0;
+    if (is_const(a)) { double m = std::fabs(a.v); std::memcpy(&ca, &m, 8); ia = -1000000000 - (int)(ca % 1000000007ll % 1000000000); }
+    if (is_const(b)) { double m = std::fabs(b.v); std::memcpy(&cb, &m, 8); ib = -1000000000 - (int)(cb % 1000000007ll % 1000000000); }
+    if (!div && ia > ib) std::swap(ia, ib);
+    const int n = cnt::make(div ? cnt::DIV : cnt::MUL, 0, ia, false, ib, false);
+    return Cnt(v, n, flip);
+}
+inline Cnt trans(int sub, Cnt a, double v)
+{
+    if (is_const(a)) return Cnt(v);
+    return Cnt(v, cnt::make(cnt::TRANS, sub, a.id, a.neg, -1, false));
+}
+inline Cnt operator+(Cnt a, Cnt b) { return add(a, b, a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { return add(a, -b, a.v - b.v); }
+inline Cnt operator*(Cnt a, Cnt b) { return mul(a, b, a.v * b.v, false); }
+inline Cnt operator/(Cnt a, Cnt b) { return mul(a, b, a.v / b.v, true); }
 inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
 inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
 inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
-inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v), a.id); }
+inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v), a.id, false); }
 inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
-inline Cnt sqrt(Cnt a) { return op(cnt::TRANS, std::sqrt(a.v), a, Cnt()); }
-inline Cnt exp(Cnt a) { return op(cnt::TRANS, std::exp(a.v), a, Cnt()); }
-inline Cnt expm1(Cnt a) { return op(cnt::TRANS, std::expm1(a.v), a, Cnt()); }
-inline Cnt erfc(Cnt a) { return op(cnt::TRANS, std::erfc(a.v), a, Cnt()); }
+inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
+inline Cnt sqrt(Cnt a) { return trans(1, a, std::sqrt(a.v)); }
+inline Cnt exp(Cnt a) { return trans(2, a, std::exp(a.v)); }
+inline Cnt expm1(Cnt a) { return trans(3, a, std::expm1(a.v)); }
+inline Cnt erfc(Cnt a) { return trans(4, a, std::erfc(a.v)); }
 
 struct Tally {
     long long add = 0, mul = 0, dv = 0, trans = 0;
@@ -105,7 +169,7 @@ static void emit(const char* name, Tally t, bool comma)
 static void smooth_state(Cnt* W, double s)
 {
     const double rho = 1.0 + 0.1 * s, U = 0.3 - 0.05 * s, V = -0.2 + 0.04 * s, p = 1.0 + 0.07 * s;
-    W[0] = rho; W[1] = rho * U; W[2] = rho * V; W[3] = p / 0.4 + 0.5 * rho * (U * U + V * V);
+    W[0] = data(rho); W[1] = data(rho * U); W[2] = data(rho * V); W[3] = data(p / 0.4 + 0.5 * rho * (U * U + V * V));
 }
 
 static void push4(std::vector<Cnt>& v, const Cnt* a)
@@ -122,8 +186,9 @@ int main()
         Cnt Wk[4][4], Dk[4][4], o[7][4];
         for (int q = 0; q < 4; ++q) {
             smooth_state(Wk[q], 0.1 * q);
-            for (int k = 0; k < 4; ++k) Dk[q][k] = 0.01 * (k + 1) * (q + 1);
+            for (int k = 0; k < 4; ++k) Dk[q][k] = data(0.01 * (k + 1) * (q + 1));
         }
+        cnt::memo.clear(); // merge common subexpressions within a unit only
         const size_t first = cnt::g.size();
         gks::face_recon<Cnt, 2, 8, Cnt>(Wk, Dk, Cnt(0.01), Cnt(gamma), true, [&](int q, int k, Cnt v) { o[q][k] = v; });
         std::vector<Cnt> outs;
@@ -137,13 +202,18 @@ int main()
             Cnt s[4];
             smooth_state(s, 0.05 * r);
             for (int k = 0; k < 4; ++k) {
-                rows[0][k][r] = s[k]; rows[3][k][r] = s[k]; rows[4][k][r] = s[k];
-                rows[1][k][r] = 0.1 * (k + 1); rows[2][k][r] = 0.01 * (k + 2);
-                rows[5][k][r] = 0.1 * (k + 1); rows[6][k][r] = 0.1 * (k + 1);
+                // the two non-equilibrium states differ from the equilibrium
+                // value (as WENO-Z and linear reconstructions do)
+                rows[0][k][r] = s[k];
+                rows[3][k][r] = data(s[k].v * (1.0 + 1e-3 * (k + 1) + 2e-4 * r));
+                rows[4][k][r] = data(s[k].v * (1.0 - 7e-4 * (k + 1) + 3e-4 * r));
+                rows[1][k][r] = data(0.1 * (k + 1) + 0.003 * r); rows[2][k][r] = data(0.01 * (k + 2) + 0.001 * r);
+                rows[5][k][r] = data(0.1 * (k + 1) + 0.002 * r); rows[6][k][r] = data(0.1 * (k + 1) - 0.002 * r);
             }
         }
         auto rv = [&](int q, int k, int r) { return rows[q][k][r]; };
         const gks::PointPar par = gks::point_par<2>(gamma, K2, ns ? 1e-4 : 0.0, 1e-3);
+        cnt::memo.clear(); // merge common subexpressions within a unit only
         const size_t first = cnt::g.size();
         bool ok = true;
         std::vector<Cnt> all, s2;
@@ -171,9 +241,10 @@ int main()
         for (int q = 0; q < 4; ++q) {
             smooth_state(Wk[q], 0.1 * q);
             Wk[q][2] = 0.0;
-            Wk[q][3] = 1.0 / 0.4 + 0.5 * Wk[q][1].v * Wk[q][1].v / Wk[q][0].v;
-            for (int k = 0; k < 4; ++k) Dk[q][k] = k == 2 ? 0.0 : 0.01 * (k + 1) * (q + 1);
+            Wk[q][3] = data(1.0 / 0.4 + 0.5 * Wk[q][1].v * Wk[q][1].v / Wk[q][0].v);
+            for (int k = 0; k < 4; ++k) Dk[q][k] = k == 2 ? Cnt(0.0) : data(0.01 * (k + 1) * (q + 1));
         }
+        cnt::memo.clear(); // merge common subexpressions within a unit only
         const size_t first = cnt::g.size();
         bool ok = gks::face_recon<Cnt, 1, 8, Cnt>(Wk, Dk, Cnt(0.01), Cnt(gamma), true, [&](int q, int k, Cnt v) { o[q][k] = v; });
         gks::PointIn<Cnt> in;
