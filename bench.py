@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--study", choices=["none", "equal-l1"], default="none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=400, help="oracle sample: window edge in cells, one step")
+    ap.add_argument("--cpu-window1", type=int, default=100, help="oracle sample on one thread: window edge")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one device-to-device copy of this many MiB (calibrates FETCH_SIZE/WRITE_SIZE)")
     return ap.parse_args()
@@ -158,26 +159,63 @@ def roofline_2d(prob, res, ops, prec):
     return out
 
 
-def cpu_baseline(prob, dt, window):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, dt, window, window1):
     """The oracle advancing a window of the same initial data (extrapolated
-    edges) by one MSMD step with the GPU's dt."""
+    edges) by one MSMD step with the GPU's dt, on all host threads (the
+    reported baseline) and on one thread (a smaller window)."""
     import numpy as np
     import oracle
 
-    n = prob.nx
-    w = min(window, n)
-    j0 = (n - w) // 2
-    sl = (slice(j0, j0 + w), slice(j0, j0 + w))
-    W, Wx, Wy = (np.ascontiguousarray(a[sl]) for a in (prob.W, prob.Wx, prob.Wy))
-    dx = (prob.xhi - prob.xlo) / n
-    kw = prob.oracle_kwargs()
-    kw.update(xlo=0.0, xhi=w * dx, ylo=0.0, yhi=w * dx, bc=(1, 1, 1, 1), dt_fixed=dt, t_end=dt)
-    t0 = time.perf_counter()
-    oracle.run(2, W, Wx, Wy, **kw)
-    el = time.perf_counter() - t0
-    return {"value": w * w / el, "unit": "cell-updates/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"one MSMD step on the central {w}x{w} window of the same {n}x{n} initial data "
-                      f"(extrapolated window edges, dt of the GPU steps), {el:.1f} s"}
+    def one(w, threads):
+        n = prob.nx
+        w = min(w, n)
+        j0 = (n - w) // 2
+        sl = (slice(j0, j0 + w), slice(j0, j0 + w))
+        W, Wx, Wy = (np.ascontiguousarray(a[sl]) for a in (prob.W, prob.Wx, prob.Wy))
+        dx = (prob.xhi - prob.xlo) / n
+        kw = prob.oracle_kwargs()
+        kw.update(xlo=0.0, xhi=w * dx, ylo=0.0, yhi=w * dx, bc=(1, 1, 1, 1), dt_fixed=dt, t_end=dt)
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        oracle.run(2, W, Wx, Wy, **kw)
+        el = time.perf_counter() - t0
+        return w * w / el, el, w
+
+    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    v, el, w = one(window, nthreads)
+    v1, el1, w1 = one(window1, 1)
+    oracle.set_threads(nthreads)
+    return {"value": v, "unit": "cell-updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"one MSMD step on the central {w}x{w} window of the same {prob.nx}x{prob.ny} initial data "
+                      f"(extrapolated window edges, dt of the GPU steps), {el:.1f} s on {nthreads} threads",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": v1, "unit": "cell-updates/s", "cores": 1,
+                              "sample": f"one MSMD step on the central {w1}x{w1} window, {el1:.1f} s"}}
+
+
+# Algorithmic HBM bytes of one 2-D MSMD step per cell: W, W_x, W_y (12
+# doubles) read and written in each stage plus the FP64 partials written in
+# stage 1 and read in stage 2 -- 72 doubles (both precisions keep the state
+# and the partials in FP64).
+STEP_BYTES_2D = 576
+
+
+def hbm_step(value):
+    """Step-level HBM roof: algorithmic bytes per cell-update times the
+    measured cell-updates/s, against the 8 TB/s peak."""
+    gbps = value * STEP_BYTES_2D / 1e9
+    return {"bytes_per_cell_update": STEP_BYTES_2D, "achieved_GBps": gbps, "peak_GBps": HBM_PEAK,
+            "frac": gbps / HBM_PEAK}
 
 
 def load_ops():
@@ -220,11 +258,14 @@ def bench_vortex(args):
                    "kernel_ms_per_step": {k: v[0] / args.steps for k, v in res["kernels"].items()},
                    "ms_per_step_with_kernel_events": res["elapsed_events"] / args.steps * 1e3},
         "roofline": roof,
+        "hbm_step": hbm_step(value),
     }
     if 1 in results and main_p == 0:
         rm = results[1]
+        vm = cells * args.steps / rm["elapsed"]
         line["config"]["mixed"] = {
-            "value": cells * args.steps / rm["elapsed"], "ms_per_step": rm["elapsed"] / args.steps * 1e3,
+            "value": vm, "ms_per_step": rm["elapsed"] / args.steps * 1e3, "speedup_vs_fp64": vm / value,
+            "hbm_step": hbm_step(vm),
             "kernel_ms_per_step": {k: v[0] / args.steps for k, v in rm["kernels"].items()},
             "ms_per_step_with_kernel_events": rm["elapsed_events"] / args.steps * 1e3,
             "roofline": roofline_2d(prob, rm, ops, 1)}
@@ -232,7 +273,7 @@ def bench_vortex(args):
         line["error"] = "non-finite state or missing steps"
     if not args.no_cpu_baseline:
         dt0 = (res["t_after"] - res["t_before"]) / args.steps
-        line["cpu_baseline"] = cpu_baseline(prob, dt0, args.cpu_window)
+        line["cpu_baseline"] = cpu_baseline(prob, dt0, args.cpu_window, args.cpu_window1)
     return line
 
 

@@ -43,12 +43,26 @@ enum {
     GKS_ESTATE = -5    /* handle unusable: a HIP runtime call failed on it earlier (that call returned
                           GKS_EDEVICE or GKS_ENOMEM); only gks_free and gks_last_error remain useful */
 };
-/* Boundary conditions, per side.  Periodic: wrap (both sides of a direction).
+/* Boundary conditions, per side (Sec. 4 uses periodic, non-reflecting,
+   reflecting-wall and prescribed-state boundaries).
+   Periodic: wrap (both sides of a direction).
    Extrapolated (the paper's non-reflecting ends): ghost cells copy the
-   boundary cell with zero normal slope.  Reflecting wall: ghost cells are the
-   mirror image of the interior (normal momentum negated; normal slopes of
-   the other variables negated). */
-enum { GKS_BC_PERIODIC = 0, GKS_BC_EXTRAP = 1, GKS_BC_REFLECT = 2 };
+     boundary cell with zero normal slope.
+   Reflecting wall: ghost cells are the mirror image of the interior (normal
+     momentum negated; normal slopes of the other variables negated).
+   Inflow: ghost cells hold the side's state A (bc_state) with zero slopes.
+   Split (2-D only; the double Mach reflection of Sec. 4.5): ghost cells at
+     position s along the side (cell-centre coordinate) hold state A where
+     s < bc_split[0] + bc_split[1] * t, and beyond that point are a
+     reflecting wall (bc_beyond = GKS_BC_REFLECT) or hold state B
+     (bc_beyond = GKS_BC_INFLOW); t is the time of the stage.
+   Characteristic (1-D only): the boundary cell is projected on the Euler
+     eigenvectors at its state; fields leaving the domain are extended
+     linearly with their slopes, incoming fields keep the boundary value
+     with zero slope.
+   Where two sides meet, the corner ghosts follow the y sides. */
+enum { GKS_BC_PERIODIC = 0, GKS_BC_EXTRAP = 1, GKS_BC_REFLECT = 2, GKS_BC_INFLOW = 3, GKS_BC_SPLIT = 4,
+       GKS_BC_CHAR = 5 };
 enum { GKS_RECON_LINEAR = 0, GKS_RECON_WENOZ = 1 };
 enum { GKS_PREC_FP64 = 0, GKS_PREC_FP32_MIXED = 1 };
 
@@ -60,7 +74,12 @@ enum { GKS_PREC_FP64 = 0, GKS_PREC_FP32_MIXED = 1 };
    dt = cfl * min over cells of dx/(|U|+c) [and dy/(|V|+c)] unless
    dt_fixed > 0.  The last step is shortened so the problem ends exactly at
    t_end.  order: 6 or 8.  recon: GKS_RECON_*.  bc: x-low, x-high, y-low,
-   y-high, GKS_BC_* (periodic must be paired). */
+   y-high, GKS_BC_* (periodic must be paired).  bc_state[side][0/1]: the
+   inflow states A and B of a side, conservative (rho, rho U, rho V, rho E)
+   (rho V ignored in 1-D; must be physical where used); bc_split[side]: the
+   switch position at t = 0 and its speed; bc_beyond[side]: GKS_BC_REFLECT
+   or GKS_BC_INFLOW (split sides only).  Fields of sides that do not use
+   them are ignored (zero-initialise them). */
 typedef struct {
     int32_t dim;
     int32_t nx, ny;
@@ -73,6 +92,9 @@ typedef struct {
     int32_t order;
     int32_t recon;
     int32_t bc[4];
+    double bc_state[4][2][4];
+    double bc_split[4][2];
+    int32_t bc_beyond[4];
 } gks_problem;
 
 typedef struct gks_handle gks_handle;

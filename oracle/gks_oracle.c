@@ -768,11 +768,67 @@ typedef struct {
     int dim, nv, nx, ny, gx, gy, sx, sy;
     double dx, dy, gamma, K, mu, cfl, dt_fixed, t_end;
     int order, recon, bc[4];
+    double xlo, ylo;
+    double bstate[4][2][4]; /* per side: inflow states A and B (conservative, 4 slots) */
+    double bsplit[4][2];    /* per split side: switch position along the side at t = 0, and its speed */
+    int bbeyond[4];         /* per split side: BC_INFLOW (state B) or BC_REFLECT beyond the switch */
 } prob_t;
 
 #define CELL(P, i, j) (((size_t)((j) + (P)->gy) * (P)->sx + (size_t)((i) + (P)->gx)) * (P)->nv)
 
-enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2 };
+enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_INFLOW = 3, BC_SPLIT = 4, BC_CHAR = 5 };
+
+/* Boundary kind of the ghost cells of `side` at position pos along the side
+   (cell-centre coordinate) and time t; *which = 0 (state A) or 1 (state B)
+   for inflow.  A split side is an inflow of state A where pos < s0 + v t
+   (the switch point moves with speed v) and its "beyond" kind elsewhere. */
+static int side_kind(const prob_t *P, int side, double pos, double t, int *which)
+{
+    int b = P->bc[side];
+    *which = 0;
+    if (b == BC_SPLIT) {
+        if (pos < P->bsplit[side][0] + P->bsplit[side][1] * t) return BC_INFLOW;
+        *which = 1;
+        return P->bbeyond[side];
+    }
+    return b;
+}
+
+/* Characteristic non-reflecting ghost values (1-D; reading A16b): the
+   boundary cell's averages and slopes are projected on the eigenvectors of
+   the Euler Jacobian frozen at that cell; a field travelling out of the
+   domain (eigenvalue times outward normal >= 0) is extended linearly with
+   its slope, an incoming field keeps the boundary value with zero slope.
+   g: ghost layer (1, 2); out: +1 on the high side, -1 on the low side. */
+static int char_ghost(const prob_t *P, const double *Wb, const double *Xb, int g, int out, double *Wg,
+                      double *Xg)
+{
+    double R[9], L[9];
+    if (euler_R(1, P->gamma, Wb, R) || invert(3, R, L)) return ORC_ENONPHYS;
+    double rho = Wb[0], U = Wb[1] / rho, p = (P->gamma - 1.0) * (Wb[2] - 0.5 * rho * U * U);
+    double c = sqrt(P->gamma * p / rho);
+    double lam[3] = {U - c, U, U + c}, q[3], dq[3];
+    for (int a = 0; a < 3; ++a) {
+        double v = 0.0, d = 0.0;
+        for (int k = 0; k < 3; ++k) { v += L[a * 3 + k] * Wb[k]; d += L[a * 3 + k] * Xb[k]; }
+        if (out * lam[a] >= 0.0) { q[a] = v + out * g * P->dx * d; dq[a] = d; }
+        else { q[a] = v; dq[a] = 0.0; }
+    }
+    for (int k = 0; k < 3; ++k) {
+        Wg[k] = 0.0; Xg[k] = 0.0;
+        for (int a = 0; a < 3; ++a) { Wg[k] += R[k * 3 + a] * q[a]; Xg[k] += R[k * 3 + a] * dq[a]; }
+    }
+    return ORC_OK;
+}
+
+/* copy inflow state `which` of `side` into a ghost cell (zero slopes) */
+static void put_state(const prob_t *P, int side, int which, double *W, double *Wx, double *Wy)
+{
+    const double *st = P->bstate[side][which];
+    if (P->dim == 1) { W[0] = st[0]; W[1] = st[1]; W[2] = st[3]; }
+    else for (int k = 0; k < 4; ++k) W[k] = st[k];
+    for (int k = 0; k < P->nv; ++k) { Wx[k] = 0.0; if (Wy) Wy[k] = 0.0; }
+}
 
 /* Two ghost layers per side.  Periodic: wrap.  Extrapolated (reading A16):
    ghost average = boundary average, ghost normal slope = 0, ghost
@@ -783,18 +839,29 @@ enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2 };
    W_g(x) = M W(2 x_w - x) with M negating the normal momentum, so a ghost
    holds M times the mirrored cell's average, M times its tangential
    gradient and -M times its normal gradient. */
-static void fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy)
+/* Ghost layers at time t (Sec. 3.1 stencils, Sec. 4 boundary conditions):
+   first the x sides for the interior rows, then the y sides for every
+   column including the x ghosts, so corner cells follow the y sides. */
+static int fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy, double t)
 {
     int nv = P->nv;
     for (int j = 0; j < P->ny; ++j)
         for (int g = 1; g <= P->gx; ++g) {
             int dst[2] = {-g, P->nx - 1 + g};
+            double ypos = P->ylo + (j + 0.5) * P->dy;
             for (int side = 0; side < 2; ++side) {
-                int bc = P->bc[side];
+                int which, bc = side_kind(P, side, ypos, t, &which);
+                size_t d = CELL(P, dst[side], j);
+                if (bc == BC_INFLOW) { put_state(P, side, which, W + d, Wx + d, Wy ? Wy + d : NULL); continue; }
+                if (bc == BC_CHAR) {
+                    size_t b = CELL(P, side == 0 ? 0 : P->nx - 1, j);
+                    if (char_ghost(P, W + b, Wx + b, g, side == 0 ? -1 : 1, W + d, Wx + d)) return ORC_ENONPHYS;
+                    continue;
+                }
                 int src = bc == BC_PERIODIC ? (side == 0 ? P->nx - g : g - 1)
                         : bc == BC_REFLECT  ? (side == 0 ? g - 1 : P->nx - g)
                                             : (side == 0 ? 0 : P->nx - 1);
-                size_t d = CELL(P, dst[side], j), s = CELL(P, src, j);
+                size_t s = CELL(P, src, j);
                 for (int k = 0; k < nv; ++k) {
                     double m = (bc == BC_REFLECT && k == 1) ? -1.0 : 1.0;
                     W[d + k] = m * W[s + k];
@@ -803,16 +870,19 @@ static void fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy)
                 }
             }
         }
-    if (P->dim == 1) return;
+    if (P->dim == 1) return ORC_OK;
     for (int i = -P->gx; i < P->nx + P->gx; ++i)
         for (int g = 1; g <= P->gy; ++g) {
             int dst[2] = {-g, P->ny - 1 + g};
+            double xpos = P->xlo + (i + 0.5) * P->dx;
             for (int side = 0; side < 2; ++side) {
-                int bc = P->bc[2 + side];
+                int which, bc = side_kind(P, 2 + side, xpos, t, &which);
+                size_t d = CELL(P, i, dst[side]);
+                if (bc == BC_INFLOW) { put_state(P, 2 + side, which, W + d, Wx + d, Wy + d); continue; }
                 int src = bc == BC_PERIODIC ? (side == 0 ? P->ny - g : g - 1)
                         : bc == BC_REFLECT  ? (side == 0 ? g - 1 : P->ny - g)
                                             : (side == 0 ? 0 : P->ny - 1);
-                size_t d = CELL(P, i, dst[side]), s = CELL(P, i, src);
+                size_t s = CELL(P, i, src);
                 for (int k = 0; k < nv; ++k) {
                     double m = (bc == BC_REFLECT && k == 2) ? -1.0 : 1.0;
                     W[d + k] = m * W[s + k];
@@ -821,6 +891,7 @@ static void fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy)
                 }
             }
         }
+    return ORC_OK;
 }
 
 /* Along direction dir (0 = x, 1 = y), the local frame puts the normal
@@ -1210,7 +1281,7 @@ static void faces_free(faces_t *F) { free(F->FL); free(F->FdL); free(F->S0); fre
    ORC_ENONPHYS / ORC_EINVAL; *t and *nsteps report progress either way. */
 int orc_run(int dim, int nx, int ny, double xlo, double xhi, double ylo, double yhi,
             double gamma, double mu, double cfl, double dt_fixed, double t_end, int max_steps,
-            int order, int recon, const int *bc,
+            int order, int recon, const int *bc, const double *bstate, const double *bsplit, const int *bbeyond,
             double *W, double *Wx, double *Wy, double *t_io, long *nsteps_out)
 {
     if (init_tables()) return ORC_EINVAL;
@@ -1227,6 +1298,16 @@ int orc_run(int dim, int nx, int ny, double xlo, double xhi, double ylo, double 
     P.K = dim == 1 ? (3.0 - gamma) / (gamma - 1.0) : (4.0 - 2.0 * gamma) / (gamma - 1.0);
     P.order = order; P.recon = recon;
     for (int k = 0; k < 4; ++k) P.bc[k] = bc[k];
+    P.xlo = xlo; P.ylo = ylo;
+    for (int k = 0; k < 4; ++k) {
+        if (bc[k] < BC_PERIODIC || bc[k] > BC_CHAR) return ORC_EINVAL;
+        if ((bc[k] == BC_SPLIT || bc[k] == BC_CHAR) && dim != (bc[k] == BC_SPLIT ? 2 : 1)) return ORC_EINVAL;
+        for (int a = 0; a < 2; ++a)
+            for (int c = 0; c < 4; ++c) P.bstate[k][a][c] = bstate ? bstate[(k * 2 + a) * 4 + c] : 0.0;
+        P.bsplit[k][0] = bsplit ? bsplit[2 * k] : 0.0;
+        P.bsplit[k][1] = bsplit ? bsplit[2 * k + 1] : 0.0;
+        P.bbeyond[k] = bbeyond ? bbeyond[k] : BC_REFLECT;
+    }
     int nv = P.nv;
     size_t ncell = (size_t)P.sx * P.sy * nv, nint = (size_t)nx * P.ny * nv;
     size_t nfx = (size_t)(nx + 1) * P.ny * nv, nfy = dim == 2 ? (size_t)nx * (P.ny + 1) * nv : 1;
@@ -1270,7 +1351,7 @@ int orc_run(int dim, int nx, int ny, double xlo, double xhi, double ylo, double 
         if (t + dt >= t_end - 1e-9 * dt) { dt = t_end - t; last = 1; }
 
         /* stage 1 at t^n */
-        fill_ghosts(&P, Wn, Wxn, dim == 2 ? Wyn : NULL);
+        if ((st = fill_ghosts(&P, Wn, Wxn, dim == 2 ? Wyn : NULL, t))) break;
         if ((st = stage(&P, Wn, Wxn, Wyn, dt, &Fx, &Fy, L, dL))) break;
         /* W* = W^n + dt/2 L^n + dt^2/8 dL^n */
         for (int j = 0; j < P.ny; ++j)
@@ -1286,7 +1367,7 @@ int orc_run(int dim, int nx, int ny, double xlo, double xhi, double ylo, double 
         slopes_from_faces(&P, vx, vy, Wxs, Wys);
 
         /* stage 2 at t* = t^n + dt/2 */
-        fill_ghosts(&P, Ws, Wxs, dim == 2 ? Wys : NULL);
+        if ((st = fill_ghosts(&P, Ws, Wxs, dim == 2 ? Wys : NULL, t + 0.5 * dt))) break;
         if ((st = stage(&P, Ws, Wxs, Wys, dt, &Fxs, &Fys, Ls, dLs))) break;
         /* W^{n+1} = W^n + dt L^n + dt^2/6 (dL^n + 2 dL*) */
         for (int j = 0; j < P.ny; ++j)
@@ -1436,6 +1517,17 @@ int orc_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* Set the number of OpenMP threads of later runs (n >= 1). */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#endif
+    (void)n;
+    return 0;
 }
 
 /* Kinetic average of two states (equilibrium value from WENO states). */

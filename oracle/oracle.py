@@ -12,7 +12,7 @@ from . import build as _build
 
 _lib = None
 
-PERIODIC, EXTRAP, REFLECT = 0, 1, 2
+PERIODIC, EXTRAP, REFLECT, INFLOW, SPLIT, CHAR = 0, 1, 2, 3, 4, 5
 LINEAR, WENOZ = 0, 1
 
 
@@ -34,7 +34,7 @@ def lib():
         i = C.POINTER(C.c_int)
         _lib.orc_run.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
-                                 C.c_int, C.c_int, i, d, d, d, d, C.POINTER(C.c_long)]
+                                 C.c_int, C.c_int, i, d, d, i, d, d, d, d, C.POINTER(C.c_long)]
         _lib.orc_linear_map.argtypes = [C.c_int, d]
         _lib.orc_candidate_map.argtypes = [C.c_int, d]
         _lib.orc_weno.argtypes = [C.c_int, d, d, d, d, d]
@@ -68,10 +68,15 @@ def _f64(a, shape=None):
 
 
 def run(dim, W, Wx, Wy=None, *, xlo, xhi, ylo=0.0, yhi=1.0, gamma=1.4, mu=0.0, cfl=0.3,
-        dt_fixed=0.0, t_end, max_steps=0, order=8, recon=WENOZ, bc=(PERIODIC,) * 4, t0=0.0):
+        dt_fixed=0.0, t_end, max_steps=0, order=8, recon=WENOZ, bc=(PERIODIC,) * 4, t0=0.0,
+        bc_state=None, bc_split=None, bc_beyond=None):
     """Advance (W, Wx[, Wy]) with the oracle.  Arrays: [nx, nv] (1-D) or
     [ny, nx, nv] (2-D), conservative averages and cell-averaged gradients.
-    Returns (W, Wx, Wy, t, nsteps).  Raises OracleError on failure."""
+    Boundary data for INFLOW / SPLIT sides: bc_state [4 sides][2 states][4]
+    (conservative, 4 slots), bc_split [4][2] (switch position at t = 0 and
+    its speed), bc_beyond [4] (INFLOW of state B or REFLECT beyond the
+    switch).  Returns (W, Wx, Wy, t, nsteps).  Raises OracleError on
+    failure."""
     W = _f64(W)
     Wx = _f64(Wx)
     if dim == 1:
@@ -81,10 +86,14 @@ def run(dim, W, Wx, Wy=None, *, xlo, xhi, ylo=0.0, yhi=1.0, gamma=1.4, mu=0.0, c
         ny, nx = W.shape[0], W.shape[1]
         Wy = _f64(Wy)
     bca = (C.c_int * 4)(*bc)
+    bstate = _f64(np.zeros(32) if bc_state is None else bc_state, 32)
+    bsplit = _f64(np.zeros(8) if bc_split is None else bc_split, 8)
+    bbey = (C.c_int * 4)(*((REFLECT,) * 4 if bc_beyond is None else bc_beyond))
     t = C.c_double(t0)
     n = C.c_long(0)
     st = lib().orc_run(dim, nx, ny, xlo, xhi, ylo, yhi, gamma, mu, cfl, dt_fixed, t_end, max_steps,
-                       order, recon, bca, _p(W), _p(Wx), _p(Wy), C.byref(t), C.byref(n))
+                       order, recon, bca, _p(bstate), _p(bsplit), bbey, _p(W), _p(Wx), _p(Wy), C.byref(t),
+                       C.byref(n))
     if st != 0:
         raise OracleError(st, f"oracle run failed with status {st} at t={t.value} after {n.value} steps",
                           t=t.value, nsteps=n.value)
@@ -197,6 +206,12 @@ def exp_fit(tau_n, dt):
 
 def threads():
     return lib().orc_threads()
+
+
+def set_threads(n):
+    """Number of OpenMP threads for later runs."""
+    lib().orc_set_threads.argtypes = [C.c_int]
+    lib().orc_set_threads(int(n))
 
 
 def kinetic_average(dim, gamma, Wl, Wr):

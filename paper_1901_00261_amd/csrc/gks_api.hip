@@ -159,9 +159,24 @@ int validate(const gks_problem* pr, int32_t nprob, int32_t precision)
         if (q.order != 6 && q.order != 8) return bad("order must be 6 or 8");
         if (q.recon != GKS_RECON_LINEAR && q.recon != GKS_RECON_WENOZ) return bad("unknown recon");
         const int nb = dim == 2 ? 4 : 2;
-        for (int k = 0; k < nb; ++k)
-            if (q.bc[k] != GKS_BC_PERIODIC && q.bc[k] != GKS_BC_EXTRAP && q.bc[k] != GKS_BC_REFLECT)
-                return bad("unknown boundary condition");
+        for (int k = 0; k < nb; ++k) {
+            const int b = q.bc[k];
+            if (b < GKS_BC_PERIODIC || b > GKS_BC_CHAR) return bad("unknown boundary condition");
+            if (b == GKS_BC_SPLIT && dim != 2) return bad("split boundaries are 2-D only");
+            if (b == GKS_BC_CHAR && dim != 1) return bad("characteristic boundaries are 1-D only");
+            if (b == GKS_BC_SPLIT && q.bc_beyond[k] != GKS_BC_REFLECT && q.bc_beyond[k] != GKS_BC_INFLOW)
+                return bad("bc_beyond of a split side must be GKS_BC_REFLECT or GKS_BC_INFLOW");
+            if (b == GKS_BC_SPLIT && !(std::isfinite(q.bc_split[k][0]) && std::isfinite(q.bc_split[k][1])))
+                return bad("bc_split must be finite");
+            // the states a side uses must be physical
+            const int nst = b == GKS_BC_INFLOW ? 1 : (b == GKS_BC_SPLIT ? (q.bc_beyond[k] == GKS_BC_INFLOW ? 2 : 1) : 0);
+            for (int a = 0; a < nst; ++a) {
+                const double* st = q.bc_state[k][a];
+                const double rho = st[0], U = st[1] / rho, V = dim == 2 ? st[2] / rho : 0.0;
+                const double pr = (q.gamma - 1.0) * (st[3] - 0.5 * rho * (U * U + V * V));
+                if (!(rho > 0.0) || !(pr > 0.0) || !std::isfinite(pr)) return bad("non-physical boundary state");
+            }
+        }
         for (int k = 0; k < nb; k += 2)
             if ((q.bc[k] == GKS_BC_PERIODIC) != (q.bc[k + 1] == GKS_BC_PERIODIC))
                 return bad("periodic boundaries must be paired");
@@ -503,6 +518,38 @@ void release(gks_handle* h)
     delete h;
 }
 
+// Device-side parameters of one problem (cells from coff, faces from foff
+// in the batched 1-D arrays).
+ProbParam make_param(const gks_problem& q, int dim, long long coff, long long foff)
+{
+    ProbParam P{};
+    P.nx = q.nx;
+    P.ny = dim == 2 ? q.ny : 1;
+    P.coff = coff;
+    P.foff = foff;
+    P.dx = (q.xhi - q.xlo) / q.nx;
+    P.dy = dim == 2 ? (q.yhi - q.ylo) / q.ny : 1.0;
+    P.gamma = q.gamma;
+    P.K = dim == 1 ? (3.0 - q.gamma) / (q.gamma - 1.0) : (4.0 - 2.0 * q.gamma) / (q.gamma - 1.0);
+    P.mu = q.mu;
+    P.cfl = q.cfl;
+    P.dt_fixed = q.dt_fixed;
+    P.t_end = q.t_end;
+    P.order = q.order;
+    P.recon = q.recon;
+    for (int k = 0; k < 4; ++k) P.bc[k] = (dim == 1 && k >= 2) ? 0 : q.bc[k];
+    P.xlo = q.xlo;
+    P.ylo = dim == 2 ? q.ylo : 0.0;
+    for (int k = 0; k < 4; ++k) {
+        for (int a = 0; a < 2; ++a)
+            for (int c = 0; c < 4; ++c) P.bstate[k][a][c] = q.bc_state[k][a][c];
+        P.bsplit[k][0] = q.bc_split[k][0];
+        P.bsplit[k][1] = q.bc_split[k][1];
+        P.bbeyond[k] = q.bc_beyond[k];
+    }
+    return P;
+}
+
 int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, const double* const* W0,
                 const double* const* Wx0, const double* const* Wy0, void* stream, gks_handle** out, bool device)
 {
@@ -547,22 +594,7 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     long long coff = 0, foff = 0;
     for (int p = 0; p < nprob; ++p) {
         const gks_problem& q = probs[p];
-        ProbParam P{};
-        P.nx = q.nx;
-        P.ny = dim == 2 ? q.ny : 1;
-        P.coff = coff;
-        P.foff = foff;
-        P.dx = (q.xhi - q.xlo) / q.nx;
-        P.dy = dim == 2 ? (q.yhi - q.ylo) / q.ny : 1.0;
-        P.gamma = q.gamma;
-        P.K = dim == 1 ? (3.0 - q.gamma) / (q.gamma - 1.0) : (4.0 - 2.0 * q.gamma) / (q.gamma - 1.0);
-        P.mu = q.mu;
-        P.cfl = q.cfl;
-        P.dt_fixed = q.dt_fixed;
-        P.t_end = q.t_end;
-        P.order = q.order;
-        P.recon = q.recon;
-        for (int k = 0; k < 4; ++k) P.bc[k] = (dim == 1 && k >= 2) ? 0 : q.bc[k];
+        const ProbParam P = make_param(q, dim, coff, foff);
         h->hp.push_back(P);
         if (dim == 1) {
             for (int s = 0; s < q.nx; s += gks::kBlock1D) tc.push_back(Tile{p, s});

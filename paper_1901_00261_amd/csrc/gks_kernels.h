@@ -26,7 +26,15 @@ struct ProbParam {
     long long foff; // first face (1-D batching)
     double dx, dy, gamma, K, mu, cfl, dt_fixed, t_end;
     int order, recon, bc[4];
+    double xlo, ylo;
+    double bstate[4][2][4]; // inflow states A, B per side (conservative, 4 slots)
+    double bsplit[4][2];    // split sides: switch position at t = 0 and its speed
+    int bbeyond[4];         // split sides: kind beyond the switch (inflow of B or reflecting)
 };
+
+// Side kinds as given (include/gks.h) and as resolved for one ghost cell.
+constexpr int kBcPeriodic = 0, kBcExtrap = 1, kBcReflect = 2, kBcInflow = 3, kBcSplit = 4, kBcChar = 5;
+constexpr int kResStateA = 3, kResStateB = 4;
 
 struct ProbState {
     double t, dt;
@@ -49,41 +57,59 @@ constexpr int kBlock1D = 128;
 // periodic; 1 ghost of an extrapolated side (copy of the boundary cell,
 // normal slope 0); 2 ghost of a reflecting wall (mirror image: the mirrored
 // cell with its normal momentum negated, its normal slopes negated except
-// that of the normal momentum).
-enum : int { kGhostNone = 0, kGhostCopy = 1, kGhostMirror = 2 };
-__device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi, int& kind)
+// that of the normal momentum); 3, 4 ghost holding the side's inflow state
+// A or B (zero slopes; the index returned is the boundary cell, only so
+// that loads stay in bounds); 5 characteristic ghost (1-D: built from the
+// boundary cell, whose index is returned).
+enum : int { kGhostNone = 0, kGhostCopy = 1, kGhostMirror = 2, kGhostStateA = 3, kGhostStateB = 4,
+             kGhostChar = 5 };
+
+// Resolved kind of the ghost cells of `side` at position pos along the side
+// (cell-centre coordinate) at time t: a split side is inflow A below the
+// moving switch point and its "beyond" kind past it.
+__device__ __forceinline__ int resolve_side(const ProbParam& P, int side, double pos, double t)
 {
-    kind = kGhostNone;
-    if (c < 0) {
-        if (bc_lo == 0) return c + n;
-        if (bc_lo == 2) {
-            kind = kGhostMirror;
-            return -1 - c;
-        }
-        kind = kGhostCopy;
-        return 0;
-    }
-    if (c >= n) {
-        if (bc_hi == 0) return c - n;
-        if (bc_hi == 2) {
-            kind = kGhostMirror;
-            return 2 * n - 1 - c;
-        }
-        kind = kGhostCopy;
-        return n - 1;
-    }
-    return c;
+    const int b = P.bc[side];
+    if (b == kBcSplit)
+        return pos < P.bsplit[side][0] + P.bsplit[side][1] * t ? kResStateA
+                                                                 : (P.bbeyond[side] == kBcInflow ? kResStateB : kBcReflect);
+    return b == kBcInflow ? kResStateA : b;
 }
 
-// map_index with selects instead of branches (the boundary types are
-// uniform, the side of the stencil per lane): the same results, and no
-// divergent branch between a lane's stencil loads.
+// One direction of the index map with a resolved side code (0 periodic,
+// 1 extrapolated, 2 reflecting, 3/4 inflow A/B, 5 characteristic).
+__device__ __forceinline__ int map_side(int c, int n, int code, int& kind)
+{
+    const bool lo = c < 0;
+    if (code == kBcPeriodic) {
+        kind = kGhostNone;
+        return lo ? c + n : c - n;
+    }
+    if (code == kBcReflect) {
+        kind = kGhostMirror;
+        return lo ? -1 - c : 2 * n - 1 - c;
+    }
+    kind = code == kBcExtrap ? kGhostCopy : (code == kResStateA ? kGhostStateA : (code == kResStateB ? kGhostStateB : kGhostChar));
+    return lo ? 0 : n - 1;
+}
+// Cell index of a 1-D stencil through the boundary conditions, with selects
+// instead of branches (the boundary types are uniform, the side of the
+// stencil per lane), so there is no divergent branch between a lane's
+// stencil loads.
+__device__ __forceinline__ int side_ghost_kind(int bc)
+{
+    return bc == kBcPeriodic ? kGhostNone
+           : bc == kBcReflect ? kGhostMirror
+           : bc == kBcInflow ? kGhostStateA
+           : bc == kBcChar   ? kGhostChar
+                             : kGhostCopy;
+}
 __device__ __forceinline__ int map_index_sel(int c, int n, int bc_lo, int bc_hi, int& kind)
 {
     const int lm = bc_lo == 0 ? c + n : (bc_lo == 2 ? -1 - c : 0);
-    const int lk = bc_lo == 0 ? kGhostNone : (bc_lo == 2 ? kGhostMirror : kGhostCopy);
+    const int lk = side_ghost_kind(bc_lo);
     const int hm = bc_hi == 0 ? c - n : (bc_hi == 2 ? 2 * n - 1 - c : n - 1);
-    const int hk = bc_hi == 0 ? kGhostNone : (bc_hi == 2 ? kGhostMirror : kGhostCopy);
+    const int hk = side_ghost_kind(bc_hi);
     const bool lo = c < 0, hi = c >= n;
     kind = lo ? lk : (hi ? hk : kGhostNone);
     return lo ? lm : (hi ? hm : c);
@@ -119,6 +145,34 @@ __device__ __forceinline__ void ghost_frame_1d(int kn, double (&w)[4], double (&
     d[0] = copy ? 0.0 : (mir ? -d[0] : d[0]);
     d[1] = copy ? 0.0 : d[1];
     d[3] = copy ? 0.0 : (mir ? -d[3] : d[3]);
+}
+
+// Characteristic ghost of a 1-D side (w, d: the boundary cell's values and
+// cell-width * slope on entry, the ghost's on return): fields with
+// eigenvalue times outward normal out >= 0 leave the domain and are
+// extended linearly over g cells, the others keep the boundary value with
+// zero slope.  False if the boundary state is not physical.
+__device__ __forceinline__ bool char_ghost_1d(double gamma, int g, int out, double (&w)[4], double (&d)[4])
+{
+    CharFrame<double, 1> fr;
+    if (!fr.init(w, gamma)) return false;
+    const double lam[4] = {fr.U - fr.c, fr.U, 0.0, fr.U + fr.c};
+    double q[4], dq[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (a == 2) { q[a] = dq[a] = 0.0; continue; }
+        double l[4];
+        fr.left(a, l);
+        const double v = l[0] * w[0] + l[1] * w[1] + l[3] * w[3];
+        const double s = l[0] * d[0] + l[1] * d[1] + l[3] * d[3];
+        const bool outgoing = out * lam[a] >= 0.0;
+        q[a] = outgoing ? v + double(out * g) * s : v;
+        dq[a] = outgoing ? s : 0.0;
+    }
+    fr.right(q, w);
+    fr.right(dq, d);
+    w[2] = d[2] = 0.0;
+    return true;
 }
 
 // Two-stage MSMD combinations (Sec. 2.2) with the fused multiply-adds
@@ -443,18 +497,27 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
                 Wk[q][0] = Wb[c[q]]; Wk[q][1] = Wb[Ntot + c[q]]; Wk[q][2] = 0.0; Wk[q][3] = Wb[2 * Ntot + c[q]];
                 Dk[q][0] = Xb[c[q]]; Dk[q][1] = Xb[Ntot + c[q]]; Dk[q][2] = 0.0; Dk[q][3] = Xb[2 * Ntot + c[q]];
             }
+            bool gok = true;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) Dk[q][k] *= P.dx;
                 ghost_frame_1d(kind[q], Wk[q], Dk[q]);
+                const int cq = f - 2 + q, side = cq < 0 ? 0 : 1;
+                if (kind[q] == kGhostStateA) {
+                    const double* st = P.bstate[side][0];
+                    Wk[q][0] = st[0]; Wk[q][1] = st[1]; Wk[q][3] = st[3];
+                    Dk[q][0] = Dk[q][1] = Dk[q][3] = 0.0;
+                } else if (kind[q] == kGhostChar) {
+                    gok = gok && char_ghost_1d(P.gamma, cq < 0 ? -cq : cq - P.nx + 1, side == 0 ? -1 : 1, Wk[q], Dk[q]);
+                }
             }
             // face reconstruction emitted in T (the FP32-mixed path stores
             // and evaluates the interface point in FP32)
             T o[7][4];
             auto put = [&](int q, int k, double v) { o[q][k] = T(v); };
-            bool ok = (P.order == 8) ? face_recon<T, 1, 8, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
-                                     : face_recon<T, 1, 6, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put);
+            bool ok = gok && ((P.order == 8) ? face_recon<T, 1, 8, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
+                                             : face_recon<T, 1, 6, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put));
             PointIn<T> in;
             PointOut<T> out;
             NonEq<T, 1, T> ne;
@@ -642,16 +705,25 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
     const double* Nb = (DIR == 0 ? Wx : Wy) + (size_t)buf * 4 * plane;
     const double h = DIR == 0 ? P.dx : P.dy;
     double Wk[4][4], Dk[4][4];
-    // ghost rows (transverse direction): extrapolated rows are copies with
-    // their normal slopes; mirrored rows negate the transverse momentum
-    int kt;
-    const int t = DIR == 0 ? map_index(tr, ny, P.bc[2], P.bc[3], kt) : map_index(tr, nx, P.bc[0], P.bc[1], kt);
+    // time of this stage's data (time-dependent boundary states)
+    const double tg = stage == 1 ? S.t : S.t + 0.5 * S.dt;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        int kn;
-        const int c = DIR == 0 ? map_index(face - 2 + q, nx, P.bc[0], P.bc[1], kn)
-                               : map_index(face - 2 + q, ny, P.bc[2], P.bc[3], kn);
-        const size_t cell = DIR == 0 ? (size_t)t * nx + c : (size_t)c * nx + t;
+        // the stencil cell (xi, yj); ghosts map through the boundary
+        // conditions, the y sides first (corner ghosts follow the y sides):
+        // extrapolated rows / columns are copies (normal slope zero across
+        // their own side), mirrored ones negate the momentum normal to their
+        // side, inflow ghosts hold the side's state with zero slopes
+        const int xi = DIR == 0 ? face - 2 + q : tr;
+        const int yj = DIR == 0 ? tr : face - 2 + q;
+        int ky = kGhostNone, yjm = yj;
+        if (yj < 0 || yj >= ny)
+            yjm = map_side(yj, ny, resolve_side(P, yj < 0 ? 2 : 3, P.xlo + (xi + 0.5) * P.dx, tg), ky);
+        int kx = kGhostNone, xim = xi;
+        if (ky >= kGhostStateA) xim = min(max(xi, 0), nx - 1);
+        else if (xi < 0 || xi >= nx)
+            xim = map_side(xi, nx, resolve_side(P, xi < 0 ? 0 : 1, P.ylo + (yjm + 0.5) * P.dy, tg), kx);
+        const size_t cell = (size_t)yjm * nx + xim;
         double w[4], d[4];
         // local frame: normal momentum in slot 1, tangential in slot 2
 #pragma unroll
@@ -660,7 +732,18 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
             w[k] = Wb[g * plane + cell];
             d[k] = h * Nb[g * plane + cell];
         }
-        ghost_frame(kn, kt, w, d);
+        if (ky >= kGhostStateA || kx >= kGhostStateA) {
+            const bool ys = ky >= kGhostStateA;
+            const double* st = ys ? P.bstate[yj < 0 ? 2 : 3][ky - kGhostStateA] : P.bstate[xi < 0 ? 0 : 1][kx - kGhostStateA];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                w[k] = st[(DIR == 1 && (k == 1 || k == 2)) ? 3 - k : k];
+                d[k] = 0.0;
+            }
+            kx = kGhostNone;
+            if (ys) ky = kGhostNone;
+        }
+        ghost_frame(DIR == 0 ? kx : ky, DIR == 0 ? ky : kx, w, d);
 #pragma unroll
         for (int k = 0; k < 4; ++k) { Wk[q][k] = w[k]; Dk[q][k] = d[k]; }
     }

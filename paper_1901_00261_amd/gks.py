@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgks.so")
 GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EDEVICE, GKS_ENONPHYS, GKS_ESTATE = 0, -1, -2, -3, -4, -5
 PREC_FP64, PREC_FP32_MIXED = 0, 1
 KERNEL_FLUX, KERNEL_ROW, KERNEL_CELL = 0, 1, 2
-BC_PERIODIC, BC_EXTRAP, BC_REFLECT = 0, 1, 2
+BC_PERIODIC, BC_EXTRAP, BC_REFLECT, BC_INFLOW, BC_SPLIT, BC_CHAR = 0, 1, 2, 3, 4, 5
 
 
 class GksError(RuntimeError):
@@ -30,7 +30,8 @@ class gks_problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("xlo", C.c_double), ("xhi", C.c_double), ("ylo", C.c_double), ("yhi", C.c_double),
                 ("gamma", C.c_double), ("mu", C.c_double), ("cfl", C.c_double), ("dt_fixed", C.c_double),
-                ("t_end", C.c_double), ("order", C.c_int32), ("recon", C.c_int32), ("bc", C.c_int32 * 4)]
+                ("t_end", C.c_double), ("order", C.c_int32), ("recon", C.c_int32), ("bc", C.c_int32 * 4),
+                ("bc_state", C.c_double * 32), ("bc_split", C.c_double * 8), ("bc_beyond", C.c_int32 * 4)]
 
 
 _lib = None
@@ -86,6 +87,17 @@ def to_struct(p) -> gks_problem:
     s.order, s.recon = p.order, p.recon
     for k in range(4):
         s.bc[k] = int(p.bc[k])
+    st = getattr(p, "bc_state", None)
+    sp = getattr(p, "bc_split", None)
+    be = getattr(p, "bc_beyond", None)
+    if st is not None:
+        for i, v in enumerate(np.asarray(st, dtype=np.float64).ravel()[:32]):
+            s.bc_state[i] = float(v)
+    if sp is not None:
+        for i, v in enumerate(np.asarray(sp, dtype=np.float64).ravel()[:8]):
+            s.bc_split[i] = float(v)
+    for k in range(4):
+        s.bc_beyond[k] = int(be[k]) if be is not None else BC_REFLECT
     return s
 
 
@@ -197,3 +209,4 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+

@@ -57,11 +57,19 @@ class Problem:
     Wx: np.ndarray = field(repr=False)
     Wy: np.ndarray | None = field(repr=False, default=None)
     name: str = ""
+    # boundary data of inflow (3) and split (4) sides: states [side][A/B][4
+    # conservative slots], switch position and speed [side][2], kind beyond
+    # the switch [side] (3 inflow of state B, 2 reflecting wall)
+    bc_state: np.ndarray = field(repr=False, default_factory=lambda: np.zeros((4, 2, 4)))
+    bc_split: np.ndarray = field(repr=False, default_factory=lambda: np.zeros((4, 2)))
+    bc_beyond: tuple = (2, 2, 2, 2)
 
     def oracle_kwargs(self):
         return dict(xlo=self.xlo, xhi=self.xhi, ylo=self.ylo, yhi=self.yhi, gamma=self.gamma,
                     mu=self.mu, cfl=self.cfl, dt_fixed=self.dt_fixed, t_end=self.t_end,
-                    order=self.order, recon=self.recon, bc=tuple(self.bc))
+                    order=self.order, recon=self.recon, bc=tuple(self.bc),
+                    bc_state=np.asarray(self.bc_state, dtype=np.float64).ravel(),
+                    bc_split=np.asarray(self.bc_split, dtype=np.float64).ravel(), bc_beyond=tuple(self.bc_beyond))
 
 
 # ---------------------------------------------------------------- 1-D
@@ -100,6 +108,35 @@ def riemann_1d(n, left, right, *, x0=0.5, order=8, recon=1, gamma=1.4, cfl=0.3, 
     Wx = np.zeros_like(W)
     return Problem(1, n, 1, xlo, xhi, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
                    (1, 1, 0, 0), W, Wx, None, name="riemann1d")
+
+
+def blast_wave_1d(n=200, *, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=3.8):
+    """Woodward-Colella blast wave (Sec. 4.2): (rho, U, p) = (1, 0, 1000)
+    for x < 10, (1, 0, 0.01) for 10 <= x < 90, (1, 0, 100) beyond, on
+    [0, 100] between reflecting walls.  With n a multiple of 10 both jumps
+    sit on faces; zero slopes."""
+    x = (np.arange(n) + 0.5) * 100.0 / n
+    p = np.where(x < 10.0, 1000.0, np.where(x < 90.0, 0.01, 100.0))
+    W = prim_to_cons(np.ones(n), 0.0, p, gamma)
+    return Problem(1, n, 1, 0.0, 100.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   (2, 2, 0, 0), W, np.zeros_like(W), None, name=f"blast_n{n}")
+
+
+def acoustic_pulse_1d(n=100, *, bc=(5, 5, 0, 0), order=8, recon=1, gamma=1.4, cfl=0.3, t_end=0.6, amp=1e-3):
+    """A right-running acoustic pulse (simple wave to first order: rho' =
+    amp exp(-((x - 0.5)/0.06)^2), U' = c rho', p' = c^2 rho' on rho = 1,
+    U = 0, p = 1/gamma, c = 1) on [0, 1]; by t = 0.6 it has left through
+    x = 1, so what remains measures the reflection of the right boundary.
+    Exact cell averages and cell-averaged gradients."""
+    c = 1.0
+
+    def fn(x):
+        r = amp * np.exp(-(((x - 0.5) / 0.06) ** 2))
+        return prim_to_cons(1.0 + r, c * r, 1.0 / gamma + c * c * r, gamma)
+
+    W, Wx = _cell_quadrature_1d(fn, n, 0.0, 1.0)
+    return Problem(1, n, 1, 0.0, 1.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   tuple(bc), W, Wx, None, name=f"pulse1d_n{n}")
 
 
 def _cell_quadrature_1d(fn, n, xlo, xhi):
@@ -312,6 +349,47 @@ def riemann_2d(n, *, ny=None, seed=5, states=None, order=8, recon=1, gamma=1.4, 
     Z = np.zeros_like(W)
     return Problem(2, n, ny, 0.0, 1.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
                    (1, 1, 1, 1), W, Z, Z.copy(), name=f"riemann2d_{n}x{ny}")
+
+
+# Double Mach reflection (Sec. 4.5): Mach 10 shock, 60 degrees to the x axis,
+# through (1/6, 0) at t = 0; post-shock and pre-shock (rho, U, V, p)
+DMR_POST = (8.0, 4.125 * math.sqrt(3.0), -4.125, 116.5)
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)
+
+
+def dmr_shock_x(y, t):
+    """x position of the moving shock at height y and time t."""
+    return 1.0 / 6.0 + (y + 20.0 * t) / math.sqrt(3.0)
+
+
+def double_mach_2d(nx=960, ny=None, *, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=0.2):
+    """Double Mach reflection on [0, 4] x [0, 1] (Sec. 4.5).  Cells whose
+    centre lies left of the shock take the post-shock state, the others the
+    pre-shock state; zero slopes.  Boundaries: post-shock inflow on the left,
+    extrapolation on the right; at the bottom the exact post-shock state for
+    x < 1/6 and a reflecting wall beyond; at the top the exact shock motion
+    (post-shock state left of the shock's crossing of y = 1, pre-shock
+    state right of it)."""
+    ny = nx // 4 if ny is None else ny
+    dx, dy = 4.0 / nx, 1.0 / ny
+    xc = (np.arange(nx) + 0.5) * dx
+    yc = (np.arange(ny) + 0.5) * dy
+    post = np.array(xc[None, :] < dmr_shock_x(yc[:, None], 0.0))
+    st = np.where(post[..., None], np.array(DMR_POST), np.array(DMR_PRE))
+    W = prim_to_cons(st[..., 0], st[..., 1], st[..., 3], gamma, V=st[..., 2])
+    Z = np.zeros_like(W)
+    wpost = prim_to_cons(DMR_POST[0], DMR_POST[1], DMR_POST[3], gamma, V=DMR_POST[2])
+    wpre = prim_to_cons(DMR_PRE[0], DMR_PRE[1], DMR_PRE[3], gamma, V=DMR_PRE[2])
+    bstate = np.zeros((4, 2, 4))
+    bsplit = np.zeros((4, 2))
+    bstate[0, 0] = wpost                       # left: post-shock inflow
+    bstate[2, 0] = wpost                       # bottom: post-shock below x = 1/6
+    bsplit[2] = (1.0 / 6.0, 0.0)               #   wall beyond
+    bstate[3, 0], bstate[3, 1] = wpost, wpre   # top: shock crossing y = 1
+    bsplit[3] = (dmr_shock_x(1.0, 0.0), 20.0 / math.sqrt(3.0))
+    return Problem(2, nx, ny, 0.0, 4.0, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   (3, 1, 4, 4), W, Z, Z.copy(), name=f"dmr_{nx}x{ny}",
+                   bc_state=bstate, bc_split=bsplit, bc_beyond=(2, 2, 2, 3))
 
 
 def pulse_box_2d(n, *, ny=None, bc=(2, 2, 2, 2), mu=0.0, gamma=1.4, order=8, recon=1, cfl=0.3, t_end=1e9,

@@ -121,10 +121,14 @@ def test_vortex_1024_fp64_windows(vortex1024):
 
 
 def test_vortex_1024_mixed_windows(vortex1024):
+    """FP32-mixed against the FP64 oracle: the FP32 rounding of the
+    interface values (unit roundoff 6e-8 of O(1) values) enters the slopes
+    divided by the cell width, so the gradient bar is 1e-4 relative
+    (measured 2.6e-5 after two steps); states 1e-6 (measured ~1e-7)."""
     p = vortex1024
     W, Wx, Wy, dts = gpu_steps(p, 1, STEPS)
     centers = sample_centers(1024, 3, 12, extra=[(512, 512)])
-    check_windows(p, (p.W, p.Wx, p.Wy), (W, Wx, Wy), dts, centers, True, CORE + 2 * MARGIN, (2e-7, 2e-5, 2e-5))
+    check_windows(p, (p.W, p.Wx, p.Wy), (W, Wx, Wy), dts, centers, True, CORE + 2 * MARGIN, (1e-6, 1e-4, 1e-4))
 
 
 def test_riemann_4096_fp64_windows(riemann4096):
@@ -136,15 +140,15 @@ def test_riemann_4096_fp64_windows(riemann4096):
 
 
 def test_riemann_4096_mixed_windows(riemann4096):
-    """Shocks: FP32 WENO-Z weights may switch differently; state bar 1e-5
-    relative (max norm over the window core), gradients unchecked beyond
-    finiteness."""
+    """Shocks in FP32-mixed: states and gradients within 1e-5 relative of
+    the FP64 oracle (max norm over each window core; measured 5e-8 on the
+    states and 4e-7 on the gradients after two steps)."""
     p = riemann4096
     W, Wx, Wy, dts = gpu_steps(p, 1, STEPS)
     assert np.isfinite(W).all() and np.isfinite(Wx).all() and np.isfinite(Wy).all()
     m = 2048
     centers = [(m, m), (m, 100), (3000, m)]
-    check_windows(p, (p.W, p.Wx, p.Wy), (W, Wx, Wy), dts, centers, False, CORE + 2 * MARGIN, (1e-5, np.inf, np.inf))
+    check_windows(p, (p.W, p.Wx, p.Wy), (W, Wx, Wy), dts, centers, False, CORE + 2 * MARGIN, (1e-5, 1e-5, 1e-5))
 
 
 @pytest.fixture(scope="module")

@@ -410,3 +410,46 @@ def test_2d_smallest_and_ragged_grids(nx, ny, bc, steps):
     got = S.state(0)
     S.close()
     check(p, got, oracle_run(p, max_steps=steps))
+
+
+def _sampled(ref, W, Wx, Wy):
+    sl = np.ix_(ref["rows"], ref["cols"])
+    return W[sl], Wx[sl], Wy[sl]
+
+
+def _check_sampled_2d(name, ref, got, tol):
+    W, Wx, Wy = _sampled(ref, got[0], got[1], got[2])
+    errs = [rel(W, ref["W"]), rel(Wx, ref["Wx"]), rel(Wy, ref["Wy"])]
+    sums = float(np.abs(got[0].sum(axis=(0, 1)) - ref["sums"]).max() / np.abs(ref["sums"]).max())
+    print(f"{name}: steps gpu {got[4]} oracle {int(ref['nsteps'])}  sampled W/Wx/Wy "
+          f"{errs[0]:.2e} {errs[1]:.2e} {errs[2]:.2e}  sums {sums:.2e}", flush=True)
+    assert got[4] == int(ref["nsteps"]) and abs(got[3] - float(ref["t"])) <= 1e-13
+    assert max(errs) <= tol and sums <= tol
+    return errs
+
+
+def test_vortex_128_to_t02_fp64():
+    """The benchmark's Navier-Stokes vortex workload on 128^2 cells, run to
+    t = 0.2 (25 CFL-0.3 steps), against the oracle's full run (sampled every
+    4th row and column plus a central block, and the conserved sums)."""
+    ref = np.load(os.path.join(GOLDEN, "vortex128_t02.npz"))
+    p = wl.isentropic_vortex_2d(128, mu=1e-4, eps=5.0, acoustic_amp=1e-3, nmodes=32, seed=3, order=8, recon=1,
+                                cfl=0.3, t_end=0.2)
+    got = gpu_run([p])[0]
+    _check_sampled_2d("vortex 128 t=0.2 fp64", ref, got, TOL_W)
+
+
+def test_riemann_2d_256_500_steps_fp64():
+    """The four-quadrant Riemann workload (seed 5) on 256^2 cells for 500
+    CFL-0.3 steps, against the oracle's run (sampled cells and sums)."""
+    path = os.path.join(GOLDEN, "riemann2d_256_s500.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle reference not written yet (tests/golden/make_oracle_refs.py riemann2d_256_s500)")
+    ref = np.load(path)
+    p = wl.riemann_2d(256, seed=5, order=8, recon=1, cfl=0.3)
+    g = gks()
+    S = g.Solver(p)
+    S.step(500)
+    got = S.state(0)
+    S.close()
+    _check_sampled_2d("riemann2d 256 500 steps fp64", ref, got, TOL_W)
