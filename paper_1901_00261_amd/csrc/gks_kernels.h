@@ -640,7 +640,7 @@ __global__ void __launch_bounds__(kBlock1D) signal1d_kernel(const ProbParam* __r
         const double rho = Wb[c], U = Wb[Ntot + c] / rho;
         const double p = (P.gamma - 1.0) * (Wb[2 * Ntot + c] - 0.5 * rho * U * U);
         if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
-        else s = (fabs(U) + sqrt(P.gamma * p / rho)) / P.dx;
+        else s = (fabs(U) + sqrt(P.gamma * p / rho)) * (1.0 / P.dx); // as in the step kernels
     }
     block_max_atomic(s, &S.smax);
 }
@@ -1188,7 +1188,7 @@ __global__ void __launch_bounds__(256) signal2d_kernel(const ProbParam* __restri
         if (!(rho > 0.0) || !(p > 0.0)) S.err = 1;
         else {
             const double cs = sqrt(P.gamma * p / rho);
-            s = fmax((fabs(U) + cs) / P.dx, (fabs(V) + cs) / P.dy);
+            s = fmax((fabs(U) + cs) * (1.0 / P.dx), (fabs(V) + cs) * (1.0 / P.dy)); // as in the step kernels
         }
     }
     block_max_atomic(s, &S.smax);
