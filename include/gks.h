@@ -168,6 +168,29 @@ int gks_cell_updates(const gks_handle* h, int64_t* count);
    GKS_GRAPH=0 disables the hipGraph replay of steps (enabled by default). */
 const char* gks_launch_config(const gks_handle* h);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc.  Advances
+   ONE 1-D problem (prob->dim == 1, at most GKS_NOALLOC_MAX_CELLS cells) by
+   nsteps MSMD steps, starting at time t0, in place in the caller's DEVICE
+   arrays W and Wx ([nx][3] row-major, as gks_init_device takes them), with
+   the same kernels and arithmetic as gks_step.  All working storage (state
+   slots, MSMD partials, parameters, work lists) is a static device array of
+   the library, one per GPU, held until the process ends: the call performs
+   no allocation, memset or host-to-device copy; it only enqueues kernels on
+   `stream` (a hipStream_t; NULL: the default stream) and returns.  Only when
+   t_out, steps_out or status_out is non-NULL does it also copy the run's
+   final time, its step count and its status (0 running, 1 reached t_end,
+   GKS_ENONPHYS) to the host and synchronise the stream.  A problem that
+   meets a non-physical state stops there; W and Wx then hold the state at
+   the start of the failing step.  Every call on a GPU shares that GPU's
+   static array, and each call re-initialises what it uses: calls that
+   overlap on one GPU (different streams or host threads) race and must not
+   be issued.  Errors: GKS_EINVAL (invalid problem, 2-D, more than
+   GKS_NOALLOC_MAX_CELLS cells, nsteps < 0), GKS_EDEVICE. */
+#define GKS_NOALLOC_MAX_CELLS 32768
+int gks_run1d_noalloc(const gks_problem* prob, int32_t precision, double* W, double* Wx, int32_t nsteps, double t0,
+                      void* stream, double* t_out, int64_t* steps_out, int32_t* status_out);
+
 #ifdef __cplusplus
 }
 #endif

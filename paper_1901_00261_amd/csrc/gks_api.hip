@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <mutex>
 
 using gks::ProbParam;
 using gks::ProbState;
@@ -739,6 +740,100 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     return GKS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free 1-D run (gks_run1d_noalloc): every buffer the batched 1-D
+// kernels use lives in `scratch`, a static device array of the library
+// (each GPU holds its own copy until the process ends).  Host code never
+// passes the array's name to a kernel: the address comes from
+// hipGetSymbolAddress, taken once per device.
+// ---------------------------------------------------------------------------
+constexpr long long kNoAllocMaxCells = 32768;
+constexpr int kNoAllocBlk = 256;                                     // tile: 255 cells per work item
+constexpr long long kNoAllocItems = kNoAllocMaxCells / (kNoAllocBlk - 1) + 1;
+constexpr long long kNoAllocTilesC = kNoAllocMaxCells / gks::kBlock1D + 1;
+// layout (in doubles, every part 256-byte aligned)
+constexpr long long na_round(long long d) { return (d + 31) & ~31ll; }
+constexpr long long kNaPar = 0;
+constexpr long long kNaState = kNaPar + na_round((sizeof(ProbParam) + 7) / 8);
+constexpr long long kNaCtr = kNaState + na_round((sizeof(ProbState) + 7) / 8); // 3 counters + item count
+constexpr long long kNaAll = kNaCtr + 32;
+constexpr long long kNaAct = kNaAll + na_round(kNoAllocItems);                 // Tile = 8 bytes
+constexpr long long kNaFirst = kNaAct + na_round(kNoAllocItems);               // first[1], count[1]
+constexpr long long kNaTilesC = kNaFirst + 32;
+constexpr long long kNaW = kNaTilesC + na_round(kNoAllocTilesC);
+constexpr long long kNaWx = kNaW + na_round(9 * kNoAllocMaxCells);
+constexpr long long kNaPW = kNaWx + na_round(9 * kNoAllocMaxCells);
+constexpr long long kNaPf = kNaPW + na_round(3 * kNoAllocMaxCells);
+constexpr long long kScratchDoubles = kNaPf + na_round(3 * (kNoAllocMaxCells + 1));
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mutex;
+
+// the device address of this device's scratch array (taken once per device)
+hipError_t scratch_address(int dev, double** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// Set-up of a run in the scratch area: the problem's parameters and state
+// (time t0, active), cleared counters, the full work-item list of BLK - 1
+// cells per item and the 128-cell tiles of the signal-speed kernel.
+__global__ void noalloc_setup(ProbParam P, double t0, ProbParam* dP, ProbState* dS, unsigned* ctr, int* nact,
+                              Tile* all, int* first, int* count, Tile* tilesC, int nitems, int ntiles)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *dP = P;
+        ProbState S{};
+        S.t = t0;
+        S.active = 1;
+        *dS = S;
+        ctr[0] = ctr[1] = ctr[2] = 0u;
+        *nact = 0;
+        first[0] = 0;
+        count[0] = nitems;
+    }
+    if (i < nitems) all[i] = Tile{0, i * (kNoAllocBlk - 1)};
+    if (i < ntiles) tilesC[i] = Tile{0, i * gks::kBlock1D};
+}
+
+// state slot holding W^n -> caller's [nx][3] arrays
+__global__ void noalloc_out(const ProbState* __restrict__ dS, const double* __restrict__ W,
+                            const double* __restrict__ Wx, double* __restrict__ Wo, double* __restrict__ Wxo, long long n)
+{
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const size_t base = (size_t)dS->cur * 3 * n;
+    for (int k = 0; k < 3; ++k) {
+        Wo[c * 3 + k] = W[base + k * n + c];
+        Wxo[c * 3 + k] = Wx[base + k * n + c];
+    }
+}
+
+template <typename T>
+void noalloc_steps(const ProbParam* dP, ProbState* dS, Tile* act, int* nact, unsigned* ctr, double* W, double* Wx,
+                   double* PW, double* Pf, long long N, long long F, Tile* all, int* first, int* count, int G,
+                   int nsteps, hipStream_t st)
+{
+    for (int s = 0; s < nsteps; ++s) {
+        gks::stage1d_kernel<T, 1, kNoAllocBlk><<<G, kNoAllocBlk, 0, st>>>(dP, dS, act, nact, ctr, W, Wx, PW, Pf, N, F,
+                                                                         1, all, first, count);
+        gks::stage1d_kernel<T, 2, kNoAllocBlk><<<G, kNoAllocBlk, 0, st>>>(dP, dS, act, nact, ctr, W, Wx, PW, Pf, N, F,
+                                                                         1, all, first, count);
+    }
+}
+
 } // namespace
 
 extern "C" {
@@ -906,6 +1001,71 @@ int gks_cell_updates(const gks_handle* h, int64_t* count)
 {
     if (!h || !count) return GKS_EINVAL;
     *count = h->last_updates;
+    return GKS_OK;
+}
+
+int gks_run1d_noalloc(const gks_problem* prob, int32_t precision, double* W, double* Wx, int32_t nsteps, double t0,
+                      void* stream, double* t_out, int64_t* steps_out, int32_t* status_out)
+{
+    if (!prob || !W || !Wx || nsteps < 0) return fail(nullptr, GKS_EINVAL, "gks_run1d_noalloc: NULL argument or nsteps < 0");
+    int st = validate(prob, 1, precision);
+    if (st) return st;
+    if (prob->dim != 1) return fail(nullptr, GKS_EINVAL, "gks_run1d_noalloc: 1-D problems only");
+    if (prob->nx > kNoAllocMaxCells) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "gks_run1d_noalloc: %d cells exceed the scratch limit of %lld cells", prob->nx,
+                 kNoAllocMaxCells);
+        return fail(nullptr, GKS_EINVAL, buf);
+    }
+    if (!std::isfinite(t0)) return fail(nullptr, GKS_EINVAL, "gks_run1d_noalloc: t0 must be finite");
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= kMaxDevices)) return fail(nullptr, GKS_EDEVICE, "device index out of range");
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    double* base = nullptr;
+    if (e == hipSuccess) e = scratch_address(dev, &base);
+    if (e != hipSuccess) return fail(nullptr, GKS_EDEVICE, std::string("gks_run1d_noalloc: ") + hipGetErrorString(e));
+    hipStream_t s = (hipStream_t)stream;
+    const long long N = prob->nx, F = N + 1;
+    ProbParam* dP = reinterpret_cast<ProbParam*>(base + kNaPar);
+    ProbState* dS = reinterpret_cast<ProbState*>(base + kNaState);
+    unsigned* ctr = reinterpret_cast<unsigned*>(base + kNaCtr);
+    int* nact = reinterpret_cast<int*>(ctr + 3);
+    Tile* all = reinterpret_cast<Tile*>(base + kNaAll);
+    Tile* act = reinterpret_cast<Tile*>(base + kNaAct);
+    int* first = reinterpret_cast<int*>(base + kNaFirst);
+    int* count = first + 1;
+    Tile* tilesC = reinterpret_cast<Tile*>(base + kNaTilesC);
+    double *dW = base + kNaW, *dWx = base + kNaWx, *dPW = base + kNaPW, *dPf = base + kNaPf;
+    const int nitems = (int)((N + kNoAllocBlk - 2) / (kNoAllocBlk - 1));
+    const int ntiles = (int)((N + gks::kBlock1D - 1) / gks::kBlock1D);
+    const int nb = (int)((N + 255) / 256);
+    // parameters, state, counters and work lists; the caller's arrays into slot 0
+    noalloc_setup<<<std::max(1, (std::max(nitems, ntiles) + 255) / 256), 256, 0, s>>>(
+        make_param(*prob, 1, 0, 0), t0, dP, dS, ctr, nact, all, first, count, tilesC, nitems, ntiles);
+    aos_to_soa<<<nb, 256, 0, s>>>(W, dW, N, 3, N);
+    aos_to_soa<<<nb, 256, 0, s>>>(Wx, dWx, N, 3, N);
+    // first dt from the state, the active work list, then the steps
+    gks::signal1d_kernel<<<ntiles, gks::kBlock1D, 0, s>>>(dP, dS, tilesC, dW, N);
+    gks::finish_kernel<<<1, 64, 0, s>>>(dP, dS, 1, 0, ctr, 3);
+    gks::compact_items_kernel<<<1, gks::kCompactThreads, 0, s>>>(dS, 1, all, first, count, act, nact);
+    const int G = std::min(nitems, std::max(ncu, 1));
+    if (precision == GKS_PREC_FP64)
+        noalloc_steps<double>(dP, dS, act, nact, ctr, dW, dWx, dPW, dPf, N, F, all, first, count, G, nsteps, s);
+    else
+        noalloc_steps<float>(dP, dS, act, nact, ctr, dW, dWx, dPW, dPf, N, F, all, first, count, G, nsteps, s);
+    noalloc_out<<<nb, 256, 0, s>>>(dS, dW, dWx, W, Wx, N);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, GKS_EDEVICE, std::string("gks_run1d_noalloc: ") + hipGetErrorString(e));
+    if (t_out || steps_out || status_out) {
+        ProbState S{};
+        e = hipMemcpyAsync(&S, dS, sizeof S, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(nullptr, GKS_EDEVICE, std::string("gks_run1d_noalloc: ") + hipGetErrorString(e));
+        if (t_out) *t_out = S.t;
+        if (steps_out) *steps_out = S.nsteps;
+        if (status_out) *status_out = S.err ? GKS_ENONPHYS : (S.active ? 0 : 1);
+    }
     return GKS_OK;
 }
 

@@ -70,13 +70,16 @@ def lib():
         L.gks_cell_updates.argtypes = [hnd, C.POINTER(C.c_int64)]
         L.gks_launch_config.argtypes = [hnd]
         L.gks_launch_config.restype = C.c_char_p
+        L.gks_run1d_noalloc.argtypes = [C.POINTER(gks_problem), C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                        C.c_double, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
 
 EXPORTED = ("gks_init", "gks_init_device", "gks_step", "gks_state", "gks_state_device", "gks_problem_status",
             "gks_free", "gks_last_error", "gks_kernel_timing", "gks_kernel_time", "gks_cell_updates",
-            "gks_launch_config")
+            "gks_launch_config", "gks_run1d_noalloc")
 
 
 def to_struct(p) -> gks_problem:
@@ -210,3 +213,19 @@ class Solver:
     def __exit__(self, *a):
         self.close()
 
+
+def run1d_noalloc(problem, W_ptr, Wx_ptr, nsteps, t0=0.0, precision=PREC_FP64, stream=None, sync=True):
+    """gks_run1d_noalloc: advance one 1-D problem in place in caller-owned
+    device arrays (addresses as ints, [nx][3] float64).  With sync, returns
+    (t, steps, status); otherwise only enqueues the kernels."""
+    s = to_struct(problem)
+    t = C.c_double(0.0)
+    n = C.c_int64(0)
+    stv = C.c_int32(0)
+    st = lib().gks_run1d_noalloc(C.byref(s), precision, C.c_void_p(W_ptr), C.c_void_p(Wx_ptr), int(nsteps),
+                                 float(t0), C.c_void_p(stream) if stream else None,
+                                 C.byref(t) if sync else None, C.byref(n) if sync else None,
+                                 C.byref(stv) if sync else None)
+    if st != GKS_OK:
+        raise GksError(st, lib().gks_last_error(None).decode())
+    return (t.value, n.value, stv.value) if sync else None
