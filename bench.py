@@ -376,11 +376,13 @@ def bench_batch1d(args):
 
 
 def study_equal_l1(args):
-    """Equal-L1 study on the vortex workload: T3 = time reached by 200 FP64
-    steps at 1024^2; reference = FP64 at 2048^2 to T3; for N = 128..1024
-    and both precisions, L1(rho) against the reference block-averaged to
-    N^2 (exact cell averages of the reference field) and the measured
-    cell-updates/s of the whole run."""
+    """Equal-L1 study: T3 = time reached by 200 FP64 steps at 1024^2;
+    reference = FP64 at 2048^2 to T3; for N = 128..1024 and both
+    precisions, L1(rho) against the reference block-averaged to N^2 (exact
+    cell averages of the reference field) and the measured cell-updates/s
+    of the whole run.  Workloads: the smooth Navier-Stokes vortex (default)
+    or, with --workload riemann2d, the shock-dominated four-quadrant Euler
+    Riemann problem."""
     import numpy as np
     import torch
     from paper_1901_00261_amd import gks
@@ -406,16 +408,22 @@ def study_equal_l1(args):
         S.close()
         return W, t, n, el
 
-    base = vortex(1024)
+    if args.workload == "riemann2d":
+        make = lambda n: wl.riemann_2d(n, seed=5, order=8, recon=1, cfl=0.3)
+        name = "2-D Euler four-quadrant Riemann problem (seed 5), [0,1]^2, extrapolated boundaries"
+    else:
+        make = vortex
+        name = "2-D Navier-Stokes vortex + seeded acoustic perturbation, periodic [0,10]^2"
+    base = make(1024)
     _, T3, n3, _ = run_to(base, 0, steps=200)
     log(f"T3 = {T3:.9f} after {n3} FP64 steps at 1024^2")
-    ref_prob = vortex(2048)
+    ref_prob = make(2048)
     Wref, tr, nr, elr = run_to(ref_prob, 0, t_end=T3)
     log(f"reference 2048^2: {nr} steps, t = {tr:.9f}, {elr:.2f} s")
     rho_ref = Wref[:, :, 0]
     rows = []
     for N in (128, 256, 512, 1024):
-        prob = base if N == 1024 else vortex(N)
+        prob = base if N == 1024 else make(N)
         f = 2048 // N
         ref_N = rho_ref.reshape(N, f, N, f).mean(axis=(1, 3))
         for prec in (0, 1):
@@ -448,7 +456,7 @@ def study_equal_l1(args):
             t_eq = math.exp(float(np.interp(ln, Ns, ts)))
         pairs.append({"mixed_N": r["N"], "mixed_L1": target, "mixed_seconds": r["seconds"],
                       "fp64_N_at_equal_L1": n_eq, "fp64_seconds_at_equal_L1": t_eq})
-    return {"study": "equal-L1", "T3": T3, "reference": {"N": 2048, "steps": nr, "seconds": elr},
+    return {"study": "equal-L1", "workload": name, "T3": T3, "reference": {"N": 2048, "steps": nr, "seconds": elr},
             "rows": rows, "equal_L1_pairs": pairs}
 
 
