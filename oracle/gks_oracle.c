@@ -68,7 +68,17 @@
  *       J. Comput. Phys. 175 (2002), theta = 3).
  *   A21 positivity fallback: a face-row WENO-Z state that is not physical
  *       is replaced by the adjacent cell average; a Gauss-point state that is
- *       not physical is replaced by its face-row line value.
+ *       not physical is replaced by its face-row line value (counted: the
+ *       count of the last run is orc_fallbacks()).
+ *   A16 extrapolated boundary: ghost = boundary cell, zero normal slope.
+ *   A16b characteristic non-reflecting boundary (1-D): outgoing
+ *       characteristic fields of the boundary cell extended linearly with
+ *       their slopes, incoming ones held at the boundary value.
+ *   A22 reflecting wall: mirror image with the normal momentum negated.
+ *   A23 inflow and split sides (Sec. 4.5): given states with zero slopes,
+ *       evaluated at each stage's time; on a split side the switch point
+ *       moves along the side, and the kind of a ghost cell is decided at
+ *       its centre coordinate.
  *   G1  the missing operator before the x^4 term of w_6 is "+" (only
  *       consequence here: none, w_6 is built from its conditions).
  *   G2  beta uses the exact integral (a4 coefficient 87617/80640).
@@ -830,18 +840,17 @@ static void put_state(const prob_t *P, int side, int which, double *W, double *W
     for (int k = 0; k < P->nv; ++k) { Wx[k] = 0.0; if (Wy) Wy[k] = 0.0; }
 }
 
-/* Two ghost layers per side.  Periodic: wrap.  Extrapolated (reading A16):
-   ghost average = boundary average, ghost normal slope = 0, ghost
-   tangential slope = boundary tangential slope.  x first (interior rows),
-   then y over all columns so that corners are filled. */
-/* Ghost cells.  Periodic: wrap.  Extrapolated: copy of the boundary cell
-   with zero normal slope.  Reflecting wall: the mirror image of the field,
-   W_g(x) = M W(2 x_w - x) with M negating the normal momentum, so a ghost
-   holds M times the mirrored cell's average, M times its tangential
-   gradient and -M times its normal gradient. */
-/* Ghost layers at time t (Sec. 3.1 stencils, Sec. 4 boundary conditions):
-   first the x sides for the interior rows, then the y sides for every
-   column including the x ghosts, so corner cells follow the y sides. */
+/* Two ghost layers per side at time t (Sec. 3.1 stencils, Sec. 4 boundary
+   conditions).  Periodic: wrap.  Extrapolated (reading A16): ghost average
+   = boundary average, normal slope 0, tangential slope copied.  Reflecting
+   wall (A22): the mirror image W_g(x) = M W(2 x_w - x), M negating the
+   normal momentum, so a ghost holds M times the mirrored cell's average and
+   tangential gradient and -M times its normal gradient.  Inflow: a given
+   state with zero slopes.  Split side: inflow of state A before a switch
+   point moving along the side, its "beyond" kind after it.  Characteristic
+   (1-D, A16b): char_ghost.  First the x sides for the interior rows, then
+   the y sides for every column including the x ghosts, so corner cells
+   follow the y sides. */
 static int fill_ghosts(const prob_t *P, double *W, double *Wx, double *Wy, double t)
 {
     int nv = P->nv;
