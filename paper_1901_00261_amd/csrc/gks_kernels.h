@@ -774,7 +774,7 @@ GKS_HD void gp_noneq_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T>
     const D base = rv(0, k, 2);
 #pragma unroll
     for (int r = 0; r < 5; ++r) {
-        const D c0 = D(kTanLin[g][0][r]), c1 = D(kTanLin[g][1][r]);
+        const D c0 = tan_lin<D>(g, 0, r), c1 = tan_lin<D>(g, 1, r);
         v5 += c0 * rv(5, k, r);
         v6 += c0 * rv(6, k, r);
         d3 += c1 * (rv(3, k, r) - base);
@@ -805,7 +805,7 @@ GKS_HD void gp_noneq_k(const Acc& rv, int g, int k, D iht, bool weno, PointIn<T>
         // linear mode: both states are the equilibrium value
         D v0 = D(0);
 #pragma unroll
-        for (int r = 0; r < 5; ++r) v0 += D(kTanLin[g][0][r]) * (rv(0, k, r) - base);
+        for (int r = 0; r < 5; ++r) v0 += tan_lin<D>(g, 0, r) * (rv(0, k, r) - base);
         wl = wr = base + v0;
     }
     Wl[k] = wl;
@@ -819,7 +819,7 @@ GKS_HD void gp_equil_k(const Acc& rv, int g, int k, D iht, PointIn<T>& in, D* W0
     const D base = rv(0, k, 2);
 #pragma unroll
     for (int r = 0; r < 5; ++r) {
-        const D c0 = D(kTanLin[g][0][r]), c1 = D(kTanLin[g][1][r]), c2 = D(kTanLin[g][2][r]);
+        const D c0 = tan_lin<D>(g, 0, r), c1 = tan_lin<D>(g, 1, r), c2 = tan_lin<D>(g, 2, r);
         const D q0 = rv(0, k, r) - base;
         v0 += c0 * q0;
         d0 += c1 * q0;

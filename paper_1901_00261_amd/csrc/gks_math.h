@@ -286,6 +286,33 @@ __device__ constexpr double kTanLinW[3][3] = {
     {-0.1125, 1.2250000000000001, -0.1125},
     {0.13988896611054835, 0.61526717557251909, 0.24484385831693256}};
 
+// FP32 copies of the three tables (each entry rounded to nearest, as a
+// conversion at the point of use would round it): the Gauss-point index is
+// a run-time value, so the FP32 path loads its coefficients as FP32 and
+// does not convert them at every use.
+struct TanTabF {
+    float lin[3][3][5], cand[3][3][3], linw[3][3];
+};
+constexpr TanTabF make_tan_tab_f()
+{
+    TanTabF t{};
+    for (int g = 0; g < 3; ++g)
+        for (int k = 0; k < 3; ++k) {
+            for (int r = 0; r < 5; ++r) t.lin[g][k][r] = float(kTanLin[g][k][r]);
+            for (int r = 0; r < 3; ++r) t.cand[g][k][r] = float(kTanCand[g][k][r]);
+            t.linw[g][k] = float(kTanLinW[g][k]);
+        }
+    return t;
+}
+__device__ constexpr TanTabF kTanF = make_tan_tab_f();
+
+// kTanLin[g][k][r] in type T
+template <typename T> GKS_HD T tan_lin(int g, int k, int r)
+{
+    if constexpr (std::is_same_v<T, float>) return kTanF.lin[g][k][r];
+    else return T(kTanLin[g][k][r]);
+}
+
 // 5th-order WENO-Z value at Gauss point g from rows q[0..4], as a quotient
 // num / den; the centre point's negative linear weights are split into two
 // positive groups (Shi, Hu, Shu, J. Comput. Phys. 175 (2002), theta = 3),
@@ -337,8 +364,7 @@ GKS_HD float tan_weno_f32(const float* q, int g)
     float cand[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        cand[k] = float(kTanCand[g][k][0]) * q[k] + float(kTanCand[g][k][1]) * q[k + 1] +
-                  float(kTanCand[g][k][2]) * q[k + 2];
+        cand[k] = kTanF.cand[g][k][0] * q[k] + kTanF.cand[g][k][1] * q[k + 1] + kTanF.cand[g][k][2] * q[k + 2];
     const float s0a = q[0] - 2.0f * q[1] + q[2], s0b = q[0] - 4.0f * q[1] + 3.0f * q[2];
     const float s1a = q[1] - 2.0f * q[2] + q[3], s1b = q[1] - q[3];
     const float s2a = q[2] - 2.0f * q[3] + q[4], s2b = 3.0f * q[2] - 4.0f * q[3] + q[4];
@@ -351,8 +377,7 @@ GKS_HD float tan_weno_f32(const float* q, int g)
 #pragma unroll
     for (int k = 0; k < 3; ++k) w[k] = 1.0f + Z * rcp(be[k] + eps); // alpha_k / gamma_k
     if (g != 1) {
-        const float a0 = float(kTanLinW[g][0]) * w[0], a1 = float(kTanLinW[g][1]) * w[1],
-                    a2 = float(kTanLinW[g][2]) * w[2];
+        const float a0 = kTanF.linw[g][0] * w[0], a1 = kTanF.linw[g][1] * w[1], a2 = kTanF.linw[g][2] * w[2];
         return (a0 * cand[0] + a1 * cand[1] + a2 * cand[2]) * rcp(a0 + a1 + a2);
     }
     // centre point: gamma+ = (g + 3|g|)/2, gamma- = gamma+ - g; value sp vp - sm vm
