@@ -747,8 +747,22 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
 #pragma unroll
         for (int k = 0; k < 4; ++k) { Wk[q][k] = w[k]; Dk[q][k] = d[k]; }
     }
-    const size_t Bs = row_stride(B, sizeof(T)), AB = (size_t)A * Bs, ab = (size_t)a * Bs + b;
-    auto put = [&](int q, int k, double v) { R[(q * 4 + k) * AB + ab] = T(v); };
+    // the 28 stores through a buffer resource: the lane's byte offset in a
+    // plane as the 32-bit vector offset, the plane as a scalar offset (the
+    // host guarantees row_buffer_elems(nx, ny, DIR, 8) * 8 < 2^32)
+    const unsigned Bs = (unsigned)row_stride(B, sizeof(T));
+    const unsigned rplane = (unsigned)A * Bs * (unsigned)sizeof(T);
+    const unsigned voff = ((unsigned)a * Bs + (unsigned)b) * (unsigned)sizeof(T);
+    const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)R, (short)0, (int)(unsigned)(row_buffer_elems(nx, ny, DIR, sizeof(T)) * sizeof(T)), 0x00020000);
+    auto put = [&](int q, int k, double v) {
+        const unsigned so = (unsigned)(q * 4 + k) * rplane;
+        using u32x2 = unsigned __attribute__((vector_size(8)));
+        if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rsrc, voff, so, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, T(v)), rsrc, voff, so, 0);
+    };
     const bool ok = face_recon<T, 2, ORDER, double, T>(Wk, Dk, h, P.gamma, P.recon != 0, put);
     if (!ok) S.err = 1;
 }

@@ -22,15 +22,28 @@ constexpr double kWenoEps = 1e-6;
 
 template <typename T> GKS_HD T tabs(T x) { return x < T(0) ? -x : x; }
 
-// Reciprocal.  FP64 (and any other type): a division.  FP32: the hardware
-// reciprocal v_rcp_f32 on the device (about 1 ulp), the unit roundoff of
-// the FP32 path anyway; a plain division on the host.
+// Reciprocal.  FP32: the hardware reciprocal v_rcp_f32 on the device
+// (about 1 ulp), the unit roundoff of the FP32 path anyway.  FP64 on the
+// device: v_rcp_f64 refined by two Newton-Raphson steps (r += r (1 - x r)),
+// within an ulp or so for the normal, finite, non-zero arguments the scheme
+// divides by (densities, pressures, sound speeds, sums of positive
+// indicators), at half the instructions of a correctly rounded division.
+// On the host (and for any other type): a plain division.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __host__ inline float frcp(float x) { return 1.0f / x; }
+__device__ __forceinline__ double drcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+__host__ inline double drcp(double x) { return 1.0 / x; }
 template <typename T> GKS_HD T rcp(T x) { return T(1) / x; }
 template <> GKS_HD float rcp<float>(float x) { return frcp(x); }
+template <> GKS_HD double rcp<double>(double x) { return drcp(x); }
 template <typename T> GKS_HD T quot(T a, T b) { return a / b; }
 template <> GKS_HD float quot<float>(float a, float b) { return a * frcp(b); }
+template <> GKS_HD double quot<double>(double a, double b) { return a * drcp(b); }
 // Type of the time-integration coefficients: FP64 when the point is
 // evaluated in FP32 (their formulas cancel for tau_n comparable to dt).
 template <typename D> using ExpT = std::conditional_t<std::is_same_v<D, float>, double, D>;
@@ -398,7 +411,7 @@ GKS_HD void tan_weno_pair(const T* ql, const T* qr, int g, T& vl, T& vr)
     T nl, dl, nr, dr;
     tan_weno_frac<T>(ql, g, nl, dl);
     tan_weno_frac<T>(qr, g, nr, dr);
-    const T r = T(1) / (dl * dr);
+    const T r = rcp(dl * dr);
     vl = nl * dr * r;
     vr = nr * dl * r;
 }
@@ -619,7 +632,7 @@ template <typename T> GKS_HD bool physical(const T* W, T gamma, int dim)
 template <typename D>
 GKS_HD void exp_fit(D tau_n, D dt, D idt, D& ke, D& kte, D& kde, D& kdte)
 {
-    const D x2 = dt / tau_n, x1 = D(0.5) * x2;
+    const D x2 = dt * rcp(tau_n), x1 = D(0.5) * x2;
     // e^{-x2} = (e^{-x1})^2 and 1 - e^{-x2} = (1 - e^{-x1})(1 + e^{-x1})
     const D q1 = exp(-x1), q2 = q1 * q1;
     const D om1 = -expm1(-x1), om2 = om1 * (D(1) + q1); // 1 - e^{-x}
