@@ -16,6 +16,10 @@ Other modes (reports, not the headline line):
   --workload riemann2d  2-D four-quadrant Euler Riemann problem, 4096^2
   --study equal-l1      L1(rho) and throughput of both precisions over
                         N = 128..1024 against an FP64 2048^2 reference
+                        (the vortex, or with --workload riemann2d the
+                        four-quadrant problem)
+  --workload cpu-configs  the oracle's rates on bounded samples of each
+                        workload, all host threads and one (no GPU)
 """
 import argparse
 import hashlib
@@ -47,7 +51,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=0, help="cells per direction (2-D workloads)")
-    ap.add_argument("--workload", choices=["vortex2d", "batch1d", "riemann2d"], default="vortex2d")
+    ap.add_argument("--workload", choices=["vortex2d", "batch1d", "riemann2d", "cpu-configs"], default="vortex2d",
+                    help="cpu-configs: the oracle's rates on bounded samples of each workload (no GPU)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--study", choices=["none", "equal-l1"], default="none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -246,6 +251,23 @@ def hbm_step(value):
             "frac": gbps / HBM_PEAK}
 
 
+def step_roof(value, ops, prec, mu):
+    """Step-level roofline: T_bound = max(B_alg / 8 TB/s, F_alg / vector
+    peak) per cell-update against the measured time per cell-update, with
+    F_alg = 2 directions x (2 stages x face row + 3 Gauss points x (stage-1
+    + stage-2 point)) from the operation counts (the cell update's ~100
+    flops left out) and the vector peak of the precision's executed mix."""
+    key = "gauss_point_ns" if mu > 0 else "gauss_point_euler"
+    f_alg = 2 * (2 * ops["face_row_2d"]["flops"] + 3 * (ops[key]["flops"] + ops[key + "_s2"]["flops"]))
+    peak, basis = valu_peak(prec)
+    t_alu = f_alg / (peak * 1e12)
+    t_hbm = STEP_BYTES_2D / (HBM_PEAK * 1e9)
+    t_meas = 1.0 / value
+    return {"flops_per_cell_update": f_alg, "bytes_per_cell_update": STEP_BYTES_2D, "peak_TFLOPs": peak,
+            "peak_basis": basis, "t_bound_ns": max(t_alu, t_hbm) * 1e9, "t_meas_ns": t_meas * 1e9,
+            "bound": "alu" if t_alu >= t_hbm else "hbm", "frac": max(t_alu, t_hbm) / t_meas}
+
+
 def load_ops():
     return json.load(open(os.path.join(ROOT, "paper_1901_00261_amd", "opcount.json")))
 
@@ -283,6 +305,7 @@ def bench_vortex(args):
                    "ms_per_step_with_kernel_events": res["elapsed_events"] / args.steps * 1e3},
         "roofline": roof,
         "hbm_step": hbm_step(value),
+        "step_roof": step_roof(value, ops, main_p, prob.mu),
     }
     if 1 in results and main_p == 0:
         rm = results[1]
@@ -290,6 +313,7 @@ def bench_vortex(args):
         line["config"]["mixed"] = {
             "value": vm, "ms_per_step": rm["elapsed"] / args.steps * 1e3, "speedup_vs_fp64": vm / value,
             "hbm_step": hbm_step(vm),
+            "step_roof": step_roof(vm, ops, 1, prob.mu),
             "kernel_ms_per_step": {k: v[0] / args.steps for k, v in rm["kernels"].items()},
             "ms_per_step_with_kernel_events": rm["elapsed_events"] / args.steps * 1e3,
             "roofline": roofline_2d(prob, rm, ops, 1)}
@@ -315,7 +339,8 @@ def bench_riemann2d(args):
         out["fp64" if p == 0 else "mixed"] = {
             "value": n * n * args.steps / r["elapsed"], "ms_per_step": r["elapsed"] / args.steps * 1e3, "ok": r["ok"],
             "t_reached": r["t_after"], "kernel_ms_per_step": {k: v[0] / args.steps for k, v in r["kernels"].items()},
-            "roofline": roofline_2d(prob, r, ops, p)}
+            "roofline": roofline_2d(prob, r, ops, p),
+            "step_roof": step_roof(n * n * args.steps / r["elapsed"], ops, p, prob.mu)}
     return out
 
 
@@ -372,6 +397,46 @@ def bench_batch1d(args):
                                                      "unit": "TFLOP/s", "frac": achieved / peak}}
             S.close()
         out["fp64" if p == 0 else "mixed"] = rec
+    return out
+
+
+def cpu_configs(args):
+    """The oracle's own rate on bounded samples of each workload, on all host
+    threads and on one (a reported baseline, not the target): the 1-D sine
+    (full run), the first problems of the seeded Riemann set (full runs), a
+    window of the vortex (one step), problems of the uneven batch (their
+    first steps) and the four-quadrant problem at 256^2 (a few steps)."""
+    import oracle
+    from paper_1901_00261_amd import workloads as wl
+    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+    def timed(probs, threads, **over):
+        oracle.set_threads(threads)
+        upd, t0 = 0, time.perf_counter()
+        for p in probs:
+            r = oracle.run(p.dim, p.W, p.Wx, p.Wy, **{**p.oracle_kwargs(), **over})
+            upd += p.nx * (p.ny if p.dim == 2 else 1) * r[4]
+        el = time.perf_counter() - t0
+        return {"value": upd / el, "cell_updates": upd, "seconds": el, "cores": threads}
+
+    batch = wl.batch_1d()
+    legs = {
+        "sine 1-D N=80, 6th linear, full run to t=2": (lambda: [wl.sine_wave_1d(80, order=6, recon=0)], {}, {}),
+        "Riemann set N=400, 8th WENO-Z, full runs (problems 0-3 / 0)": (
+            lambda: wl.riemann_set_1d(4, n=400), {}, {"one": lambda: wl.riemann_set_1d(1, n=400)}),
+        "uneven batch, problems 0-7, first 40 steps": (lambda: batch[:8], {"max_steps": 40},
+                                                       {"one": lambda: batch[:2]}),
+        "four-quadrant Riemann 256^2, 8th WENO-Z, 4 steps / 1 step": (
+            lambda: [wl.riemann_2d(256, seed=5, order=8, recon=1, cfl=0.3)], {"max_steps": 4},
+            {"over1": {"max_steps": 1}}),
+    }
+    out = {"cpu_model": cpu_model(), "threads": nthreads, "unit": "cell-updates/s", "legs": {}}
+    for name, (mk, over, one) in legs.items():
+        rec = {"all_threads": timed(mk(), nthreads, **over)}
+        rec["one_thread"] = timed(one.get("one", mk)(), 1, **one.get("over1", over))
+        out["legs"][name] = rec
+        print(name, json.dumps(rec), file=sys.stderr, flush=True)
+    oracle.set_threads(nthreads)
     return out
 
 
@@ -466,6 +531,9 @@ def main():
         print("bench.py: measures the single-GPU path only; --gpus must be 1 "
               "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "cpu-configs":
+        print(json.dumps(cpu_configs(args)), flush=True)
+        return
     import torch
 
     if args.copy_probe_mib:
