@@ -195,39 +195,11 @@ GKS_HD void weno_right(const T* w, const T* d, T& val, T& der)
 
 // ---------------------------------------------------------------------------
 // Euler eigenvectors in the normal direction (slot 1 = normal velocity),
-// closed form.  R: right eigenvectors as columns, L = R^{-1}.
+// closed form, from six scalars; entries are rebuilt on demand (keeps two
+// 4x4 matrices out of the registers while the WENO-Z runs).  R: right
+// eigenvectors as columns (acoustic-, entropy, shear (2-D), acoustic+),
+// L = R^{-1}.
 // ---------------------------------------------------------------------------
-template <typename T, int DIM>
-GKS_HD bool char_frame(const T* W, T gamma, T R[4][4], T L[4][4])
-{
-    const T rho = W[0];
-    const T U = W[1] / rho, V = (DIM == 2) ? W[2] / rho : T(0);
-    const T q2 = U * U + V * V;
-    const T p = (gamma - T(1)) * (W[3] - T(0.5) * rho * q2);
-    if (!(rho > T(0)) || !(p > T(0))) return false;
-    const T c = sqrt(gamma * p / rho);
-    const T H = (W[3] + p) / rho;
-    const T b1 = (gamma - T(1)) / (c * c);
-    const T b2 = T(0.5) * q2 * b1;
-    const T ic = T(1) / c;
-    for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) { R[a][b] = T(0); L[a][b] = T(0); }
-    // columns: acoustic-, entropy, shear (2-D), acoustic+
-    R[0][0] = T(1); R[1][0] = U - c; R[2][0] = V; R[3][0] = H - U * c;
-    R[0][1] = T(1); R[1][1] = U;     R[2][1] = V; R[3][1] = T(0.5) * q2;
-    R[0][3] = T(1); R[1][3] = U + c; R[2][3] = V; R[3][3] = H + U * c;
-    L[0][0] = T(0.5) * (b2 + U * ic); L[0][1] = T(-0.5) * (b1 * U + ic); L[0][2] = T(-0.5) * b1 * V; L[0][3] = T(0.5) * b1;
-    L[1][0] = T(1) - b2;              L[1][1] = b1 * U;                  L[1][2] = b1 * V;              L[1][3] = -b1;
-    L[3][0] = T(0.5) * (b2 - U * ic); L[3][1] = T(-0.5) * (b1 * U - ic); L[3][2] = T(-0.5) * b1 * V; L[3][3] = T(0.5) * b1;
-    if constexpr (DIM == 2) {
-        R[2][2] = T(1); R[3][2] = V;
-        L[2][0] = -V; L[2][2] = T(1);
-    }
-    return true;
-}
-
-// The same eigenvectors from six scalars, entries rebuilt on demand (keeps
-// two 4x4 matrices out of the registers while the WENO-Z runs).
 template <typename T, int DIM>
 struct CharFrame {
     T U, V, c, H, b1, b2, ic;
