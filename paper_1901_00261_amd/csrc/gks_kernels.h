@@ -239,29 +239,34 @@ __device__ __forceinline__ void tile_xy(int gx, int& tx, int& ty)
 template <typename T, int DIM, int ORDER, typename D = double, typename F = D, typename Emit>
 GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, bool weno, Emit&& emit)
 {
+    // outputs in O: FP32 when the frame is FP32 (the FP32-mixed path stores
+    // them as FP32), otherwise D
+    using O = std::conditional_t<std::is_same_v<F, float>, float, D>;
     const D ih = D(1) / h;
+    const O iho = O(ih);
     // offsets from the cell left of the face keep the differences exact
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (DIM == 1 && k == 2) {
 #pragma unroll
-            for (int q = 0; q < 7; ++q) emit(q, k, D(0));
+            for (int q = 0; q < 7; ++q) emit(q, k, O(0));
             continue;
         }
         const D base = Wk[1][k];
+        const O baseo = O(base);
         T w[4], d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) { w[q] = T(Wk[q][k] - base); d[q] = T(Dk[q][k]); }
         T v, vx, vxx;
         linear_recon<T, ORDER>(w, d, v, vx, vxx);
-        emit(0, k, base + D(v));
-        emit(1, k, D(vx) * ih);
-        emit(2, k, D(vxx) * ih * ih);
+        emit(0, k, baseo + O(v));
+        emit(1, k, O(vx) * iho);
+        emit(2, k, O(vxx) * iho * iho);
         if (!weno) {
-            emit(3, k, base + D(v));
-            emit(4, k, base + D(v));
-            emit(5, k, D(vx) * ih);
-            emit(6, k, D(vx) * ih);
+            emit(3, k, baseo + O(v));
+            emit(4, k, baseo + O(v));
+            emit(5, k, O(vx) * iho);
+            emit(6, k, O(vx) * iho);
         }
     }
     if (!weno) return true;
@@ -299,21 +304,21 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
     fr.right(qr, Wrf);
     fr.right(qlx, Wlxf);
     fr.right(qrx, Wrxf);
-    D Wl[4], Wr[4], Wlx[4], Wrx[4];
+    O Wl[4], Wr[4], Wlx[4], Wrx[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        Wl[k] = D(Wlf[k]) + Wk[1][k];
-        Wr[k] = D(Wrf[k]) + Wk[1][k];
-        Wlx[k] = D(Wlxf[k]);
-        Wrx[k] = D(Wrxf[k]);
+        Wl[k] = O(Wlf[k]) + O(Wk[1][k]);
+        Wr[k] = O(Wrf[k]) + O(Wk[1][k]);
+        Wlx[k] = O(Wlxf[k]);
+        Wrx[k] = O(Wrxf[k]);
     }
-    const bool okl = physical<D>(Wl, gamma, DIM), okr = physical<D>(Wr, gamma, DIM);
+    const bool okl = physical<O>(Wl, O(gamma), DIM), okr = physical<O>(Wr, O(gamma), DIM);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        emit(3, k, okl ? Wl[k] : Wk[1][k]);
-        emit(4, k, okr ? Wr[k] : Wk[2][k]);
-        emit(5, k, Wlx[k] * ih);
-        emit(6, k, Wrx[k] * ih);
+        emit(3, k, okl ? Wl[k] : O(Wk[1][k]));
+        emit(4, k, okr ? Wr[k] : O(Wk[2][k]));
+        emit(5, k, Wlx[k] * iho);
+        emit(6, k, Wrx[k] * iho);
     }
     return true;
 }
@@ -423,7 +428,7 @@ __global__ void __launch_bounds__(kCompactThreads) compact_items_kernel(const Pr
 // problem's last face) carry the MSMD partial Pf from stage 1 to stage 2.
 // ---------------------------------------------------------------------------
 template <typename T, int STAGE, int BLK>
-__global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+__global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
                                                       Tile* items, int* nitems_p,
                                                       unsigned* __restrict__ ctr, double* __restrict__ W,
                                                       double* __restrict__ Wx, double* __restrict__ PW,
@@ -515,7 +520,7 @@ __global__ void __launch_bounds__(BLK) stage1d_kernel(const ProbParam* __restric
             // face reconstruction emitted in T (the FP32-mixed path stores
             // and evaluates the interface point in FP32)
             T o[7][4];
-            auto put = [&](int q, int k, double v) { o[q][k] = T(v); };
+            auto put = [&](int q, int k, auto v) { o[q][k] = T(v); };
             bool ok = gok && ((P.order == 8) ? face_recon<T, 1, 8, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
                                              : face_recon<T, 1, 6, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put));
             PointIn<T> in;
@@ -755,11 +760,11 @@ __global__ void __launch_bounds__(256) row2d_kernel(const ProbParam* __restrict_
     const unsigned voff = ((unsigned)a * Bs + (unsigned)b) * (unsigned)sizeof(T);
     const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)R, (short)0, (int)(unsigned)(row_buffer_elems(nx, ny, DIR, sizeof(T)) * sizeof(T)), 0x00020000);
-    auto put = [&](int q, int k, double v) {
+    auto put = [&](int q, int k, auto v) {
         const unsigned so = (unsigned)(q * 4 + k) * rplane;
         using u32x2 = unsigned __attribute__((vector_size(8)));
         if constexpr (sizeof(T) == 8)
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rsrc, voff, so, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, double(v)), rsrc, voff, so, 0);
         else
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, T(v)), rsrc, voff, so, 0);
     };
