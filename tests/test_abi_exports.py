@@ -90,6 +90,37 @@ def test_host_validation_without_gpu():
     st, msg = init([q], arrays)
     assert st == gks.GKS_EINVAL and "paired" in msg
     assert L.gks_step(None, 1, None) == gks.GKS_EINVAL
+    # boundary kinds of Sec. 4: split sides are 2-D only, characteristic
+    # ends 1-D only, inflow and split states must be physical, a split side
+    # needs a wall or a second inflow beyond its switch and a finite switch
+    q = wl.sine_wave_1d(16)
+    q.bc = (4, 1, 0, 0)
+    st, msg = init([q], arrays)
+    assert st == gks.GKS_EINVAL and "2-D only" in msg
+    v = wl.pulse_box_2d(8, bc=(5, 5, 2, 2))
+    va = [(v.W, v.Wx, v.Wy)]
+    st, msg = init([v], va)
+    assert st == gks.GKS_EINVAL and "1-D only" in msg
+    q = wl.sine_wave_1d(16)
+    q.bc = (3, 1, 0, 0)
+    q.bc_state = np.zeros((4, 2, 4))  # zero density
+    st, msg = init([q], arrays)
+    assert st == gks.GKS_EINVAL and "non-physical boundary state" in msg
+    v = wl.double_mach_2d(16, 4)
+    va = [(v.W, v.Wx, v.Wy)]
+    v.bc_beyond = (2, 2, 1, 3)
+    st, msg = init([v], va)
+    assert st == gks.GKS_EINVAL and "bc_beyond" in msg
+    v = wl.double_mach_2d(16, 4)
+    v.bc_split = v.bc_split.copy()
+    v.bc_split[3, 1] = float("inf")
+    st, msg = init([v], va)
+    assert st == gks.GKS_EINVAL and "finite" in msg
+    v = wl.double_mach_2d(16, 4)
+    v.bc_state = v.bc_state.copy()
+    v.bc_state[3, 1, 3] = 0.0  # second top state with negative pressure
+    st, msg = init([v], va)
+    assert st == gks.GKS_EINVAL and "non-physical boundary state" in msg
     import torch
     if not torch.cuda.is_available():
         st, msg = init([p], arrays)
