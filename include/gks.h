@@ -69,8 +69,9 @@ enum { GKS_PREC_FP64 = 0, GKS_PREC_FP32_MIXED = 1 };
 /* One problem (Sec. 2 and Sec. 4 of the paper).
    dim: 1 or 2.  nx, ny: interior cells (ny = 1 when dim == 1), at least 4.
    gamma > 1.  mu >= 0 dynamic viscosity (0: Euler); collision times follow
-   Sec. 4 (tau = mu/p for the viscous terms, tau_n = eps dt or mu/p plus the
-   pressure-jump term in the exponentials).  cfl > 0 sets
+   Sec. 4: the viscous terms take mu/p (0 for Euler) plus the pressure-jump
+   term |p_l - p_r| / (p_l + p_r) dt, the exponentials eps dt (Euler,
+   eps = 0.01) or mu/p plus the same jump term.  cfl > 0 sets
    dt = cfl * min over cells of dx/(|U|+c) [and dy/(|V|+c)] unless
    dt_fixed > 0.  The last step is shortened so the problem ends exactly at
    t_end.  order: 6 or 8.  recon: GKS_RECON_*.  bc: x-low, x-high, y-low,
