@@ -39,9 +39,9 @@ import oracle  # noqa: E402
 from paper_1901_00261_amd import workloads as wl  # noqa: E402
 
 
-def _run(p, **over):
+def _run(p, W=None, Wx=None, Wy=None, **over):
     kw = {**p.oracle_kwargs(), **over}
-    return oracle.run(p.dim, p.W, p.Wx, p.Wy, **kw)
+    return oracle.run(p.dim, p.W if W is None else W, p.Wx if Wx is None else Wx, p.Wy if Wy is None else Wy, **kw)
 
 
 def _nonphysical(W, gamma):
@@ -83,12 +83,33 @@ def _sample_2d(W, Wx, Wy, stride, block):
     return dict(rows=rows, cols=cols, W=W[sl], Wx=Wx[sl], Wy=Wy[sl], sums=W.sum(axis=(0, 1)))
 
 
-def riemann2d():
+CHECKPOINT = os.environ.get("GKS_GOLDEN_CHECKPOINT", "")
+
+
+def riemann2d(steps=500, chunk=25):
+    """The run goes in chunks of `chunk` steps, each continuing from the
+    previous state and time (the oracle sizes every step from the state it
+    starts from, so the chunks give the uninterrupted run); with
+    GKS_GOLDEN_CHECKPOINT=<file> the state after each chunk is saved there
+    and a later call resumes from it."""
     p = wl.riemann_2d(256, seed=5, order=8, recon=1, cfl=0.3)
-    W, Wx, Wy, t, n = _run(p, max_steps=500)
-    print(f"riemann2d 256: t={t:.6f} steps={n} fallbacks={oracle.fallbacks()}", flush=True)
+    W, Wx, Wy, t, n, fb = p.W, p.Wx, p.Wy, 0.0, 0, 0
+    if CHECKPOINT and os.path.exists(CHECKPOINT):
+        c = np.load(CHECKPOINT)
+        W, Wx, Wy, t, n, fb = c["W"], c["Wx"], c["Wy"], float(c["t"]), int(c["n"]), int(c["fb"])
+        print(f"riemann2d 256: resuming at step {n}, t={t:.6f}", flush=True)
+    while n < steps:
+        m = min(chunk, steps - n)
+        W, Wx, Wy, t, k = _run(p, W=W, Wx=Wx, Wy=Wy, t0=t, max_steps=m)
+        assert k == m
+        n += k
+        fb += oracle.fallbacks()
+        print(f"riemann2d 256: step {n}, t={t:.6f}", flush=True)
+        if CHECKPOINT:
+            np.savez(CHECKPOINT, W=W, Wx=Wx, Wy=Wy, t=t, n=n, fb=fb)
+    print(f"riemann2d 256: t={t:.6f} steps={n} fallbacks={fb}", flush=True)
     out = _sample_2d(W, Wx, Wy, 8, ((116, 140), (116, 140)))
-    out.update(t=t, nsteps=n, fallbacks=oracle.fallbacks())
+    out.update(t=t, nsteps=n, fallbacks=fb)
     return out
 
 
