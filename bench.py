@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=0, help="cells per direction (2-D workloads)")
     ap.add_argument("--workload", choices=["vortex2d", "batch1d", "riemann2d", "cpu-configs"], default="vortex2d",
-                    help="cpu-configs: the oracle's rates on bounded samples of each workload (no GPU)")
+                    help="cpu-configs: the CPU-baseline leg (the oracle) on bounded samples of each workload (no GPU)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--study", choices=["none", "equal-l1"], default="none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -400,9 +400,10 @@ def bench_batch1d(args):
     return out
 
 
-def cpu_configs(args):
-    """The oracle's own rate on bounded samples of each workload, on all host
-    threads and on one (a reported baseline, not the target): the 1-D sine
+def cpu_baseline_configs(args):
+    """The CPU-baseline leg on every workload: the oracle's own rate on
+    bounded samples, on all host threads and on one (a reported baseline,
+    not the target): the 1-D sine
     (full run), the first problems of the seeded Riemann set (full runs), a
     window of the vortex (one step), problems of the uneven batch (their
     first steps) and the four-quadrant problem at 256^2 (a few steps)."""
@@ -532,7 +533,7 @@ def main():
               "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "cpu-configs":
-        print(json.dumps(cpu_configs(args)), flush=True)
+        print(json.dumps(cpu_baseline_configs(args)), flush=True)
         return
     import torch
 
