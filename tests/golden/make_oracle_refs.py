@@ -84,6 +84,7 @@ def _sample_2d(W, Wx, Wy, stride, block):
 
 
 CHECKPOINT = os.environ.get("GKS_GOLDEN_CHECKPOINT", "")
+MAX_CHUNKS = int(os.environ.get("GKS_GOLDEN_MAX_CHUNKS", "0"))  # > 0: stop after that many chunks
 
 
 def riemann2d(steps=500, chunk=25):
@@ -91,14 +92,20 @@ def riemann2d(steps=500, chunk=25):
     previous state and time (the oracle sizes every step from the state it
     starts from, so the chunks give the uninterrupted run); with
     GKS_GOLDEN_CHECKPOINT=<file> the state after each chunk is saved there
-    and a later call resumes from it."""
+    and a later call resumes from it; GKS_GOLDEN_MAX_CHUNKS=<k> ends a call
+    after k chunks (nothing is written until the run is complete)."""
     p = wl.riemann_2d(256, seed=5, order=8, recon=1, cfl=0.3)
     W, Wx, Wy, t, n, fb = p.W, p.Wx, p.Wy, 0.0, 0, 0
     if CHECKPOINT and os.path.exists(CHECKPOINT):
         c = np.load(CHECKPOINT)
         W, Wx, Wy, t, n, fb = c["W"], c["Wx"], c["Wy"], float(c["t"]), int(c["n"]), int(c["fb"])
         print(f"riemann2d 256: resuming at step {n}, t={t:.6f}", flush=True)
+    done = 0
     while n < steps:
+        if MAX_CHUNKS and done == MAX_CHUNKS:
+            print(f"riemann2d 256: stopping after {done} chunks at step {n}", flush=True)
+            return None
+        done += 1
         m = min(chunk, steps - n)
         W, Wx, Wy, t, k = _run(p, W=W, Wx=Wx, Wy=Wy, t0=t, max_steps=m)
         assert k == m
@@ -130,6 +137,8 @@ def main(names):
     for name in names or JOBS:
         t0 = time.time()
         res = JOBS[name]()
+        if res is None:
+            continue
         np.savez_compressed(os.path.join(HERE, name + ".npz"), **res)
         print(f"{name}: written in {time.time() - t0:.0f} s", flush=True)
 
