@@ -59,7 +59,14 @@ struct gks_handle {
     int* dCount[3] = {nullptr, nullptr, nullptr};
     Tile* dAct[3] = {nullptr, nullptr, nullptr};  // items of the active problems (rebuilt every step)
     int* dNact = nullptr;
-    int act_blk = -1; // tile size the device work list was last built for (-1: stale)
+    int act_list = -1; // item list (index) the device work list was last built from (-1: stale)
+    std::vector<int> hcount[3]; // per problem: items of each tile size (host copy)
+    std::vector<char> last_active; // problem still running after the last gks_step (host copy)
+    // lane-pair steps: while the active work items of the tuned tile size
+    // are fewer than the CUs, the steps run the 256-thread kernel whose lane
+    // pairs share a face, on tiles of 127 cells (GKS_SPLIT: 0 never,
+    // 1 automatic (default), 2 always)
+    int split = 0, split_mode = 1;
     int ncu = 256;
     // launch configuration (autotuned): threads per tile, workgroups per CU
     // (0: one workgroup per work item)
@@ -220,25 +227,36 @@ void harvest(gks_handle* h)
 
 // the device work list for the current tile size, rebuilt from the problem
 // states when it is stale (first step, tile size changed, state restored)
+// item list of the current launch shape: the tuned tile size, or the
+// 127-cell tiles of the lane-pair kernel
+int list_index(const gks_handle* h)
+{
+    return h->split ? 1 : (h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2));
+}
+
 void ensure_work_list(gks_handle* h, hipStream_t st)
 {
-    if (h->act_blk == h->blk) return;
-    const int b = h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2);
+    const int b = list_index(h);
+    if (h->act_list == b) return;
     gks::compact_items_kernel<<<1, gks::kCompactThreads, 0, st>>>(h->dS, h->nprob, h->dItems[b], h->dFirst[b],
                                                                   h->dCount[b], h->dAct[b], h->dNact);
-    h->act_blk = h->blk;
+    h->act_list = b;
 }
 
 template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
 {
-    const int b = h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2);
+    const int b = list_index(h);
     const int n = h->nItems[b];
     ensure_work_list(h, st);
     Tile* it = h->dAct[b];
     int* na = h->dNact;
     const int G = h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu);
     record(h, st, 0, true);
-    if (h->blk == 64) {
+    if (h->split) {
+        const int Gs = std::min(n, std::max(1, h->gmul) * h->ncu);
+        gks::stage1d_kernel<T, 1, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+        gks::stage1d_kernel<T, 2, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+    } else if (h->blk == 64) {
         gks::stage1d_kernel<T, 1, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
         gks::stage1d_kernel<T, 2, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
     } else if (h->blk == 128) {
@@ -250,7 +268,7 @@ template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
     }
     record(h, st, 0, false);
     // the last workgroup of the second stage commits the step and rebuilds the work list
-    h->act_blk = h->blk;
+    h->act_list = b;
 }
 
 template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
@@ -469,9 +487,9 @@ int autotune(gks_handle* h)
             st = fail(h, GKS_EDEVICE, "autotune: state restore failed");
             break;
         }
-        h->act_blk = -1; // the work list reflects the tuning steps, not the restored state
+        h->act_list = -1; // the work list reflects the tuning steps, not the restored state
     }
-    h->act_blk = -1;
+    h->act_list = -1;
     h->timing = was_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -623,6 +641,8 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
             h->ncu = ncu;
     }
     if (const char* g = getenv("GKS_GRAPH")) h->use_graph = atoi(g) != 0;
+    if (const char* g = getenv("GKS_SPLIT")) h->split_mode = std::min(std::max(atoi(g), 0), 2);
+    h->last_active.assign(nprob, 1);
     TRY(([&]() -> int {
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         if (dim == 2) {
@@ -646,6 +666,7 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
                 count[p] = (int)items.size() - first[p];
             }
             h->nItems[b] = (int)items.size();
+            h->hcount[b] = count;
             TRY(([&]() -> int {
                 HIP_TRY(h, dalloc(&h->dItems[b], items.size()));
                 HIP_TRY(h, dalloc(&h->dAct[b], items.size()));
@@ -861,6 +882,22 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
         const int st = autotune(h);
         if (st) return st;
     }
+    if (h->dim == 1 && h->tuned) {
+        // lane-pair steps while the work items of the tuned tile size still
+        // running (known from the last call) are fewer than the CUs
+        int want = h->split_mode == 2;
+        if (h->split_mode == 1) {
+            const int bn = h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2);
+            long long items = 0;
+            for (int p = 0; p < h->nprob; ++p)
+                if (h->last_active[p]) items += h->hcount[bn][p];
+            want = items < h->ncu;
+        }
+        if (want != h->split) {
+            h->split = want;
+            drop_graph(h);
+        }
+    }
     const bool graph = h->use_graph && !h->timing && max_steps > 0;
     if (graph && !h->gexec) {
         const int st = build_graph(h);
@@ -881,6 +918,7 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
     long long upd = 0;
     for (int p = 0; p < h->nprob; ++p) {
         active += after[p].active;
+        h->last_active[p] = after[p].active ? 1 : 0;
         if (after[p].err && !before[p].err && bad < 0) bad = p;
         upd += (after[p].nsteps - before[p].nsteps) * (long long)h->hp[p].nx * h->hp[p].ny;
     }
@@ -989,9 +1027,10 @@ const char* gks_launch_config(const gks_handle* hc)
         h->cfg_text = "1-D: not tuned yet (tunes on the first gks_step)";
     } else {
         const int n = h->nItems[h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2)];
-        char buf[128];
-        snprintf(buf, sizeof buf, "; blk %d gmul %d: %d workgroups for %d work items", h->blk, h->gmul,
-                 h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu), n);
+        char buf[192];
+        snprintf(buf, sizeof buf, "; blk %d gmul %d: %d workgroups for %d work items; lane-pair steps %s (%s)",
+                 h->blk, h->gmul, h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu), n, h->split ? "on" : "off",
+                 h->split_mode == 0 ? "never" : (h->split_mode == 2 ? "always" : "while items < CUs"));
         h->cfg_text = h->tune_note + buf;
     }
     return h->cfg_text.c_str();

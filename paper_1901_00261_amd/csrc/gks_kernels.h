@@ -236,8 +236,16 @@ __device__ __forceinline__ void tile_xy(int gx, int& tx, int& ty)
 // arithmetic (on differences from the cell left of the face, formed in D);
 // F the characteristic frame and the projections (FP32 in the mixed path).
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, int ORDER, typename D = double, typename F = D, typename Emit>
-GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, bool weno, Emit&& emit)
+// SPLIT = 2: a lane pair shares the face; the lane of the given side (0: the
+// left state, 1: the right state, as the left state of the mirrored stencil)
+// runs the WENO-Z of its side only and takes the other side from its
+// partner.  SPLIT = 1: one lane runs both sides; in FP32 the same way, the
+// inputs and results of each side's WENO-Z passed through opaque(), as the
+// lane pair passes them through its exchange, so that the two forms round
+// alike (the FP64 forms round alike without it).  SPLIT = 0: one lane, no
+// such barrier.
+template <typename T, int DIM, int ORDER, typename D = double, typename F = D, int SPLIT = 0, typename Emit>
+GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, bool weno, Emit&& emit, int side = 0)
 {
     // outputs in O: FP32 when the frame is FP32 (the FP32-mixed path stores
     // them as FP32), otherwise D
@@ -295,8 +303,44 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
             d[q] = T(sd);
         }
         T vl, dl, vr, dr;
-        weno_left<T, ORDER>(w, d, vl, dl);
-        weno_right<T, ORDER>(w, d, vr, dr);
+        if constexpr (SPLIT == 0 || (SPLIT == 1 && sizeof(T) == 8)) {
+            weno_left<T, ORDER>(w, d, vl, dl);
+            weno_right<T, ORDER>(w, d, vr, dr);
+        } else if constexpr (SPLIT == 1) {
+            // weno_right(w, d) is weno_left of the mirrored stencil with
+            // the derivative negated
+            T wa[4], da[4], wb[4], db[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                wa[q] = opaque(w[q]);
+                da[q] = opaque(d[q]);
+                wb[q] = opaque(w[3 - q]);
+                db[q] = opaque(-d[3 - q]);
+            }
+            T va, ea, vb, eb;
+            weno_left<T, ORDER>(wa, da, va, ea);
+            weno_left<T, ORDER>(wb, db, vb, eb);
+            vl = opaque(va);
+            dl = opaque(ea);
+            vr = opaque(vb);
+            dr = -opaque(eb);
+        } else {
+            T ws[4], ds[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ws[q] = opaque32(side ? w[3 - q] : w[q]);
+                ds[q] = opaque32(side ? -d[3 - q] : d[q]);
+            }
+            T v, dd;
+            weno_left<T, ORDER>(ws, ds, v, dd);
+            v = opaque32(v);
+            dd = opaque32(dd);
+            const T pv = pair_swap(v), pd = pair_swap(dd);
+            vl = side ? pv : v;
+            dl = side ? pd : dd;
+            vr = side ? v : pv;
+            dr = -(side ? dd : pd);
+        }
         ql[a] = F(vl); qlx[a] = F(dl); qr[a] = F(vr); qrx[a] = F(dr);
     }
     F Wlf[4], Wrf[4], Wlxf[4], Wrxf[4];
@@ -427,7 +471,7 @@ __global__ void __launch_bounds__(kCompactThreads) compact_items_kernel(const Pr
 // list for the next step, so a step is two launches.  Faces owned by the tile (all but its last face, plus the
 // problem's last face) carry the MSMD partial Pf from stage 1 to stage 2.
 // ---------------------------------------------------------------------------
-template <typename T, int STAGE, int BLK>
+template <typename T, int STAGE, int BLK, int SPLIT = 1>
 __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
                                                       Tile* items, int* nitems_p,
                                                       unsigned* __restrict__ ctr, double* __restrict__ W,
@@ -486,8 +530,12 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
                 }
             }
         }
-        // ---- faces c0 .. c0 + BLK - 1
-        const int f = tl.start + t;
+        // ---- faces c0 .. c0 + NF - 1 (NF = BLK / SPLIT: with SPLIT = 2 the
+        // lanes 2j and 2j + 1 share face j, one WENO-Z side and one
+        // non-equilibrium state each)
+        constexpr int NF = BLK / SPLIT;
+        const int j = t / SPLIT, side = t % SPLIT;
+        const int f = tl.start + j;
         if (f <= P.nx) {
             const double* Wb = W + (size_t)rd * 3 * Ntot + P.coff;
             const double* Xb = Wx + (size_t)rd * 3 * Ntot + P.coff;
@@ -521,8 +569,8 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
             // and evaluates the interface point in FP32)
             T o[7][4];
             auto put = [&](int q, int k, auto v) { o[q][k] = T(v); };
-            bool ok = gok && ((P.order == 8) ? face_recon<T, 1, 8, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
-                                             : face_recon<T, 1, 6, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put));
+            bool ok = gok && ((P.order == 8) ? face_recon<T, 1, 8, double, T, SPLIT>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put, side)
+                                             : face_recon<T, 1, 6, double, T, SPLIT>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put, side));
             PointIn<T> in;
             PointOut<T> out;
             NonEq<T, 1, T> ne;
@@ -535,8 +583,57 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
                     in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
                     in.Wly[k] = in.Wry[k] = T(0);
                 }
-                ok = noneq_states<T, 1, T>(o[3], o[4], T(P.gamma), T(P.K), T(par.iN), ne, in.Wlx, in.Wly, in.Wrx,
-                                           in.Wry);
+                if constexpr (SPLIT == 1 && sizeof(T) == 8) {
+                    ok = noneq_states<T, 1, T>(o[3], o[4], T(P.gamma), T(P.K), T(par.iN), ne, in.Wlx, in.Wly, in.Wrx,
+                                               in.Wry);
+                } else if constexpr (SPLIT == 1) {
+                    // both states on this lane, their inputs, shares and
+                    // sides passed through opaque() as the lane pair passes
+                    // them through its exchange
+                    T Wa[4], Wb[4], Na[4], Nb[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        Wa[k] = opaque(o[3][k]); Wb[k] = opaque(o[4][k]);
+                        Na[k] = opaque(in.Wlx[k]); Nb[k] = opaque(in.Wrx[k]);
+                    }
+                    NeSide<T, 1, T> l, r;
+                    const bool okl = noneq_side<T, 1, T>(Wa, opaque(0), T(P.gamma), T(P.K), T(par.iN), l, Na, in.Wly);
+                    const bool okr = noneq_side<T, 1, T>(Wb, opaque(1), T(P.gamma), T(P.K), T(par.iN), r, Nb, in.Wry);
+                    ok = okl && okr;
+                    ne_opaque32(l);
+                    ne_opaque32(r);
+                    noneq_combine<T, 1, T>(l, r, ne);
+                } else {
+                    // this lane's state (selected element by element, so that
+                    // the arrays stay in registers), then the partner's share
+                    T Ws[4], Wn[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) { Ws[k] = side ? o[4][k] : o[3][k]; Wn[k] = side ? in.Wrx[k] : in.Wlx[k]; }
+                    NeSide<T, 1, T> own, l, r;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) { Ws[k] = opaque32(Ws[k]); Wn[k] = opaque32(Wn[k]); }
+                    const bool oko = noneq_side<T, 1, T>(Ws, side, T(P.gamma), T(P.K), T(par.iN), own, Wn, in.Wly);
+                    ne_opaque32(own);
+                    const bool okp = __builtin_amdgcn_update_dpp(0, (int)oko, 0xB1, 0xF, 0xF, false) != 0;
+                    ok = oko && okp;
+                    // left share first, whichever lane holds it
+                    auto pick = [&](T mine, T& lv, T& rv) {
+                        const T other = pair_swap(mine);
+                        lv = side ? other : mine;
+                        rv = side ? mine : other;
+                    };
+                    pick(own.p, l.p, r.p);
+                    pick(own.rs, l.rs, r.rs);
+                    pick(own.rt, l.rt, r.rt);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        pick(own.h0[k], l.h0[k], r.h0[k]);
+                        pick(own.h1[k], l.h1[k], r.h1[k]);
+                        pick(own.h2[k], l.h2[k], r.h2[k]);
+                        pick(own.h3[k], l.h3[k], r.h3[k]);
+                    }
+                    noneq_combine<T, 1, T>(l, r, ne);
+                }
             }
             if (ok) ok = gks_point<T, 1, T>(par, in, P.recon ? ne.Xs : o[0], ne, out);
             if (!ok) {
@@ -544,27 +641,28 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
 #pragma unroll
                 for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = T(0);
             }
-            const bool own = (t < BLK - 1) || (f == P.nx);
+            const bool own = (j < NF - 1) || (f == P.nx);
             const long long g = P.foff + f;
             const int slot[3] = {0, 1, 3};
+            if (side == 0) // both lanes of a pair hold the same results
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int sl = slot[k];
-                sh_FdL[k][t] = double(out.FdL[sl]);
-                if (STAGE == 1) {
-                    const double s0 = double(out.S0[sl]), s1 = double(out.S1[sl]), s2 = double(out.S2[sl]);
-                    sh_FL[k][t] = double(out.FL[sl]);
-                    sh_Wf[k][t] = msmd_half(s0, s1, s2, dt);
-                    if (own) Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
-                } else {
-                    sh_Wf[k][t] = msmd_corr(sh_face[k][t], double(out.S2[sl]), dt);
+                for (int k = 0; k < 3; ++k) {
+                    const int sl = slot[k];
+                    sh_FdL[k][j] = double(out.FdL[sl]);
+                    if (STAGE == 1) {
+                        const double s0 = double(out.S0[sl]), s1 = double(out.S1[sl]), s2 = double(out.S2[sl]);
+                        sh_FL[k][j] = double(out.FL[sl]);
+                        sh_Wf[k][j] = msmd_half(s0, s1, s2, dt);
+                        if (own) Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
+                    } else {
+                        sh_Wf[k][j] = msmd_corr(sh_face[k][j], double(out.S2[sl]), dt);
+                    }
                 }
-            }
         }
         __syncthreads();
-        // ---- cells c0 .. c0 + BLK - 2
+        // ---- cells c0 .. c0 + NF - 2
         const int i = tl.start + t;
-        const bool live = (t < BLK - 1) && (i < P.nx);
+        const bool live = (t < NF - 1) && (i < P.nx);
         const double idx = 1.0 / P.dx;
         double wn[3] = {0.0, 0.0, 0.0};
         if (live) {

@@ -44,6 +44,45 @@ template <> GKS_HD double rcp<double>(double x) { return drcp(x); }
 template <typename T> GKS_HD T quot(T a, T b) { return a / b; }
 template <> GKS_HD float quot<float>(float a, float b) { return a * frcp(b); }
 template <> GKS_HD double quot<double>(double a, double b) { return a * drcp(b); }
+// a * b + c, fused for float and double (so that code shared by two
+// kernels rounds alike whatever the compiler would contract)
+template <typename T> GKS_HD T fmadd(T a, T b, T c) { return a * b + c; }
+template <> GKS_HD float fmadd<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> GKS_HD double fmadd<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// A value the compiler must treat as unknown (an empty asm statement that
+// claims to change it; no instruction): code on either side of it is then
+// contracted and shared in the same way whatever surrounds it, so that two
+// kernels that compute a result through different routes round it alike.
+__device__ __forceinline__ float opaque(float x) { asm volatile("" : "+v"(x)); return x; }
+__device__ __forceinline__ double opaque(double x) { asm volatile("" : "+v"(x)); return x; }
+__device__ __forceinline__ int opaque(int x) { asm volatile("" : "+v"(x)); return x; }
+__host__ inline float opaque(float x) { return x; }
+__host__ inline double opaque(double x) { return x; }
+__host__ inline int opaque(int x) { return x; }
+// opaque() for FP32 values only: the lane-pair and single-lane forms of the
+// 1-D face compile to the same FP64 rounding without the barrier, while
+// their FP32 forms differ unless it is there
+template <typename T>
+GKS_HD T opaque32(T x)
+{
+    if constexpr (sizeof(T) == 4) return opaque(x);
+    else return x;
+}
+
+// The value of the other lane of a lane pair (lanes 2j and 2j + 1): a DPP
+// quad permutation (1, 0, 3, 2), one VALU move per 32 bits.
+__device__ __forceinline__ float pair_swap(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double x)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0xB1, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
 // Type of the time-integration coefficients: FP64 when the point is
 // evaluated in FP32 (their formulas cancel for tau_n comparable to dt).
 template <typename D> using ExpT = std::conditional_t<std::is_same_v<D, float>, double, D>;
@@ -415,13 +454,11 @@ GKS_HD void make_moments(T U, T V, T lam, T h, T K, int half, Moments<T, DIM, NU
         const T sl = sqrt(lam);
         // (1/2) / sqrt(pi lam) = h sqrt(lam) / sqrt(pi)
         const T e = exp(-lam * U * U) * (h * sl) * T(0.56418958354775628695);
-        if (half > 0) {
-            m.mu[0] = T(0.5) * erfc(-sl * U);
-            m.mu[1] = U * m.mu[0] + e;
-        } else {
-            m.mu[0] = T(0.5) * erfc(sl * U);
-            m.mu[1] = U * m.mu[0] - e;
-        }
+        // u > 0 (half = +1) or u < 0 (half = -1), without a branch: the two
+        // states of a lane pair run the same instructions
+        const T s = half > 0 ? T(1) : T(-1);
+        m.mu[0] = T(0.5) * erfc(-s * sl * U);
+        m.mu[1] = fmadd(U, m.mu[0], s * e);
     }
 #pragma unroll
     for (int n = 2; n < NU; ++n) m.mu[n] = U * m.mu[n - 1] + T(n - 1) * h * m.mu[n - 2];
@@ -818,55 +855,99 @@ struct NonEq {
     T Hn[4], Hm[4];
 };
 
+// One state's share: its pressure and density and, per unit density, its
+// half-range moments h0 = <psi>, h1 = <u psi> (type D) and, when slopes are
+// given, h2 = <(a.u) psi>, h3 = <u (a.u) psi> (type T).  side 0: the left
+// state over u > 0; side 1: the right state over u < 0.
+template <typename D, int DIM, typename T = D>
+struct NeSide {
+    D p, rs;
+    D h0[4], h1[4];
+    T rt;
+    T h2[4], h3[4];
+};
+
+template <typename D, int DIM, typename T = D>
+GKS_HD bool noneq_side(const D* Ws, int side, D gamma, D K, D iN, NeSide<D, DIM, T>& o, const T* Wn = nullptr,
+                       const T* Wt = nullptr)
+{
+    D rs, Us, Vs, ls, ps, irs_d, ips;
+    const bool ok = primitive<D, DIM>(Ws, gamma, rs, Us, Vs, ls, ps, irs_d, ips);
+    const D hs = ps * irs_d; // 1 / (2 lam) = p / rho
+    o.p = ps;
+    o.rs = rs;
+    Moments<D, DIM, 7> m;
+    make_moments<D, DIM, 7>(Us, Vs, ls, hs, K, side ? -1 : +1, m);
+    psi_mom<0, 0, DIM>(m, o.h0);
+    psi_mom<1, 0, DIM>(m, o.h1);
+    o.rt = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { o.h2[k] = T(0); o.h3[k] = T(0); }
+    if (Wn) {
+        Moments<T, DIM, 7> mt;
+        cast_moments<D, 7, DIM, T>(m, mt);
+        const T irs = T(irs_d), h_t = T(hs), N_t = T(K) + T(DIM), iN_t = T(iN);
+        o.rt = T(rs);
+        T b[4], as1[4], as2[4] = {T(0), T(0), T(0), T(0)}, t1[4], t2[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = Wn[k] * irs;
+        micro_solve<T, DIM>(mt.U, mt.V, mt.lam, h_t, N_t, iN_t, b, as1);
+        if constexpr (DIM == 2) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b[k] = Wt[k] * irs;
+            micro_solve<T, DIM>(mt.U, mt.V, mt.lam, h_t, N_t, iN_t, b, as2);
+        }
+        lin<1, 0, DIM>(mt, as1, o.h2); // <a1 u psi>_half
+        lin<2, 0, DIM>(mt, as1, o.h3); // <a1 u^2 psi>_half
+        if constexpr (DIM == 2) {
+            lin<0, 1, DIM>(mt, as2, t1);
+            lin<1, 1, DIM>(mt, as2, t2);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { o.h2[k] += t1[k]; o.h3[k] += t2[k]; }
+        }
+    }
+    return ok;
+}
+
+// every field of a share through opaque32()
+template <typename D, int DIM, typename T>
+__device__ __forceinline__ void ne_opaque32(NeSide<D, DIM, T>& o)
+{
+    o.p = opaque32(o.p);
+    o.rs = opaque32(o.rs);
+    o.rt = opaque32(o.rt);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        o.h0[k] = opaque32(o.h0[k]);
+        o.h1[k] = opaque32(o.h1[k]);
+        o.h2[k] = opaque32(o.h2[k]);
+        o.h3[k] = opaque32(o.h3[k]);
+    }
+}
+
+// The two states' sums, left share first: X = rs_r h_r + rs_l h_l (fused).
+template <typename D, int DIM, typename T = D>
+GKS_HD void noneq_combine(const NeSide<D, DIM, T>& l, const NeSide<D, DIM, T>& r, NonEq<D, DIM, T>& ne)
+{
+    ne.pl = l.p;
+    ne.pr = r.p;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ne.Xs[k] = fmadd(r.rs, r.h0[k], l.rs * l.h0[k]);
+        ne.Xf[k] = fmadd(r.rs, r.h1[k], l.rs * l.h1[k]);
+        ne.Hn[k] = fmadd(r.rt, r.h2[k], l.rt * l.h2[k]);
+        ne.Hm[k] = fmadd(r.rt, r.h3[k], l.rt * l.h3[k]);
+    }
+}
+
 template <typename D, int DIM, typename T = D>
 GKS_HD bool noneq_states(const D* Wl, const D* Wr, D gamma, D K, D iN, NonEq<D, DIM, T>& ne, const T* Wlx = nullptr,
                          const T* Wly = nullptr, const T* Wrx = nullptr, const T* Wry = nullptr)
 {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { ne.Xs[k] = D(0); ne.Xf[k] = D(0); ne.Hn[k] = T(0); ne.Hm[k] = T(0); }
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-        D rs, Us, Vs, ls, ps, irs_d, ips;
-        if (!primitive<D, DIM>(side ? Wr : Wl, gamma, rs, Us, Vs, ls, ps, irs_d, ips)) return false;
-        const D hs = ps * irs_d; // 1 / (2 lam) = p / rho
-        if (side) ne.pr = ps;
-        else ne.pl = ps;
-        Moments<D, DIM, 7> m;
-        make_moments<D, DIM, 7>(Us, Vs, ls, hs, K, side ? -1 : +1, m);
-        D h[4] = {D(0), D(0), D(0), D(0)};
-        psi_mom<0, 0, DIM>(m, h);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) ne.Xs[k] += rs * h[k];
-        psi_mom<1, 0, DIM>(m, h);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) ne.Xf[k] += rs * h[k];
-        const T* Wn = side ? Wrx : Wlx;
-        if (Wn) {
-            const T* Wt = side ? Wry : Wly;
-            Moments<T, DIM, 7> mt;
-            cast_moments<D, 7, DIM, T>(m, mt);
-            const T rt = T(rs), irs = T(irs_d), h_t = T(hs), N_t = T(K) + T(DIM), iN_t = T(iN);
-            T b[4], as1[4], as2[4] = {T(0), T(0), T(0), T(0)}, h2[4], h3[4], t1[4], t2[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) b[k] = Wn[k] * irs;
-            micro_solve<T, DIM>(mt.U, mt.V, mt.lam, h_t, N_t, iN_t, b, as1);
-            if constexpr (DIM == 2) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) b[k] = Wt[k] * irs;
-                micro_solve<T, DIM>(mt.U, mt.V, mt.lam, h_t, N_t, iN_t, b, as2);
-            }
-            lin<1, 0, DIM>(mt, as1, h2); // <a1 u psi>_half
-            lin<2, 0, DIM>(mt, as1, h3); // <a1 u^2 psi>_half
-            if constexpr (DIM == 2) {
-                lin<0, 1, DIM>(mt, as2, t1);
-                lin<1, 1, DIM>(mt, as2, t2);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) { h2[k] += t1[k]; h3[k] += t2[k]; }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { ne.Hn[k] += rt * h2[k]; ne.Hm[k] += rt * h3[k]; }
-        }
-    }
+    NeSide<D, DIM, T> l, r;
+    if (!noneq_side<D, DIM, T>(Wl, 0, gamma, K, iN, l, Wlx, Wly)) return false;
+    if (!noneq_side<D, DIM, T>(Wr, 1, gamma, K, iN, r, Wrx, Wry)) return false;
+    noneq_combine<D, DIM, T>(l, r, ne);
     return true;
 }
 

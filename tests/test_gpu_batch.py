@@ -21,11 +21,11 @@ def gks():
     return g
 
 
-def run(probs, steps=None, tune=None, graph=None, precision=0):
+def run(probs, steps=None, tune=None, graph=None, precision=0, split=None):
     g = gks()
-    old = {k: os.environ.get(k) for k in ("GKS_TUNE", "GKS_GRAPH")}
+    old = {k: os.environ.get(k) for k in ("GKS_TUNE", "GKS_GRAPH", "GKS_SPLIT")}
     try:
-        for k, v in (("GKS_TUNE", tune), ("GKS_GRAPH", graph)):
+        for k, v in (("GKS_TUNE", tune), ("GKS_GRAPH", graph), ("GKS_SPLIT", split)):
             if v is None:
                 os.environ.pop(k, None)
             else:
@@ -55,7 +55,10 @@ def batch():
 
 @pytest.mark.parametrize("tune", ["64:0", "64:1", "128:2", "256:0", "256:4"])
 def test_launch_modes_bit_identical(batch, tune):
-    ref, _ = run(batch, tune="128:0", graph="0")
+    # the reference runs the single-lane kernel throughout; with its 36 work
+    # items the compared run switches to the lane-pair kernel after its
+    # first call
+    ref, _ = run(batch, tune="128:0", graph="0", split="0")
     got, cfg = run(batch, tune=tune)
     assert cfg.startswith("forced")
     for a, b in zip(ref, got):
@@ -64,10 +67,57 @@ def test_launch_modes_bit_identical(batch, tune):
 
 @pytest.mark.parametrize("tune", ["64:1", "256:0"])
 def test_launch_modes_bit_identical_mixed(batch, tune):
-    ref, _ = run(batch, tune="128:0", graph="0", precision=1)
+    ref, _ = run(batch, tune="128:0", graph="0", precision=1, split="0")
     got, _ = run(batch, tune=tune, precision=1)
     for a, b in zip(ref, got):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lane_pair_steps_bit_identical(batch, precision):
+    """The lane-pair kernel (two lanes share a face: one WENO-Z side and one
+    non-equilibrium state each, exchanged by DPP moves) reproduces the
+    single-lane kernel bit for bit: on for the whole run against off."""
+    ref, cfg0 = run(batch, split="0", precision=precision)
+    got, cfg = run(batch, split="2", precision=precision)
+    assert "lane-pair steps off" in cfg0 and "lane-pair steps on" in cfg
+    for a, b in zip(ref, got):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]
+
+
+def test_lane_pair_switch_during_a_run():
+    """The 256-problem uneven batch: its active work items fall below the
+    CU count as the small problems finish, and the automatic switch to the
+    lane-pair kernel leaves every problem bit-identical to a run without it."""
+    g = gks()
+    probs = wl.batch_1d(t_end=0.02)
+
+    def go(split):
+        old = os.environ.get("GKS_SPLIT")
+        os.environ["GKS_SPLIT"] = split
+        try:
+            S = g.Solver(probs)
+            # three problems of this batch meet a non-physical state in
+            # their first steps and stop; the others run on
+            while S.step(500, raise_on_error=False) != 0:
+                pass
+            out = [S.state(p) + (S.status(p),) for p in range(len(probs))]
+            cfg = S.launch_config()
+            S.close()
+        finally:
+            if old is None:
+                os.environ.pop("GKS_SPLIT", None)
+            else:
+                os.environ["GKS_SPLIT"] = old
+        return out, cfg
+
+    ref, cfg0 = go("0")
+    got, cfg = go("1")
+    assert "lane-pair steps off" in cfg0 and "lane-pair steps on" in cfg
+    assert sum(r[5] == g.GKS_ENONPHYS for r in ref) == 3
+    for a, b in zip(ref, got):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]
+        assert a[5] == b[5]
 
 
 def test_bad_tune_string_is_rejected(batch):
