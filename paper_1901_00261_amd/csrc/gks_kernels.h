@@ -465,7 +465,8 @@ __global__ void __launch_bounds__(kCompactThreads) compact_items_kernel(const Pr
 // the list is exhausted, so the same kernel runs persistent (a few
 // workgroups per CU) or as a plain grid (one workgroup per item); every
 // workgroup reaches the exit.  The item list holds only the problems still
-// active; its length is read from device memory.  The last workgroup of the
+// active; its length is read from device memory, and workgroups beyond it
+// leave at once.  The last workgroup of the
 // second stage to finish (a done-counter, ctr[2]) commits the step for every
 // problem, resets the counters and, when a problem has stopped, rebuilds the
 // list for the next step, so a step is two launches.  Faces owned by the tile (all but its last face, plus the
@@ -485,6 +486,13 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
     __shared__ int sh_item;
     const int t = threadIdx.x;
     const int nitems = *nitems_p;
+    // Only the first min(grid, items) workgroups take part (the grid is
+    // sized for the full list; in a run's tail most problems have stopped):
+    // the others leave before touching a counter.  A workgroup that starts
+    // after the last participant has committed the step reads the rebuilt
+    // list's length, which is no larger, so it leaves as well.
+    const int nwg = min((int)gridDim.x, nitems);
+    if ((int)blockIdx.x >= nwg) return;
     for (;;) {
         if (t == 0) sh_item = (int)atomicAdd(&ctr[STAGE - 1], 1u);
         __syncthreads();
@@ -709,7 +717,7 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
         __syncthreads();
         if (t == 0) {
             __threadfence(); // release
-            sh_last = atomicAdd(&ctr[2], 1u) == gridDim.x - 1;
+            sh_last = atomicAdd(&ctr[2], 1u) == (unsigned)nwg - 1;
             sh_stopped = 0;
         }
         __syncthreads();
