@@ -371,9 +371,9 @@ def bench_batch1d(args):
             upd = 0
             steps = 0
             while True:
-                r = S.step(100, raise_on_error=False)
+                r = S.step(128, raise_on_error=False)
                 upd += S.cell_updates()
-                steps += 100
+                steps += 128
                 if r == 0:
                     break
             torch.cuda.synchronize()

@@ -81,8 +81,9 @@ struct gks_handle {
     // to the step's stream around them (not while kernels are being timed)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipGraph_t graph = nullptr, graphK = nullptr;
-    hipGraphExec_t gexec = nullptr, gexecK = nullptr; // one step, kGraphSteps steps
+    // graphs of 1, kGraphSteps[0] and kGraphSteps[1] steps
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -346,34 +347,33 @@ void launch_step(gks_handle* h, hipStream_t st)
 
 void drop_graph(gks_handle* h)
 {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
-    if (h->gexecK) (void)hipGraphExecDestroy(h->gexecK);
-    if (h->graphK) (void)hipGraphDestroy(h->graphK);
-    h->gexec = h->gexecK = nullptr;
-    h->graph = h->graphK = nullptr;
+    for (int g = 0; g < 3; ++g) {
+        if (h->gexec[g]) (void)hipGraphExecDestroy(h->gexec[g]);
+        if (h->graph[g]) (void)hipGraphDestroy(h->graph[g]);
+        h->gexec[g] = nullptr;
+        h->graph[g] = nullptr;
+    }
 }
 
-// steps per replay of the long graph: fewer graph launches, so fewer gaps
-// between steps and less host work per step
-constexpr int kGraphSteps = 8;
+// steps per replay of the longer graphs: fewer graph launches, so fewer
+// gaps between steps (about 8 us each) and less host work per step
+constexpr int kGraphSteps[2] = {8, 32};
 
-// capture one MSMD step, and kGraphSteps steps in a row, (kernel nodes
+// capture one MSMD step, and kGraphSteps[g] steps in a row, (kernel nodes
 // only) on the private capture stream; a step's launches depend only on
-// device state, so a replay of the long graph equals kGraphSteps replays of
-// the short one
+// device state, so a replay of a long graph equals as many replays of the
+// short one
 int build_graph(gks_handle* h)
 {
     drop_graph(h);
     if (h->dim == 1) ensure_work_list(h, h->stream); // the captured step assumes a current list
-    HIP_TRY(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    launch_step(h, h->cap);
-    HIP_TRY(h, hipStreamEndCapture(h->cap, &h->graph));
-    HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
-    HIP_TRY(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    for (int s = 0; s < kGraphSteps; ++s) launch_step(h, h->cap);
-    HIP_TRY(h, hipStreamEndCapture(h->cap, &h->graphK));
-    HIP_TRY(h, hipGraphInstantiate(&h->gexecK, h->graphK, nullptr, nullptr, 0));
+    for (int g = 0; g < 3; ++g) {
+        const int n = g == 0 ? 1 : kGraphSteps[g - 1];
+        HIP_TRY(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        for (int s = 0; s < n; ++s) launch_step(h, h->cap);
+        HIP_TRY(h, hipStreamEndCapture(h->cap, &h->graph[g]));
+        HIP_TRY(h, hipGraphInstantiate(&h->gexec[g], h->graph[g], nullptr, nullptr, 0));
+    }
     return GKS_OK;
 }
 
@@ -899,15 +899,17 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
         }
     }
     const bool graph = h->use_graph && !h->timing && max_steps > 0;
-    if (graph && !h->gexec) {
+    if (graph && !h->gexec[0]) {
         const int st = build_graph(h);
         if (st) return st;
     }
     int s = 0;
     if (graph)
-        for (; s + kGraphSteps <= max_steps; s += kGraphSteps) HIP_TRY(h, hipGraphLaunch(h->gexecK, h->stream));
+        for (int g = 2; g >= 1; --g)
+            for (; s + kGraphSteps[g - 1] <= max_steps; s += kGraphSteps[g - 1])
+                HIP_TRY(h, hipGraphLaunch(h->gexec[g], h->stream));
     for (; s < max_steps; ++s) {
-        if (graph) HIP_TRY(h, hipGraphLaunch(h->gexec, h->stream));
+        if (graph) HIP_TRY(h, hipGraphLaunch(h->gexec[0], h->stream));
         else launch_step(h, h->stream);
     }
     HIP_TRY(h, hipGetLastError());
