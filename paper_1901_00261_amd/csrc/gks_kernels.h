@@ -493,12 +493,19 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
     // list's length, which is no larger, so it leaves as well.
     const int nwg = min((int)gridDim.x, nitems);
     if ((int)blockIdx.x >= nwg) return;
-    for (;;) {
-        if (t == 0) sh_item = (int)atomicAdd(&ctr[STAGE - 1], 1u);
+    // A workgroup's first item is its own index; each later one comes from
+    // the counter (offset by the participants), requested as the previous
+    // item starts, so that the atomic's latency hides behind that item.
+    auto advance = [&](int n) {
+        if (t == 0) sh_item = n;
         __syncthreads();
-        const int it = sh_item;
+        const int v = sh_item;
         __syncthreads();
-        if (it >= nitems) break;
+        return v;
+    };
+    int nxt = 0;
+    for (int it = blockIdx.x; it < nitems; it = advance(nxt)) {
+        if (t == 0) nxt = nwg + (int)atomicAdd(&ctr[STAGE - 1], 1u);
         const Tile tl = items[it];
         const ProbParam& P = PP[tl.p];
         ProbState& S = PS[tl.p];
