@@ -63,7 +63,7 @@ struct gks_handle {
     std::vector<int> hcount[3]; // per problem: items of each tile size (host copy)
     std::vector<char> last_active; // problem still running after the last gks_step (host copy)
     // lane-pair steps: while the active work items of the tuned tile size
-    // are fewer than the CUs, the steps run the 256-thread kernel whose lane
+    // are at most half the CUs, the steps run the 256-thread kernel whose lane
     // pairs share a face, on tiles of 127 cells (GKS_SPLIT: 0 never,
     // 1 automatic (default), 2 always)
     int split = 0, split_mode = 1;
@@ -884,14 +884,15 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
     }
     if (h->dim == 1 && h->tuned) {
         // lane-pair steps while the work items of the tuned tile size still
-        // running (known from the last call) are fewer than the CUs
+        // running (known from the last call) are at most half the CUs, so
+        // the lane-pair items (twice as many) still fill each CU once
         int want = h->split_mode == 2;
         if (h->split_mode == 1) {
             const int bn = h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2);
             long long items = 0;
             for (int p = 0; p < h->nprob; ++p)
                 if (h->last_active[p]) items += h->hcount[bn][p];
-            want = items < h->ncu;
+            want = 2 * items <= h->ncu;
         }
         if (want != h->split) {
             h->split = want;
@@ -1032,7 +1033,7 @@ const char* gks_launch_config(const gks_handle* hc)
         char buf[192];
         snprintf(buf, sizeof buf, "; blk %d gmul %d: %d workgroups for %d work items; lane-pair steps %s (%s)",
                  h->blk, h->gmul, h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu), n, h->split ? "on" : "off",
-                 h->split_mode == 0 ? "never" : (h->split_mode == 2 ? "always" : "while items < CUs"));
+                 h->split_mode == 0 ? "never" : (h->split_mode == 2 ? "always" : "while items <= CUs / 2"));
         h->cfg_text = h->tune_note + buf;
     }
     return h->cfg_text.c_str();

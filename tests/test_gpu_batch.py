@@ -86,7 +86,7 @@ def test_lane_pair_steps_bit_identical(batch, precision):
 
 
 def test_lane_pair_switch_during_a_run():
-    """The 256-problem uneven batch: its active work items fall below the
+    """The 256-problem uneven batch: its active work items fall to half the
     CU count as the small problems finish, and the automatic switch to the
     lane-pair kernel leaves every problem bit-identical to a run without it."""
     g = gks()
@@ -99,7 +99,10 @@ def test_lane_pair_switch_during_a_run():
             S = g.Solver(probs)
             # three problems of this batch meet a non-physical state in
             # their first steps and stop; the others run on
-            while S.step(500, raise_on_error=False) != 0:
+            # calls of 100 steps, so that the switch (decided at each call
+            # from the work items left after the previous one) comes while
+            # the largest problems still run
+            while S.step(100, raise_on_error=False) != 0:
                 pass
             out = [S.state(p) + (S.status(p),) for p in range(len(probs))]
             cfg = S.launch_config()
