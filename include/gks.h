@@ -162,11 +162,18 @@ int gks_cell_updates(const gks_handle* h, int64_t* count);
    The first gks_step of a 1-D handle autotunes (BLK, GMUL) by timing a few
    steps from the initial state, which is restored afterwards (larger tiles
    and fewer workgroups are tried first and kept unless another candidate
-   is more than 3 % faster); every
-   configuration performs the same arithmetic, so results do not depend on
-   the choice.  Environment: GKS_TUNE="BLK:GMUL" forces a configuration,
-   GKS_TUNE_CACHE=<file> caches tuning results by problem-set signature,
-   GKS_GRAPH=0 disables the hipGraph replay of steps (enabled by default). */
+   is more than 3 % faster).  Each gks_step call chooses the form of its
+   steps from the work items still active after the previous call: at most
+   half as many 127-cell items as compute units, a lane-pair kernel (two
+   lanes per face); FP64 with at least two 255-cell items per compute unit,
+   three kernels per stage (face reconstruction, interface point, cells);
+   otherwise the tuned kernel.  Every configuration and form performs the
+   same arithmetic, so results do not depend on the choice.  Environment:
+   GKS_TUNE="BLK:GMUL" forces a configuration, GKS_TUNE_CACHE=<file> caches
+   tuning results by problem-set signature, GKS_GRAPH=0 disables the
+   hipGraph replay of steps (enabled by default), GKS_SPLIT and GKS_PHASES
+   (0 never, 1 automatic, the default, 2 always) control the lane-pair and
+   three-kernel forms. */
 const char* gks_launch_config(const gks_handle* h);
 
 /* For callers that cannot allocate device memory: code under HIP graph

@@ -41,6 +41,7 @@ struct gks_handle {
     double *FL = nullptr, *FdL = nullptr, *Wfs = nullptr, *Pf = nullptr;
     double *FLy = nullptr, *FdLy = nullptr, *Wfsy = nullptr, *Pfy = nullptr;
     void *Rx = nullptr, *Ry = nullptr; // face-row buffers: double (FP64) or float (FP32-mixed)
+    double *R1 = nullptr, *R2 = nullptr; // 1-D three-phase steps: reconstructed faces, face values
     double* stage = nullptr; // transpose staging
     size_t stage_len = 0;
     std::string err;
@@ -67,6 +68,11 @@ struct gks_handle {
     // pairs share a face, on tiles of 127 cells (GKS_SPLIT: 0 never,
     // 1 automatic (default), 2 always)
     int split = 0, split_mode = 1;
+    // three-phase steps (FP64): while the active 255-cell work items are
+    // at least kPhaseItemsPerCU per CU, each stage runs as the face, point
+    // and cell kernels, two waves per SIMD (GKS_PHASES: 0 never,
+    // 1 automatic (default), 2 always)
+    int phases = 0, phases_mode = 1;
     int ncu = 256;
     // launch configuration (autotuned): threads per tile, workgroups per CU
     // (0: one workgroup per work item)
@@ -232,7 +238,7 @@ void harvest(gks_handle* h)
 // 127-cell tiles of the lane-pair kernel
 int list_index(const gks_handle* h)
 {
-    return h->split ? 1 : (h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2));
+    return h->split ? 1 : (h->phases ? 2 : (h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2)));
 }
 
 void ensure_work_list(gks_handle* h, hipStream_t st)
@@ -253,7 +259,18 @@ template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
     int* na = h->dNact;
     const int G = h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu);
     record(h, st, 0, true);
-    if (h->split) {
+    if (h->phases) {
+        // FP64 only; one workgroup per item of the full list
+        double* W = h->W;
+        double* X = h->Wx;
+        gks::face1d_kernel<1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->R1, h->Ntot, h->F);
+        gks::point1d_kernel<1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, h->R1, h->R2, h->Pf, h->F);
+        gks::cell1d_kernel<1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->PW, h->R2, h->Ntot, h->F);
+        gks::face1d_kernel<2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->R1, h->Ntot, h->F);
+        gks::point1d_kernel<2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, h->R1, h->R2, h->Pf, h->F);
+        gks::cell1d_kernel<2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->PW, h->R2, h->Ntot, h->F);
+        gks::commit1d_kernel<<<1, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+    } else if (h->split) {
         const int Gs = std::min(n, std::max(1, h->gmul) * h->ncu);
         gks::stage1d_kernel<T, 1, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
         gks::stage1d_kernel<T, 2, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
@@ -354,6 +371,11 @@ void drop_graph(gks_handle* h)
         h->graph[g] = nullptr;
     }
 }
+
+// three-phase steps while the active 255-cell work items number at least
+// this many per CU (1 to 4 measured within 1 % of each other on the
+// 256-problem batch)
+constexpr int kPhaseItemsPerCU = 2;
 
 // steps per replay of the longer graphs: fewer graph launches, so fewer
 // gaps between steps (about 8 us each) and less host work per step
@@ -516,7 +538,7 @@ void release(gks_handle* h)
     for (void* p : {(void*)h->dP, (void*)h->dS, (void*)h->dTilesC, (void*)h->W, (void*)h->Wx,
                     (void*)h->Wy, (void*)h->PW, (void*)h->FL, (void*)h->FdL, (void*)h->Wfs, (void*)h->Pf,
                     (void*)h->FLy, (void*)h->FdLy, (void*)h->Wfsy, (void*)h->Pfy, (void*)h->Rx, (void*)h->Ry,
-                    (void*)h->stage})
+                    (void*)h->R1, (void*)h->R2, (void*)h->stage})
         dfree(p);
     drop_graph(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
@@ -642,6 +664,8 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     }
     if (const char* g = getenv("GKS_GRAPH")) h->use_graph = atoi(g) != 0;
     if (const char* g = getenv("GKS_SPLIT")) h->split_mode = std::min(std::max(atoi(g), 0), 2);
+    if (const char* g = getenv("GKS_PHASES")) h->phases_mode = std::min(std::max(atoi(g), 0), 2);
+    if (precision != GKS_PREC_FP64 || dim != 1) h->phases_mode = 0;
     h->last_active.assign(nprob, 1);
     TRY(([&]() -> int {
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
@@ -894,8 +918,29 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
                 if (h->last_active[p]) items += h->hcount[bn][p];
             want = 2 * items <= h->ncu;
         }
-        if (want != h->split) {
+        // three-phase steps (FP64) while the 255-cell items fill the CUs
+        // several times; the lane-pair steps take precedence
+        int wantp = 0;
+        if (!want && h->phases_mode != 0) {
+            long long items = 0;
+            for (int p = 0; p < h->nprob; ++p)
+                if (h->last_active[p]) items += h->hcount[2][p];
+            wantp = h->phases_mode == 2 || items >= kPhaseItemsPerCU * h->ncu;
+        }
+        if (wantp && !h->R1) {
+            // the face buffers, allocated on first use; without them the
+            // steps stay fused
+            if (dalloc(&h->R1, 21 * (size_t)h->F) != hipSuccess || dalloc(&h->R2, 9 * (size_t)h->F) != hipSuccess) {
+                (void)hipGetLastError();
+                dfree(h->R1);
+                h->R1 = nullptr;
+                h->phases_mode = 0;
+                wantp = 0;
+            }
+        }
+        if (want != h->split || wantp != h->phases) {
             h->split = want;
+            h->phases = wantp;
             drop_graph(h);
         }
     }
@@ -1030,10 +1075,13 @@ const char* gks_launch_config(const gks_handle* hc)
         h->cfg_text = "1-D: not tuned yet (tunes on the first gks_step)";
     } else {
         const int n = h->nItems[h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2)];
-        char buf[192];
-        snprintf(buf, sizeof buf, "; blk %d gmul %d: %d workgroups for %d work items; lane-pair steps %s (%s)",
+        char buf[320];
+        snprintf(buf, sizeof buf,
+                 "; blk %d gmul %d: %d workgroups for %d work items; lane-pair steps %s (%s); three-phase steps %s (%s)",
                  h->blk, h->gmul, h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu), n, h->split ? "on" : "off",
-                 h->split_mode == 0 ? "never" : (h->split_mode == 2 ? "always" : "while items <= CUs / 2"));
+                 h->split_mode == 0 ? "never" : (h->split_mode == 2 ? "always" : "while items <= CUs / 2"),
+                 h->phases ? "on" : "off",
+                 h->phases_mode == 0 ? "never" : (h->phases_mode == 2 ? "always" : "while 255-cell items >= 2 per CU"));
         h->cfg_text = h->tune_note + buf;
     }
     return h->cfg_text.c_str();

@@ -19,6 +19,10 @@
 #include "gks_math.h"
 
 namespace gks {
+// Multiply-adds are contracted into FMAs only within one statement, so a
+// function rounds the same way wherever it is inlined (the single-lane,
+// lane-pair and three-phase forms of the batched 1-D step agree bit for bit).
+#pragma clang fp contract(on)
 
 struct ProbParam {
     int nx, ny;
@@ -239,12 +243,11 @@ __device__ __forceinline__ void tile_xy(int gx, int& tx, int& ty)
 // SPLIT = 2: a lane pair shares the face; the lane of the given side (0: the
 // left state, 1: the right state, as the left state of the mirrored stencil)
 // runs the WENO-Z of its side only and takes the other side from its
-// partner.  SPLIT = 1: one lane runs both sides; in FP32 the same way, the
-// inputs and results of each side's WENO-Z passed through opaque(), as the
-// lane pair passes them through its exchange, so that the two forms round
-// alike (the FP64 forms round alike without it).  SPLIT = 0: one lane, no
-// such barrier.
-template <typename T, int DIM, int ORDER, typename D = double, typename F = D, int SPLIT = 0, typename Emit>
+// partner.  SPLIT = 1: one lane runs both sides.  Both forms round alike:
+// every multiply-add is contracted within its own statement (the fp
+// contract pragma at the top of these headers), so the contraction does not
+// depend on the code around it.
+template <typename T, int DIM, int ORDER, typename D = double, typename F = D, int SPLIT = 1, typename Emit>
 GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, bool weno, Emit&& emit, int side = 0)
 {
     // outputs in O: FP32 when the frame is FP32 (the FP32-mixed path stores
@@ -303,38 +306,20 @@ GKS_HD bool face_recon(const D (&Wk)[4][4], const D (&Dk)[4][4], D h, D gamma, b
             d[q] = T(sd);
         }
         T vl, dl, vr, dr;
-        if constexpr (SPLIT == 0 || (SPLIT == 1 && sizeof(T) == 8)) {
+        if constexpr (SPLIT == 1) {
             weno_left<T, ORDER>(w, d, vl, dl);
             weno_right<T, ORDER>(w, d, vr, dr);
-        } else if constexpr (SPLIT == 1) {
+        } else {
             // weno_right(w, d) is weno_left of the mirrored stencil with
             // the derivative negated
-            T wa[4], da[4], wb[4], db[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                wa[q] = opaque(w[q]);
-                da[q] = opaque(d[q]);
-                wb[q] = opaque(w[3 - q]);
-                db[q] = opaque(-d[3 - q]);
-            }
-            T va, ea, vb, eb;
-            weno_left<T, ORDER>(wa, da, va, ea);
-            weno_left<T, ORDER>(wb, db, vb, eb);
-            vl = opaque(va);
-            dl = opaque(ea);
-            vr = opaque(vb);
-            dr = -opaque(eb);
-        } else {
             T ws[4], ds[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                ws[q] = opaque32(side ? w[3 - q] : w[q]);
-                ds[q] = opaque32(side ? -d[3 - q] : d[q]);
+                ws[q] = side ? w[3 - q] : w[q];
+                ds[q] = side ? -d[3 - q] : d[q];
             }
             T v, dd;
             weno_left<T, ORDER>(ws, ds, v, dd);
-            v = opaque32(v);
-            dd = opaque32(dd);
             const T pv = pair_swap(v), pd = pair_swap(dd);
             vl = side ? pv : v;
             dl = side ? pd : dd;
@@ -456,6 +441,116 @@ __global__ void __launch_bounds__(kCompactThreads) compact_items_kernel(const Pr
     compact_items_block<kCompactThreads>(PS, nprob, all, first, count, act, nact, scan);
 }
 
+// The four stencil cells of face f of a 1-D problem through its boundary
+// conditions: values and dx-scaled slopes (slot 2 zero), all 24 loads issued
+// together.  Wb, Xb: the problem's first cell in the state and slope slots
+// (component stride Ntot).  False when a characteristic ghost cell has no
+// physical state.
+__device__ __forceinline__ bool gather_face_1d(const ProbParam& P, const double* Wb, const double* Xb, long long Ntot,
+                                               int f, double (&Wk)[4][4], double (&Dk)[4][4])
+{
+    int kind[4], c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] = map_index_sel(f - 2 + q, P.nx, P.bc[0], P.bc[1], kind[q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Wk[q][0] = Wb[c[q]]; Wk[q][1] = Wb[Ntot + c[q]]; Wk[q][2] = 0.0; Wk[q][3] = Wb[2 * Ntot + c[q]];
+        Dk[q][0] = Xb[c[q]]; Dk[q][1] = Xb[Ntot + c[q]]; Dk[q][2] = 0.0; Dk[q][3] = Xb[2 * Ntot + c[q]];
+    }
+    bool gok = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Dk[q][k] *= P.dx;
+        ghost_frame_1d(kind[q], Wk[q], Dk[q]);
+        const int cq = f - 2 + q, side = cq < 0 ? 0 : 1;
+        if (kind[q] == kGhostStateA) {
+            const double* st = P.bstate[side][0];
+            Wk[q][0] = st[0]; Wk[q][1] = st[1]; Wk[q][3] = st[3];
+            Dk[q][0] = Dk[q][1] = Dk[q][3] = 0.0;
+        } else if (kind[q] == kGhostChar) {
+            gok = gok && char_ghost_1d(P.gamma, cq < 0 ? -cq : cq - P.nx + 1, side == 0 ? -1 : 1, Wk[q], Dk[q]);
+        }
+    }
+    return gok;
+}
+
+// Cell c (global index) of a 1-D problem at the end of stage STAGE, from the
+// values fv(q, k, s) of its left (s = 0) and right (s = 1) faces, q = 0 the
+// flux F^L, 1 its time derivative, 2 the face state W_f (component k of 3),
+// and its value wc(k) (stage 1: W^n; stage 2: the partial PW): writes
+// W (slot wr), W_x and, in stage 1, PW.  Returns the cell's signal speed
+// over dx after stage 2, flagging a non-physical state (0 then, and after
+// stage 1).
+template <int STAGE, typename FV, typename CV>
+__device__ __forceinline__ double update_cell_1d(const ProbParam& P, ProbState& S, long long c, int wr, double dt,
+                                                 double idx, const FV& fv, const CV& wc, double* __restrict__ W,
+                                                 double* __restrict__ Wx, double* __restrict__ PW, long long Ntot)
+{
+    double wn[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double dL = -(fv(1, k, 1) - fv(1, k, 0)) * idx;
+        const double slope = (fv(2, k, 1) - fv(2, k, 0)) * idx;
+        if (STAGE == 1) {
+            const double L = -(fv(0, k, 1) - fv(0, k, 0)) * idx;
+            const double w = wc(k);
+            W[((size_t)wr * 3 + k) * Ntot + c] = msmd_half(w, L, dL, dt);
+            PW[k * Ntot + c] = msmd_pred(w, L, dL, dt);
+        } else {
+            wn[k] = msmd_corr(wc(k), dL, dt);
+            W[((size_t)wr * 3 + k) * Ntot + c] = wn[k];
+        }
+        Wx[((size_t)wr * 3 + k) * Ntot + c] = slope;
+    }
+    if (STAGE == 1) return 0.0;
+    const double rho = wn[0], U = wn[1] / rho;
+    const double p = (P.gamma - 1.0) * (wn[2] - 0.5 * rho * U * U);
+    if (!(rho > 0.0) || !(p > 0.0)) {
+        atomicOr(&S.err, 1);
+        return 0.0;
+    }
+    return (fabs(U) + sqrt(P.gamma * p / rho)) * idx;
+}
+
+// End of a step's second stage (1-D): the last of the nwg workgroups taking
+// part commits the step for every problem, sets the next dt, resets the
+// counters and, when a problem has stopped, rebuilds the work list.
+// Release/acquire pairing of the "last workgroup" pattern: every
+// workgroup's writes of the launch (cell states, the error flags, the
+// signal-speed maxima) are made visible device-wide by the release fence
+// before its done-counter increment; the workgroup that sees the final
+// count issues the acquire fence before it reads them.  Called by every
+// thread of the workgroups taking part.
+template <int BLK>
+__device__ __forceinline__ void commit_if_last(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob,
+                                               unsigned* __restrict__ ctr, int nwg, const Tile* __restrict__ all,
+                                               const int* __restrict__ first, const int* __restrict__ count,
+                                               Tile* items, int* nitems_p)
+{
+    __shared__ int sh_last, sh_stopped;
+    __shared__ int sh_scan[BLK];
+    const int t = threadIdx.x;
+    __syncthreads();
+    if (t == 0) {
+        __threadfence(); // release
+        sh_last = atomicAdd(&ctr[2], 1u) == (unsigned)nwg - 1;
+        sh_stopped = 0;
+    }
+    __syncthreads();
+    if (sh_last) {
+        __threadfence(); // acquire: no stale cached copies of the problem states
+        bool stopped = false;
+        for (int p = t; p < nprob; p += BLK) stopped |= finish_problem(PP[p], PS[p], 1, 3);
+        if (stopped) atomicOr(&sh_stopped, 1);
+        if (t < 3) ctr[t] = 0u;
+        __threadfence();
+        __syncthreads();
+        // the list changes only when a problem has stopped
+        if (sh_stopped) compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched 1-D: one launch per MSMD stage for all problems.  A work item is
 // a tile of BLK-1 cells of one problem; the workgroup computes the BLK faces
@@ -552,34 +647,9 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
         const int j = t / SPLIT, side = t % SPLIT;
         const int f = tl.start + j;
         if (f <= P.nx) {
-            const double* Wb = W + (size_t)rd * 3 * Ntot + P.coff;
-            const double* Xb = Wx + (size_t)rd * 3 * Ntot + P.coff;
-            // the four stencil cells through the boundary condition, all 24
-            // loads issued together
             double Wk[4][4], Dk[4][4];
-            int kind[4], c[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) c[q] = map_index_sel(f - 2 + q, P.nx, P.bc[0], P.bc[1], kind[q]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                Wk[q][0] = Wb[c[q]]; Wk[q][1] = Wb[Ntot + c[q]]; Wk[q][2] = 0.0; Wk[q][3] = Wb[2 * Ntot + c[q]];
-                Dk[q][0] = Xb[c[q]]; Dk[q][1] = Xb[Ntot + c[q]]; Dk[q][2] = 0.0; Dk[q][3] = Xb[2 * Ntot + c[q]];
-            }
-            bool gok = true;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) Dk[q][k] *= P.dx;
-                ghost_frame_1d(kind[q], Wk[q], Dk[q]);
-                const int cq = f - 2 + q, side = cq < 0 ? 0 : 1;
-                if (kind[q] == kGhostStateA) {
-                    const double* st = P.bstate[side][0];
-                    Wk[q][0] = st[0]; Wk[q][1] = st[1]; Wk[q][3] = st[3];
-                    Dk[q][0] = Dk[q][1] = Dk[q][3] = 0.0;
-                } else if (kind[q] == kGhostChar) {
-                    gok = gok && char_ghost_1d(P.gamma, cq < 0 ? -cq : cq - P.nx + 1, side == 0 ? -1 : 1, Wk[q], Dk[q]);
-                }
-            }
+            const bool gok = gather_face_1d(P, W + (size_t)rd * 3 * Ntot + P.coff, Wx + (size_t)rd * 3 * Ntot + P.coff,
+                                            Ntot, f, Wk, Dk);
             // face reconstruction emitted in T (the FP32-mixed path stores
             // and evaluates the interface point in FP32)
             T o[7][4];
@@ -598,26 +668,9 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
                     in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
                     in.Wly[k] = in.Wry[k] = T(0);
                 }
-                if constexpr (SPLIT == 1 && sizeof(T) == 8) {
+                if constexpr (SPLIT == 1) {
                     ok = noneq_states<T, 1, T>(o[3], o[4], T(P.gamma), T(P.K), T(par.iN), ne, in.Wlx, in.Wly, in.Wrx,
                                                in.Wry);
-                } else if constexpr (SPLIT == 1) {
-                    // both states on this lane, their inputs, shares and
-                    // sides passed through opaque() as the lane pair passes
-                    // them through its exchange
-                    T Wa[4], Wb[4], Na[4], Nb[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        Wa[k] = opaque(o[3][k]); Wb[k] = opaque(o[4][k]);
-                        Na[k] = opaque(in.Wlx[k]); Nb[k] = opaque(in.Wrx[k]);
-                    }
-                    NeSide<T, 1, T> l, r;
-                    const bool okl = noneq_side<T, 1, T>(Wa, opaque(0), T(P.gamma), T(P.K), T(par.iN), l, Na, in.Wly);
-                    const bool okr = noneq_side<T, 1, T>(Wb, opaque(1), T(P.gamma), T(P.K), T(par.iN), r, Nb, in.Wry);
-                    ok = okl && okr;
-                    ne_opaque32(l);
-                    ne_opaque32(r);
-                    noneq_combine<T, 1, T>(l, r, ne);
                 } else {
                     // this lane's state (selected element by element, so that
                     // the arrays stay in registers), then the partner's share
@@ -625,10 +678,7 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
 #pragma unroll
                     for (int k = 0; k < 4; ++k) { Ws[k] = side ? o[4][k] : o[3][k]; Wn[k] = side ? in.Wrx[k] : in.Wlx[k]; }
                     NeSide<T, 1, T> own, l, r;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) { Ws[k] = opaque32(Ws[k]); Wn[k] = opaque32(Wn[k]); }
                     const bool oko = noneq_side<T, 1, T>(Ws, side, T(P.gamma), T(P.K), T(par.iN), own, Wn, in.Wly);
-                    ne_opaque32(own);
                     const bool okp = __builtin_amdgcn_update_dpp(0, (int)oko, 0xB1, 0xF, 0xF, false) != 0;
                     ok = oko && okp;
                     // left share first, whichever lane holds it
@@ -679,67 +729,157 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
         const int i = tl.start + t;
         const bool live = (t < NF - 1) && (i < P.nx);
         const double idx = 1.0 / P.dx;
-        double wn[3] = {0.0, 0.0, 0.0};
-        if (live) {
-            const long long c = P.coff + i;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double dL = -(sh_FdL[k][t + 1] - sh_FdL[k][t]) * idx;
-                const double slope = (sh_Wf[k][t + 1] - sh_Wf[k][t]) * idx;
-                if (STAGE == 1) {
-                    const double L = -(sh_FL[k][t + 1] - sh_FL[k][t]) * idx;
-                    const double w = sh_cell[k][t];
-                    W[((size_t)wr * 3 + k) * Ntot + c] = msmd_half(w, L, dL, dt);
-                    PW[k * Ntot + c] = msmd_pred(w, L, dL, dt);
-                } else {
-                    wn[k] = msmd_corr(sh_cell[k][t], dL, dt);
-                    W[((size_t)wr * 3 + k) * Ntot + c] = wn[k];
-                }
-                Wx[((size_t)wr * 3 + k) * Ntot + c] = slope;
-            }
-        }
-        if (STAGE == 2) {
-            double sp = 0.0;
-            if (live) {
-                const double rho = wn[0], U = wn[1] / rho;
-                const double p = (P.gamma - 1.0) * (wn[2] - 0.5 * rho * U * U);
-                if (!(rho > 0.0) || !(p > 0.0)) atomicOr(&S.err, 1);
-                else sp = (fabs(U) + sqrt(P.gamma * p / rho)) * idx;
-            }
-            block_max_atomic(sp, &S.smax);
-        }
+        const double sp = live ? update_cell_1d<STAGE>(
+                                     P, S, P.coff + i, wr, dt, idx,
+                                     [&](int q, int k, int s) {
+                                         return q == 0 ? sh_FL[k][t + s] : (q == 1 ? sh_FdL[k][t + s] : sh_Wf[k][t + s]);
+                                     },
+                                     [&](int k) { return sh_cell[k][t]; }, W, Wx, PW, Ntot)
+                               : 0.0;
+        if (STAGE == 2) block_max_atomic(sp, &S.smax);
         __syncthreads(); // LDS reuse by the next item
     }
-    if (STAGE == 2) {
-        // the last workgroup to finish commits the step for every problem,
-        // sets the next dt and builds the next step's work list
-        __shared__ int sh_last, sh_stopped;
-        __shared__ int sh_scan[BLK];
-        // Release/acquire pairing of the "last workgroup" pattern: every
-        // workgroup's writes of this launch (cell states, the error flags,
-        // the signal-speed maxima) are made visible device-wide by the
-        // release fence before its done-counter increment; the workgroup
-        // that sees the final count issues the acquire fence below before
-        // it reads them.
-        __syncthreads();
-        if (t == 0) {
-            __threadfence(); // release
-            sh_last = atomicAdd(&ctr[2], 1u) == (unsigned)nwg - 1;
-            sh_stopped = 0;
-        }
-        __syncthreads();
-        if (sh_last) {
-            __threadfence(); // acquire: no stale cached copies of the problem states
-            bool stopped = false;
-            for (int p = t; p < nprob; p += BLK) stopped |= finish_problem(PP[p], PS[p], 1, 3);
-            if (stopped) atomicOr(&sh_stopped, 1);
-            if (t < 3) ctr[t] = 0u;
-            __threadfence();
-            __syncthreads();
-            // the list changes only when a problem has stopped
-            if (sh_stopped) compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
+    if (STAGE == 2) commit_if_last<BLK>(PP, PS, nprob, ctr, nwg, all, first, count, items, nitems_p);
+}
+
+// ---------------------------------------------------------------------------
+// Batched 1-D, FP64, three-phase form of a stage: the fused kernel's face
+// reconstruction, interface point and cell update as three launches over
+// the same 255-cell work items (one workgroup per item, workgroups beyond
+// the active items leaving at once), with the face values passed through
+// HBM.  Each phase fits in 256 registers, so two waves share a SIMD, where
+// the fused FP64 kernel (366 registers) runs one; the results are those of
+// the fused kernel bit for bit.  Face buffers (F faces, component stride F):
+//   R1[21]: quantity q (face_recon order) of component k in row 3 q + k',
+//           k' = 0, 1, 2 for the components rho, rho U, rho E;
+//   R2[9]:  rows 0-2 F^L, 3-5 its time derivative, 6-8 the face state W_f.
+// ---------------------------------------------------------------------------
+constexpr int kPhaseBlk = 256;
+
+// Phase 1: gather and reconstruction of the item's own faces (all but its
+// last face, plus the problem's last face).
+template <int STAGE>
+__global__ void __launch_bounds__(kPhaseBlk, 2)
+    face1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
+                  const int* __restrict__ nitems_p, const double* __restrict__ W, const double* __restrict__ Wx,
+                  double* __restrict__ R1, long long Ntot, long long F)
+{
+    if ((int)blockIdx.x >= *nitems_p) return;
+    const Tile tl = items[blockIdx.x];
+    const ProbParam& P = PP[tl.p];
+    ProbState& S = PS[tl.p];
+    if (!S.active) return;
+    const int j = threadIdx.x, f = tl.start + j;
+    if (f > P.nx || (j == kPhaseBlk - 1 && f != P.nx)) return;
+    const int cur = S.cur, rd = STAGE == 1 ? cur : (cur == 2 ? 0 : cur + 1);
+    double Wk[4][4], Dk[4][4];
+    const bool gok = gather_face_1d(P, W + (size_t)rd * 3 * Ntot + P.coff, Wx + (size_t)rd * 3 * Ntot + P.coff, Ntot, f,
+                                    Wk, Dk);
+    double* r = R1 + P.foff + f;
+    auto put = [&](int q, int k, auto v) {
+        if (k != 2) r[(q * 3 + (k == 3 ? 2 : k)) * F] = double(v);
+    };
+    const bool ok = gok && ((P.order == 8) ? face_recon<double, 1, 8, double, double>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
+                                           : face_recon<double, 1, 6, double, double>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put));
+    if (!ok) atomicOr(&S.err, 1);
+}
+
+// Phase 2: the interface point of each own face and the MSMD face values.
+template <int STAGE>
+__global__ void __launch_bounds__(kPhaseBlk, 2)
+    point1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
+                   const int* __restrict__ nitems_p, const double* __restrict__ R1, double* __restrict__ R2,
+                   double* __restrict__ Pf, long long F)
+{
+    if ((int)blockIdx.x >= *nitems_p) return;
+    const Tile tl = items[blockIdx.x];
+    const ProbParam& P = PP[tl.p];
+    ProbState& S = PS[tl.p];
+    if (!S.active) return;
+    const int j = threadIdx.x, f = tl.start + j;
+    if (f > P.nx || (j == kPhaseBlk - 1 && f != P.nx)) return;
+    const long long g = P.foff + f;
+    const double dt = S.dt;
+    double o[7][4];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        o[q][0] = R1[(q * 3) * F + g];
+        o[q][1] = R1[(q * 3 + 1) * F + g];
+        o[q][2] = 0.0;
+        o[q][3] = R1[(q * 3 + 2) * F + g];
+    }
+    PointIn<double> in;
+    PointOut<double> out;
+    NonEq<double, 1, double> ne;
+    const PointPar par = point_par<1>(P.gamma, P.K, P.mu, dt);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        in.W0x[k] = o[1][k]; in.W0xx[k] = o[2][k];
+        in.W0y[k] = in.W0xy[k] = in.W0yy[k] = 0.0;
+        in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
+        in.Wly[k] = in.Wry[k] = 0.0;
+    }
+    bool ok = noneq_states<double, 1, double>(o[3], o[4], P.gamma, P.K, par.iN, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+    if (ok) ok = gks_point<double, 1, double>(par, in, P.recon ? ne.Xs : o[0], ne, out);
+    if (!ok) {
+        atomicOr(&S.err, 1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = 0.0;
+    }
+    const int slot[3] = {0, 1, 3};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int sl = slot[k];
+        R2[(3 + k) * F + g] = out.FdL[sl];
+        if (STAGE == 1) {
+            const double s0 = out.S0[sl], s1 = out.S1[sl], s2 = out.S2[sl];
+            R2[k * F + g] = out.FL[sl];
+            R2[(6 + k) * F + g] = msmd_half(s0, s1, s2, dt);
+            Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
+        } else {
+            R2[(6 + k) * F + g] = msmd_corr(Pf[k * F + g], out.S2[sl], dt);
         }
     }
+}
+
+// Phase 3: the item's cells; after stage 2 their signal speeds.  The step
+// is committed by commit1d_kernel, launched after it: with one workgroup
+// per item, a last-workgroup commit here would cost every workgroup a
+// device-wide release fence and an atomic on one counter.
+template <int STAGE>
+__global__ void __launch_bounds__(kPhaseBlk)
+    cell1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
+                  const int* __restrict__ nitems_p, double* __restrict__ W, double* __restrict__ Wx,
+                  double* __restrict__ PW, const double* __restrict__ R2, long long Ntot, long long F)
+{
+    if ((int)blockIdx.x >= *nitems_p) return;
+    const Tile tl = items[blockIdx.x];
+    const ProbParam& P = PP[tl.p];
+    ProbState& S = PS[tl.p];
+    if (!S.active) return;
+    const int t = threadIdx.x, i = tl.start + t;
+    const bool live = t < kPhaseBlk - 1 && i < P.nx;
+    const int cur = S.cur, half = cur == 2 ? 0 : cur + 1, next = cur == 0 ? 2 : cur - 1;
+    const int wr = STAGE == 1 ? half : next;
+    const double dt = S.dt, idx = 1.0 / P.dx;
+    const long long c = P.coff + i, g = P.foff + i;
+    const double sp =
+        live ? update_cell_1d<STAGE>(
+                   P, S, c, wr, dt, idx, [&](int q, int k, int s) { return R2[(3 * q + k) * F + g + s]; },
+                   [&](int k) { return STAGE == 1 ? W[((size_t)cur * 3 + k) * Ntot + c] : PW[k * Ntot + c]; }, W, Wx,
+                   PW, Ntot)
+             : 0.0;
+    if (STAGE == 2) block_max_atomic(sp, &S.smax);
+}
+
+// The step's commit after the three-phase stages: one workgroup, in the
+// role of the last workgroup of the fused kernel's second stage.
+__global__ void __launch_bounds__(kPhaseBlk)
+    commit1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, Tile* items, int* nitems_p,
+                    unsigned* __restrict__ ctr, int nprob, const Tile* __restrict__ all, const int* __restrict__ first,
+                    const int* __restrict__ count)
+{
+    commit_if_last<kPhaseBlk>(PP, PS, nprob, ctr, 1, all, first, count, items, nitems_p);
 }
 
 // maximum signal speed of the current state (start of a run)

@@ -16,6 +16,10 @@
 #define GKS_HD __host__ __device__ __forceinline__
 
 namespace gks {
+// Multiply-adds are contracted into FMAs only within one statement, so a
+// function rounds the same way wherever it is inlined (the single-lane,
+// lane-pair and three-phase forms of the batched 1-D step agree bit for bit).
+#pragma clang fp contract(on)
 
 // WENO-Z regularisation (reading of Sec. 3.3: 1e-6 reproduces Tables 3-4)
 constexpr double kWenoEps = 1e-6;
@@ -49,26 +53,6 @@ template <> GKS_HD double quot<double>(double a, double b) { return a * drcp(b);
 template <typename T> GKS_HD T fmadd(T a, T b, T c) { return a * b + c; }
 template <> GKS_HD float fmadd<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <> GKS_HD double fmadd<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// A value the compiler must treat as unknown (an empty asm statement that
-// claims to change it; no instruction): code on either side of it is then
-// contracted and shared in the same way whatever surrounds it, so that two
-// kernels that compute a result through different routes round it alike.
-__device__ __forceinline__ float opaque(float x) { asm volatile("" : "+v"(x)); return x; }
-__device__ __forceinline__ double opaque(double x) { asm volatile("" : "+v"(x)); return x; }
-__device__ __forceinline__ int opaque(int x) { asm volatile("" : "+v"(x)); return x; }
-__host__ inline float opaque(float x) { return x; }
-__host__ inline double opaque(double x) { return x; }
-__host__ inline int opaque(int x) { return x; }
-// opaque() for FP32 values only: the lane-pair and single-lane forms of the
-// 1-D face compile to the same FP64 rounding without the barrier, while
-// their FP32 forms differ unless it is there
-template <typename T>
-GKS_HD T opaque32(T x)
-{
-    if constexpr (sizeof(T) == 4) return opaque(x);
-    else return x;
-}
 
 // The value of the other lane of a lane pair (lanes 2j and 2j + 1): a DPP
 // quad permutation (1, 0, 3, 2), one VALU move per 32 bits.
@@ -907,22 +891,6 @@ GKS_HD bool noneq_side(const D* Ws, int side, D gamma, D K, D iN, NeSide<D, DIM,
         }
     }
     return ok;
-}
-
-// every field of a share through opaque32()
-template <typename D, int DIM, typename T>
-__device__ __forceinline__ void ne_opaque32(NeSide<D, DIM, T>& o)
-{
-    o.p = opaque32(o.p);
-    o.rs = opaque32(o.rs);
-    o.rt = opaque32(o.rt);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        o.h0[k] = opaque32(o.h0[k]);
-        o.h1[k] = opaque32(o.h1[k]);
-        o.h2[k] = opaque32(o.h2[k]);
-        o.h3[k] = opaque32(o.h3[k]);
-    }
 }
 
 // The two states' sums, left share first: X = rs_r h_r + rs_l h_l (fused).

@@ -21,11 +21,11 @@ def gks():
     return g
 
 
-def run(probs, steps=None, tune=None, graph=None, precision=0, split=None):
+def run(probs, steps=None, tune=None, graph=None, precision=0, split=None, phases=None):
     g = gks()
-    old = {k: os.environ.get(k) for k in ("GKS_TUNE", "GKS_GRAPH", "GKS_SPLIT")}
+    old = {k: os.environ.get(k) for k in ("GKS_TUNE", "GKS_GRAPH", "GKS_SPLIT", "GKS_PHASES")}
     try:
-        for k, v in (("GKS_TUNE", tune), ("GKS_GRAPH", graph), ("GKS_SPLIT", split)):
+        for k, v in (("GKS_TUNE", tune), ("GKS_GRAPH", graph), ("GKS_SPLIT", split), ("GKS_PHASES", phases)):
             if v is None:
                 os.environ.pop(k, None)
             else:
@@ -85,22 +85,40 @@ def test_lane_pair_steps_bit_identical(batch, precision):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]
 
 
-def test_lane_pair_switch_during_a_run():
-    """The 256-problem uneven batch: its active work items fall to half the
-    CU count as the small problems finish, and the automatic switch to the
-    lane-pair kernel leaves every problem bit-identical to a run without it."""
+def test_three_phase_steps_bit_identical(batch):
+    """FP64 three-phase steps (face, point and cell kernels, the face values
+    through HBM) reproduce the fused kernel bit for bit: on for the whole
+    run against off; the FP32-mixed path never uses them."""
+    ref, cfg0 = run(batch, split="0", phases="0")
+    got, cfg = run(batch, split="0", phases="2")
+    assert "three-phase steps off" in cfg0 and "three-phase steps on" in cfg
+    for a, b in zip(ref, got):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]
+    _, cfgm = run(batch, steps=3, precision=1, phases="2")
+    assert "three-phase steps off (never)" in cfgm
+
+
+def test_step_form_switches_during_a_run():
+    """The 256-problem uneven batch: three-phase steps while its work items
+    fill the CUs, fused steps below that, lane-pair steps once the items are
+    at most half the CUs; every problem ends bit-identical to a run in the
+    fused form throughout."""
     g = gks()
     probs = wl.batch_1d(t_end=0.02)
 
-    def go(split):
-        old = os.environ.get("GKS_SPLIT")
+    def go(split, phases):
+        old = {k: os.environ.get(k) for k in ("GKS_SPLIT", "GKS_PHASES")}
         os.environ["GKS_SPLIT"] = split
+        os.environ["GKS_PHASES"] = phases
         try:
             S = g.Solver(probs)
             # three problems of this batch meet a non-physical state in
             # their first steps and stop; the others run on
-            # calls of 100 steps, so that the switch (decided at each call
-            # from the work items left after the previous one) comes while
+            S.step(1, raise_on_error=False)
+            S.step(1, raise_on_error=False)
+            cfg_first = S.launch_config()
+            # calls of 100 steps, so that the switches (decided at each call
+            # from the work items left after the previous one) come while
             # the largest problems still run
             while S.step(100, raise_on_error=False) != 0:
                 pass
@@ -108,15 +126,18 @@ def test_lane_pair_switch_during_a_run():
             cfg = S.launch_config()
             S.close()
         finally:
-            if old is None:
-                os.environ.pop("GKS_SPLIT", None)
-            else:
-                os.environ["GKS_SPLIT"] = old
-        return out, cfg
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        return out, cfg_first, cfg
 
-    ref, cfg0 = go("0")
-    got, cfg = go("1")
-    assert "lane-pair steps off" in cfg0 and "lane-pair steps on" in cfg
+    ref, _, cfg0 = go("0", "0")
+    got, cfg1, cfg = go("1", "1")
+    assert "lane-pair steps off" in cfg0 and "three-phase steps off" in cfg0
+    assert "three-phase steps on" in cfg1
+    assert "lane-pair steps on" in cfg and "three-phase steps off" in cfg
     assert sum(r[5] == g.GKS_ENONPHYS for r in ref) == 3
     for a, b in zip(ref, got):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]

@@ -119,6 +119,34 @@ def test_inflow_and_batch_of_boundary_kinds():
         check(p, r, oracle_run(p))
 
 
+def test_boundary_kinds_in_three_phase_steps():
+    """The batch of boundary kinds (inflow, characteristic ends, walls with
+    the blast wave's positivity fallbacks, extrapolation) in FP64
+    three-phase steps (face, point and cell kernels) equals the fused steps
+    bit for bit."""
+    import os
+    a = wl.riemann_1d(60, *wl.SOD, t_end=0.05)
+    a.bc = (3, 1, 0, 0)
+    a.bc_state[0, 0] = [1.0, 1.5, 0.0, 2.5 + 0.5 * 1.5 ** 2]
+    probs = [a, wl.acoustic_pulse_1d(50, bc=(5, 5, 0, 0), t_end=0.2), wl.blast_wave_1d(200, t_end=0.5),
+             wl.riemann_1d(40, *wl.SOD, t_end=0.05)]
+    old = {k: os.environ.get(k) for k in ("GKS_SPLIT", "GKS_PHASES")}
+    try:
+        os.environ["GKS_SPLIT"] = "0"
+        os.environ["GKS_PHASES"] = "0"
+        ref = gpu_run(probs)
+        os.environ["GKS_PHASES"] = "2"
+        got = gpu_run(probs)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for p, r, q in zip(probs, ref, got):
+        assert np.array_equal(r[0], q[0]) and np.array_equal(r[1], q[1]) and r[4] == q[4] and r[5] == q[5], p.name
+
+
 def test_split_sides_2d():
     """Split sides (inflow below a switch point, wall or a second state
     beyond) on a small box, against the oracle, including the limits where
