@@ -68,7 +68,7 @@ struct gks_handle {
     // pairs share a face, on tiles of 127 cells (GKS_SPLIT: 0 never,
     // 1 automatic (default), 2 always)
     int split = 0, split_mode = 1;
-    // three-phase steps (FP64): while the active 255-cell work items are
+    // three-phase steps: while the active 255-cell work items are
     // at least kPhaseItemsPerCU per CU, each stage runs as the face, point
     // and cell kernels, two waves per SIMD (GKS_PHASES: 0 never,
     // 1 automatic (default), 2 always)
@@ -260,14 +260,15 @@ template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
     const int G = h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu);
     record(h, st, 0, true);
     if (h->phases) {
-        // FP64 only; one workgroup per item of the full list
+        // one workgroup per item of the full list; R1 holds T values
         double* W = h->W;
         double* X = h->Wx;
-        gks::face1d_kernel<1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->R1, h->Ntot, h->F);
-        gks::point1d_kernel<1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, h->R1, h->R2, h->Pf, h->F);
+        T* R1 = reinterpret_cast<T*>(h->R1);
+        gks::face1d_kernel<T, 1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, R1, h->Ntot, h->F);
+        gks::point1d_kernel<T, 1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, R1, h->R2, h->Pf, h->F);
         gks::cell1d_kernel<1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->PW, h->R2, h->Ntot, h->F);
-        gks::face1d_kernel<2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->R1, h->Ntot, h->F);
-        gks::point1d_kernel<2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, h->R1, h->R2, h->Pf, h->F);
+        gks::face1d_kernel<T, 2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, R1, h->Ntot, h->F);
+        gks::point1d_kernel<T, 2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, R1, h->R2, h->Pf, h->F);
         gks::cell1d_kernel<2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->PW, h->R2, h->Ntot, h->F);
         gks::commit1d_kernel<<<1, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
     } else if (h->split) {
@@ -665,7 +666,7 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
     if (const char* g = getenv("GKS_GRAPH")) h->use_graph = atoi(g) != 0;
     if (const char* g = getenv("GKS_SPLIT")) h->split_mode = std::min(std::max(atoi(g), 0), 2);
     if (const char* g = getenv("GKS_PHASES")) h->phases_mode = std::min(std::max(atoi(g), 0), 2);
-    if (precision != GKS_PREC_FP64 || dim != 1) h->phases_mode = 0;
+    if (dim != 1) h->phases_mode = 0;
     h->last_active.assign(nprob, 1);
     TRY(([&]() -> int {
         HIP_TRY(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
@@ -918,7 +919,7 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
                 if (h->last_active[p]) items += h->hcount[bn][p];
             want = 2 * items <= h->ncu;
         }
-        // three-phase steps (FP64) while the 255-cell items fill the CUs
+        // three-phase steps while the 255-cell items fill the CUs
         // several times; the lane-pair steps take precedence
         int wantp = 0;
         if (!want && h->phases_mode != 0) {

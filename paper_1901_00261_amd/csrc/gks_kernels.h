@@ -743,26 +743,28 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
 }
 
 // ---------------------------------------------------------------------------
-// Batched 1-D, FP64, three-phase form of a stage: the fused kernel's face
+// Batched 1-D, three-phase form of a stage: the fused kernel's face
 // reconstruction, interface point and cell update as three launches over
 // the same 255-cell work items (one workgroup per item, workgroups beyond
 // the active items leaving at once), with the face values passed through
-// HBM.  Each phase fits in 256 registers, so two waves share a SIMD, where
-// the fused FP64 kernel (366 registers) runs one; the results are those of
-// the fused kernel bit for bit.  Face buffers (F faces, component stride F):
+// HBM.  In FP64 each phase fits in 256 registers, so two waves share a
+// SIMD, where the fused kernel (366 registers) runs one; in FP32 the phases
+// run three or more waves per SIMD, the fused kernel two.  The results are
+// those of the fused kernel bit for bit.  Face buffers (F faces, component
+// stride F):
 //   R1[21]: quantity q (face_recon order) of component k in row 3 q + k',
-//           k' = 0, 1, 2 for the components rho, rho U, rho E;
+//           k' = 0, 1, 2 for the components rho, rho U, rho E (type T);
 //   R2[9]:  rows 0-2 F^L, 3-5 its time derivative, 6-8 the face state W_f.
 // ---------------------------------------------------------------------------
 constexpr int kPhaseBlk = 256;
 
 // Phase 1: gather and reconstruction of the item's own faces (all but its
-// last face, plus the problem's last face).
-template <int STAGE>
+// last face, plus the problem's last face), stored in T.
+template <typename T, int STAGE>
 __global__ void __launch_bounds__(kPhaseBlk, 2)
     face1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
                   const int* __restrict__ nitems_p, const double* __restrict__ W, const double* __restrict__ Wx,
-                  double* __restrict__ R1, long long Ntot, long long F)
+                  T* __restrict__ R1, long long Ntot, long long F)
 {
     if ((int)blockIdx.x >= *nitems_p) return;
     const Tile tl = items[blockIdx.x];
@@ -775,20 +777,21 @@ __global__ void __launch_bounds__(kPhaseBlk, 2)
     double Wk[4][4], Dk[4][4];
     const bool gok = gather_face_1d(P, W + (size_t)rd * 3 * Ntot + P.coff, Wx + (size_t)rd * 3 * Ntot + P.coff, Ntot, f,
                                     Wk, Dk);
-    double* r = R1 + P.foff + f;
+    T* r = R1 + P.foff + f;
     auto put = [&](int q, int k, auto v) {
-        if (k != 2) r[(q * 3 + (k == 3 ? 2 : k)) * F] = double(v);
+        if (k != 2) r[(q * 3 + (k == 3 ? 2 : k)) * F] = T(v);
     };
-    const bool ok = gok && ((P.order == 8) ? face_recon<double, 1, 8, double, double>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
-                                           : face_recon<double, 1, 6, double, double>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put));
+    const bool ok = gok && ((P.order == 8) ? face_recon<T, 1, 8, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put)
+                                           : face_recon<T, 1, 6, double, T>(Wk, Dk, P.dx, P.gamma, P.recon != 0, put));
     if (!ok) atomicOr(&S.err, 1);
 }
 
-// Phase 2: the interface point of each own face and the MSMD face values.
-template <int STAGE>
+// Phase 2: the interface point of each own face (in T) and the MSMD face
+// values (FP64).
+template <typename T, int STAGE>
 __global__ void __launch_bounds__(kPhaseBlk, 2)
     point1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
-                   const int* __restrict__ nitems_p, const double* __restrict__ R1, double* __restrict__ R2,
+                   const int* __restrict__ nitems_p, const T* __restrict__ R1, double* __restrict__ R2,
                    double* __restrict__ Pf, long long F)
 {
     if ((int)blockIdx.x >= *nitems_p) return;
@@ -800,44 +803,44 @@ __global__ void __launch_bounds__(kPhaseBlk, 2)
     if (f > P.nx || (j == kPhaseBlk - 1 && f != P.nx)) return;
     const long long g = P.foff + f;
     const double dt = S.dt;
-    double o[7][4];
+    T o[7][4];
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
         o[q][0] = R1[(q * 3) * F + g];
         o[q][1] = R1[(q * 3 + 1) * F + g];
-        o[q][2] = 0.0;
+        o[q][2] = T(0);
         o[q][3] = R1[(q * 3 + 2) * F + g];
     }
-    PointIn<double> in;
-    PointOut<double> out;
-    NonEq<double, 1, double> ne;
+    PointIn<T> in;
+    PointOut<T> out;
+    NonEq<T, 1, T> ne;
     const PointPar par = point_par<1>(P.gamma, P.K, P.mu, dt);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         in.W0x[k] = o[1][k]; in.W0xx[k] = o[2][k];
-        in.W0y[k] = in.W0xy[k] = in.W0yy[k] = 0.0;
+        in.W0y[k] = in.W0xy[k] = in.W0yy[k] = T(0);
         in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
-        in.Wly[k] = in.Wry[k] = 0.0;
+        in.Wly[k] = in.Wry[k] = T(0);
     }
-    bool ok = noneq_states<double, 1, double>(o[3], o[4], P.gamma, P.K, par.iN, ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
-    if (ok) ok = gks_point<double, 1, double>(par, in, P.recon ? ne.Xs : o[0], ne, out);
+    bool ok = noneq_states<T, 1, T>(o[3], o[4], T(P.gamma), T(P.K), T(par.iN), ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+    if (ok) ok = gks_point<T, 1, T>(par, in, P.recon ? ne.Xs : o[0], ne, out);
     if (!ok) {
         atomicOr(&S.err, 1);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = 0.0;
+        for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = T(0);
     }
     const int slot[3] = {0, 1, 3};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int sl = slot[k];
-        R2[(3 + k) * F + g] = out.FdL[sl];
+        R2[(3 + k) * F + g] = double(out.FdL[sl]);
         if (STAGE == 1) {
-            const double s0 = out.S0[sl], s1 = out.S1[sl], s2 = out.S2[sl];
-            R2[k * F + g] = out.FL[sl];
+            const double s0 = double(out.S0[sl]), s1 = double(out.S1[sl]), s2 = double(out.S2[sl]);
+            R2[k * F + g] = double(out.FL[sl]);
             R2[(6 + k) * F + g] = msmd_half(s0, s1, s2, dt);
             Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
         } else {
-            R2[(6 + k) * F + g] = msmd_corr(Pf[k * F + g], out.S2[sl], dt);
+            R2[(6 + k) * F + g] = msmd_corr(Pf[k * F + g], double(out.S2[sl]), dt);
         }
     }
 }

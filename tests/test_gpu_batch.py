@@ -85,17 +85,16 @@ def test_lane_pair_steps_bit_identical(batch, precision):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]
 
 
-def test_three_phase_steps_bit_identical(batch):
-    """FP64 three-phase steps (face, point and cell kernels, the face values
+@pytest.mark.parametrize("precision", [0, 1])
+def test_three_phase_steps_bit_identical(batch, precision):
+    """Three-phase steps (face, point and cell kernels, the face values
     through HBM) reproduce the fused kernel bit for bit: on for the whole
-    run against off; the FP32-mixed path never uses them."""
-    ref, cfg0 = run(batch, split="0", phases="0")
-    got, cfg = run(batch, split="0", phases="2")
+    run against off."""
+    ref, cfg0 = run(batch, split="0", phases="0", precision=precision)
+    got, cfg = run(batch, split="0", phases="2", precision=precision)
     assert "three-phase steps off" in cfg0 and "three-phase steps on" in cfg
     for a, b in zip(ref, got):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]
-    _, cfgm = run(batch, steps=3, precision=1, phases="2")
-    assert "three-phase steps off (never)" in cfgm
 
 
 def test_step_form_switches_during_a_run():
