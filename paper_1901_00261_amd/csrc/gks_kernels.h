@@ -513,41 +513,54 @@ __device__ __forceinline__ double update_cell_1d(const ProbParam& P, ProbState& 
     return (fabs(U) + sqrt(P.gamma * p / rho)) * idx;
 }
 
+// Commit of a 1-D step by one workgroup: the step for every problem, the
+// next dt, the counters reset and, when a problem has stopped, the work
+// list rebuilt.
+template <int BLK>
+__device__ __forceinline__ void commit_step_block(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                  int nprob, unsigned* __restrict__ ctr, const Tile* __restrict__ all,
+                                                  const int* __restrict__ first, const int* __restrict__ count,
+                                                  Tile* items, int* nitems_p)
+{
+    __shared__ int sh_stopped;
+    __shared__ int sh_scan[BLK];
+    const int t = threadIdx.x;
+    if (t == 0) sh_stopped = 0;
+    __syncthreads();
+    bool stopped = false;
+    for (int p = t; p < nprob; p += BLK) stopped |= finish_problem(PP[p], PS[p], 1, 3);
+    if (stopped) atomicOr(&sh_stopped, 1);
+    if (t < 3) ctr[t] = 0u;
+    __threadfence();
+    __syncthreads();
+    // the list changes only when a problem has stopped
+    if (sh_stopped) compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
+}
+
 // End of a step's second stage (1-D): the last of the nwg workgroups taking
-// part commits the step for every problem, sets the next dt, resets the
-// counters and, when a problem has stopped, rebuilds the work list.
-// Release/acquire pairing of the "last workgroup" pattern: every
-// workgroup's writes of the launch (cell states, the error flags, the
-// signal-speed maxima) are made visible device-wide by the release fence
-// before its done-counter increment; the workgroup that sees the final
-// count issues the acquire fence before it reads them.  Called by every
-// thread of the workgroups taking part.
+// part commits the step.  Release/acquire pairing of the "last workgroup"
+// pattern: every workgroup's writes of the launch (cell states, the error
+// flags, the signal-speed maxima) are made visible device-wide by the
+// release fence before its done-counter increment; the workgroup that sees
+// the final count issues the acquire fence before it reads them.  Called by
+// every thread of the workgroups taking part.
 template <int BLK>
 __device__ __forceinline__ void commit_if_last(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob,
                                                unsigned* __restrict__ ctr, int nwg, const Tile* __restrict__ all,
                                                const int* __restrict__ first, const int* __restrict__ count,
                                                Tile* items, int* nitems_p)
 {
-    __shared__ int sh_last, sh_stopped;
-    __shared__ int sh_scan[BLK];
+    __shared__ int sh_last;
     const int t = threadIdx.x;
     __syncthreads();
     if (t == 0) {
         __threadfence(); // release
         sh_last = atomicAdd(&ctr[2], 1u) == (unsigned)nwg - 1;
-        sh_stopped = 0;
     }
     __syncthreads();
     if (sh_last) {
         __threadfence(); // acquire: no stale cached copies of the problem states
-        bool stopped = false;
-        for (int p = t; p < nprob; p += BLK) stopped |= finish_problem(PP[p], PS[p], 1, 3);
-        if (stopped) atomicOr(&sh_stopped, 1);
-        if (t < 3) ctr[t] = 0u;
-        __threadfence();
-        __syncthreads();
-        // the list changes only when a problem has stopped
-        if (sh_stopped) compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
+        commit_step_block<BLK>(PP, PS, nprob, ctr, all, first, count, items, nitems_p);
     }
 }
 
@@ -567,7 +580,7 @@ __device__ __forceinline__ void commit_if_last(const ProbParam* __restrict__ PP,
 // list for the next step, so a step is two launches.  Faces owned by the tile (all but its last face, plus the
 // problem's last face) carry the MSMD partial Pf from stage 1 to stage 2.
 // ---------------------------------------------------------------------------
-template <typename T, int STAGE, int BLK, int SPLIT = 1>
+template <typename T, int STAGE, int BLK, int SPLIT = 1, bool COMMIT = true>
 __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
                                                       Tile* items, int* nitems_p,
                                                       unsigned* __restrict__ ctr, double* __restrict__ W,
@@ -739,7 +752,7 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
         if (STAGE == 2) block_max_atomic(sp, &S.smax);
         __syncthreads(); // LDS reuse by the next item
     }
-    if (STAGE == 2) commit_if_last<BLK>(PP, PS, nprob, ctr, nwg, all, first, count, items, nitems_p);
+    if (STAGE == 2 && COMMIT) commit_if_last<BLK>(PP, PS, nprob, ctr, nwg, all, first, count, items, nitems_p);
 }
 
 // ---------------------------------------------------------------------------
@@ -876,13 +889,14 @@ __global__ void __launch_bounds__(kPhaseBlk)
 }
 
 // The step's commit after the three-phase stages: one workgroup, in the
-// role of the last workgroup of the fused kernel's second stage.
+// role of the last workgroup of the fused kernel's second stage (the
+// launch boundary orders it after the cell kernel's writes).
 __global__ void __launch_bounds__(kPhaseBlk)
     commit1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, Tile* items, int* nitems_p,
                     unsigned* __restrict__ ctr, int nprob, const Tile* __restrict__ all, const int* __restrict__ first,
                     const int* __restrict__ count)
 {
-    commit_if_last<kPhaseBlk>(PP, PS, nprob, ctr, 1, all, first, count, items, nitems_p);
+    commit_step_block<kPhaseBlk>(PP, PS, nprob, ctr, all, first, count, items, nitems_p);
 }
 
 // maximum signal speed of the current state (start of a run)
