@@ -272,23 +272,21 @@ template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
         gks::cell1d_kernel<2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->PW, h->R2, h->Ntot, h->F);
     } else if (h->split) {
         const int Gs = std::min(n, std::max(1, h->gmul) * h->ncu);
-        gks::stage1d_kernel<T, 1, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
-        gks::stage1d_kernel<T, 2, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+        gks::stage1d_kernel<T, 1, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
     } else if (h->blk == 64) {
-        gks::stage1d_kernel<T, 1, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
-        gks::stage1d_kernel<T, 2, 64, 1, false><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+        gks::stage1d_kernel<T, 1, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 64><<<G, 64, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
     } else if (h->blk == 128) {
-        gks::stage1d_kernel<T, 1, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
-        gks::stage1d_kernel<T, 2, 128, 1, false><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+        gks::stage1d_kernel<T, 1, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 128><<<G, 128, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
     } else {
-        gks::stage1d_kernel<T, 1, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
-        gks::stage1d_kernel<T, 2, 256, 1, false><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+        gks::stage1d_kernel<T, 1, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
+        gks::stage1d_kernel<T, 2, 256><<<G, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
     }
     // the step's commit (and the work list's rebuild when a problem has
-    // stopped): by the last workgroup of the lane-pair second stage, by its
-    // own one-workgroup launch after the other forms
-    if (!h->split)
-        gks::commit1d_kernel<<<1, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
+    // stopped) in a one-workgroup launch
+    gks::commit1d_kernel<<<1, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->nprob, h->dItems[b], h->dFirst[b], h->dCount[b]);
     record(h, st, 0, false);
     h->act_list = b;
 }
@@ -876,10 +874,9 @@ void noalloc_steps(const ProbParam* dP, ProbState* dS, Tile* act, int* nact, uns
                    int nsteps, hipStream_t st)
 {
     for (int s = 0; s < nsteps; ++s) {
-        gks::stage1d_kernel<T, 1, kNoAllocBlk><<<G, kNoAllocBlk, 0, st>>>(dP, dS, act, nact, ctr, W, Wx, PW, Pf, N, F,
-                                                                         1, all, first, count);
-        gks::stage1d_kernel<T, 2, kNoAllocBlk><<<G, kNoAllocBlk, 0, st>>>(dP, dS, act, nact, ctr, W, Wx, PW, Pf, N, F,
-                                                                         1, all, first, count);
+        gks::stage1d_kernel<T, 1, kNoAllocBlk><<<G, kNoAllocBlk, 0, st>>>(dP, dS, act, nact, ctr, W, Wx, PW, Pf, N, F);
+        gks::stage1d_kernel<T, 2, kNoAllocBlk><<<G, kNoAllocBlk, 0, st>>>(dP, dS, act, nact, ctr, W, Wx, PW, Pf, N, F);
+        gks::commit1d_kernel<<<1, gks::kPhaseBlk, 0, st>>>(dP, dS, act, nact, ctr, 1, all, first, count);
     }
 }
 

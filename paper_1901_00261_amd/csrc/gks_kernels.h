@@ -537,33 +537,6 @@ __device__ __forceinline__ void commit_step_block(const ProbParam* __restrict__ 
     if (sh_stopped) compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
 }
 
-// End of a step's second stage (1-D): the last of the nwg workgroups taking
-// part commits the step.  Release/acquire pairing of the "last workgroup"
-// pattern: every workgroup's writes of the launch (cell states, the error
-// flags, the signal-speed maxima) are made visible device-wide by the
-// release fence before its done-counter increment; the workgroup that sees
-// the final count issues the acquire fence before it reads them.  Called by
-// every thread of the workgroups taking part.
-template <int BLK>
-__device__ __forceinline__ void commit_if_last(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, int nprob,
-                                               unsigned* __restrict__ ctr, int nwg, const Tile* __restrict__ all,
-                                               const int* __restrict__ first, const int* __restrict__ count,
-                                               Tile* items, int* nitems_p)
-{
-    __shared__ int sh_last;
-    const int t = threadIdx.x;
-    __syncthreads();
-    if (t == 0) {
-        __threadfence(); // release
-        sh_last = atomicAdd(&ctr[2], 1u) == (unsigned)nwg - 1;
-    }
-    __syncthreads();
-    if (sh_last) {
-        __threadfence(); // acquire: no stale cached copies of the problem states
-        commit_step_block<BLK>(PP, PS, nprob, ctr, all, first, count, items, nitems_p);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Batched 1-D: one launch per MSMD stage for all problems.  A work item is
 // a tile of BLK-1 cells of one problem; the workgroup computes the BLK faces
@@ -574,20 +547,18 @@ __device__ __forceinline__ void commit_if_last(const ProbParam* __restrict__ PP,
 // workgroups per CU) or as a plain grid (one workgroup per item); every
 // workgroup reaches the exit.  The item list holds only the problems still
 // active; its length is read from device memory, and workgroups beyond it
-// leave at once.  The last workgroup of the
-// second stage to finish (a done-counter, ctr[2]) commits the step for every
-// problem, resets the counters and, when a problem has stopped, rebuilds the
-// list for the next step, so a step is two launches.  Faces owned by the tile (all but its last face, plus the
-// problem's last face) carry the MSMD partial Pf from stage 1 to stage 2.
+// leave at once.  commit1d_kernel, launched after the second stage, commits
+// the step for every problem, resets the counters and, when a problem has
+// stopped, rebuilds the list for the next step.  Faces owned by the tile
+// (all but its last face, plus the problem's last face) carry the MSMD
+// partial Pf from stage 1 to stage 2.
 // ---------------------------------------------------------------------------
-template <typename T, int STAGE, int BLK, int SPLIT = 1, bool COMMIT = true>
+template <typename T, int STAGE, int BLK, int SPLIT = 1>
 __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
                                                       Tile* items, int* nitems_p,
                                                       unsigned* __restrict__ ctr, double* __restrict__ W,
                                                       double* __restrict__ Wx, double* __restrict__ PW,
-                                                      double* __restrict__ Pf, long long Ntot, long long F,
-                                                      int nprob, const Tile* __restrict__ all,
-                                                      const int* __restrict__ first, const int* __restrict__ count)
+                                                      double* __restrict__ Pf, long long Ntot, long long F)
 {
     __shared__ double sh_FL[3][BLK], sh_FdL[3][BLK], sh_Wf[3][BLK];
     __shared__ double sh_cell[3][BLK], sh_face[3][BLK]; // the item's staged cell and face values
@@ -596,9 +567,7 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
     const int nitems = *nitems_p;
     // Only the first min(grid, items) workgroups take part (the grid is
     // sized for the full list; in a run's tail most problems have stopped):
-    // the others leave before touching a counter.  A workgroup that starts
-    // after the last participant has committed the step reads the rebuilt
-    // list's length, which is no larger, so it leaves as well.
+    // the others leave before touching a counter.
     const int nwg = min((int)gridDim.x, nitems);
     if ((int)blockIdx.x >= nwg) return;
     // A workgroup's first item is its own index; each later one comes from
@@ -752,7 +721,6 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
         if (STAGE == 2) block_max_atomic(sp, &S.smax);
         __syncthreads(); // LDS reuse by the next item
     }
-    if (STAGE == 2 && COMMIT) commit_if_last<BLK>(PP, PS, nprob, ctr, nwg, all, first, count, items, nitems_p);
 }
 
 // ---------------------------------------------------------------------------
