@@ -770,7 +770,7 @@ __global__ void __launch_bounds__(kPhaseBlk, 2)
 // Phase 2: the interface point of each own face (in T) and the MSMD face
 // values (FP64).
 template <typename T, int STAGE>
-__global__ void __launch_bounds__(kPhaseBlk, 2)
+__global__ void __launch_bounds__(kPhaseBlk, 3)
     point1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
                    const int* __restrict__ nitems_p, const T* __restrict__ R1, double* __restrict__ R2,
                    double* __restrict__ Pf, long long F)
