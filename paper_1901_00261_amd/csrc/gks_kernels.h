@@ -827,9 +827,7 @@ __global__ void __launch_bounds__(kPhaseBlk, 3)
 }
 
 // Phase 3: the item's cells; after stage 2 their signal speeds.  The step
-// is committed by commit1d_kernel, launched after it: with one workgroup
-// per item, a last-workgroup commit here would cost every workgroup a
-// device-wide release fence and an atomic on one counter.
+// is committed by commit1d_kernel, launched after it.
 template <int STAGE>
 __global__ void __launch_bounds__(kPhaseBlk)
     cell1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
@@ -856,9 +854,9 @@ __global__ void __launch_bounds__(kPhaseBlk)
     if (STAGE == 2) block_max_atomic(sp, &S.smax);
 }
 
-// The step's commit after the three-phase stages: one workgroup, in the
-// role of the last workgroup of the fused kernel's second stage (the
-// launch boundary orders it after the cell kernel's writes).
+// The step's commit after the second stage of any form: one workgroup (the
+// launch boundary orders it after the stage's writes, so no workgroup of
+// the stage needs a device-wide fence or a done counter).
 __global__ void __launch_bounds__(kPhaseBlk)
     commit1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, Tile* items, int* nitems_p,
                     unsigned* __restrict__ ctr, int nprob, const Tile* __restrict__ all, const int* __restrict__ first,
