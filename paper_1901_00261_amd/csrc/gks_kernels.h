@@ -531,9 +531,10 @@ __device__ __forceinline__ void commit_step_block(const ProbParam* __restrict__ 
     for (int p = t; p < nprob; p += BLK) stopped |= finish_problem(PP[p], PS[p], 1, 3);
     if (stopped) atomicOr(&sh_stopped, 1);
     if (t < 3) ctr[t] = 0u;
-    __threadfence();
     __syncthreads();
-    // the list changes only when a problem has stopped
+    // the list changes only when a problem has stopped; its scan reads the
+    // problems' states in the order in which this workgroup's threads wrote
+    // them (thread t: problems t, t + BLK, ...), so no fence is needed
     if (sh_stopped) compact_items_block<BLK>(PS, nprob, all, first, count, items, nitems_p, sh_scan);
 }
 
