@@ -68,7 +68,7 @@ struct gks_handle {
     // pairs share a face, on tiles of 127 cells (GKS_SPLIT: 0 never,
     // 1 automatic (default), 2 always)
     int split = 0, split_mode = 1;
-    // three-phase steps: while the active 255-cell work items are
+    // three-phase steps (FP64): while the active 255-cell work items are
     // at least kPhaseItemsPerCU per CU, each stage runs as the face, point
     // and cell kernels, two waves per SIMD (GKS_PHASES: 0 never,
     // 1 automatic (default), 2 always)
@@ -926,7 +926,9 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
             long long items = 0;
             for (int p = 0; p < h->nprob; ++p)
                 if (h->last_active[p]) items += h->hcount[2][p];
-            wantp = h->phases_mode == 2 || items >= kPhaseItemsPerCU * h->ncu;
+            // automatic only in FP64: the FP32 fused kernel already runs two
+            // waves per SIMD and is the faster form there
+            wantp = h->phases_mode == 2 || (h->precision == GKS_PREC_FP64 && items >= kPhaseItemsPerCU * h->ncu);
         }
         if (wantp && !h->R1) {
             // the face buffers, allocated on first use; without them the
@@ -1082,7 +1084,10 @@ const char* gks_launch_config(const gks_handle* hc)
                  h->blk, h->gmul, h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu), n, h->split ? "on" : "off",
                  h->split_mode == 0 ? "never" : (h->split_mode == 2 ? "always" : "while items <= CUs / 2"),
                  h->phases ? "on" : "off",
-                 h->phases_mode == 0 ? "never" : (h->phases_mode == 2 ? "always" : "while 255-cell items >= 2 per CU"));
+                 h->phases_mode == 0 ? "never"
+                 : h->phases_mode == 2 ? "always"
+                 : h->precision == GKS_PREC_FP64 ? "while 255-cell items >= 2 per CU"
+                                                  : "FP64 only");
         h->cfg_text = h->tune_note + buf;
     }
     return h->cfg_text.c_str();
