@@ -165,15 +165,15 @@ int gks_cell_updates(const gks_handle* h, int64_t* count);
    is more than 3 % faster).  Each gks_step call chooses the form of its
    steps from the work items still active after the previous call: at most
    half as many 127-cell items as compute units, a lane-pair kernel (two
-   lanes per face); in FP64, at least two 255-cell items per compute unit,
-   three kernels per stage (face reconstruction, interface point, cells);
+   lanes per face); at least two 255-cell items per compute unit, two
+   kernels per stage (face reconstruction; interface point and cells);
    otherwise the tuned kernel.  Every configuration and form performs the
    same arithmetic, so results do not depend on the choice.  Environment:
    GKS_TUNE="BLK:GMUL" forces a configuration, GKS_TUNE_CACHE=<file> caches
    tuning results by problem-set signature, GKS_GRAPH=0 disables the
    hipGraph replay of steps (enabled by default), GKS_SPLIT and GKS_PHASES
    (0 never, 1 automatic, the default, 2 always) control the lane-pair and
-   three-kernel forms. */
+   two-kernel forms. */
 const char* gks_launch_config(const gks_handle* h);
 
 /* For callers that cannot allocate device memory: code under HIP graph

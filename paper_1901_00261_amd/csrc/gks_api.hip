@@ -41,7 +41,7 @@ struct gks_handle {
     double *FL = nullptr, *FdL = nullptr, *Wfs = nullptr, *Pf = nullptr;
     double *FLy = nullptr, *FdLy = nullptr, *Wfsy = nullptr, *Pfy = nullptr;
     void *Rx = nullptr, *Ry = nullptr; // face-row buffers: double (FP64) or float (FP32-mixed)
-    double *R1 = nullptr, *R2 = nullptr; // 1-D three-phase steps: reconstructed faces, face values
+    double* R1 = nullptr; // 1-D two-kernel steps: reconstructed faces
     double* stage = nullptr; // transpose staging
     size_t stage_len = 0;
     std::string err;
@@ -68,10 +68,10 @@ struct gks_handle {
     // pairs share a face, on tiles of 127 cells (GKS_SPLIT: 0 never,
     // 1 automatic (default), 2 always)
     int split = 0, split_mode = 1;
-    // three-phase steps (FP64): while the active 255-cell work items are
-    // at least kPhaseItemsPerCU per CU, each stage runs as the face, point
-    // and cell kernels, two waves per SIMD (GKS_PHASES: 0 never,
-    // 1 automatic (default), 2 always)
+    // two-kernel steps: while the active 255-cell work items are at least
+    // kPhaseItemsPerCU per CU, each stage runs as the face kernel and the
+    // point-and-cell kernel (GKS_PHASES: 0 never, 1 automatic (default),
+    // 2 always)
     int phases = 0, phases_mode = 1;
     int ncu = 256;
     // launch configuration (autotuned): threads per tile, workgroups per CU
@@ -265,11 +265,9 @@ template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
         double* X = h->Wx;
         T* R1 = reinterpret_cast<T*>(h->R1);
         gks::face1d_kernel<T, 1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, R1, h->Ntot, h->F);
-        gks::point1d_kernel<T, 1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, R1, h->R2, h->Pf, h->F);
-        gks::cell1d_kernel<1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->PW, h->R2, h->Ntot, h->F);
+        gks::pointcell1d_kernel<T, 1><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, R1, W, X, h->PW, h->Pf, h->Ntot, h->F);
         gks::face1d_kernel<T, 2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, R1, h->Ntot, h->F);
-        gks::point1d_kernel<T, 2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, R1, h->R2, h->Pf, h->F);
-        gks::cell1d_kernel<2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, W, X, h->PW, h->R2, h->Ntot, h->F);
+        gks::pointcell1d_kernel<T, 2><<<n, gks::kPhaseBlk, 0, st>>>(h->dP, h->dS, it, na, R1, W, X, h->PW, h->Pf, h->Ntot, h->F);
     } else if (h->split) {
         const int Gs = std::min(n, std::max(1, h->gmul) * h->ncu);
         gks::stage1d_kernel<T, 1, 256, 2><<<Gs, 256, 0, st>>>(h->dP, h->dS, it, na, h->ctr, h->W, h->Wx, h->PW, h->Pf, h->Ntot, h->F);
@@ -374,7 +372,7 @@ void drop_graph(gks_handle* h)
     }
 }
 
-// three-phase steps while the active 255-cell work items number at least
+// two-kernel steps while the active 255-cell work items number at least
 // this many per CU (1 to 4 measured within 1 % of each other on the
 // 256-problem batch)
 constexpr int kPhaseItemsPerCU = 2;
@@ -540,7 +538,7 @@ void release(gks_handle* h)
     for (void* p : {(void*)h->dP, (void*)h->dS, (void*)h->dTilesC, (void*)h->W, (void*)h->Wx,
                     (void*)h->Wy, (void*)h->PW, (void*)h->FL, (void*)h->FdL, (void*)h->Wfs, (void*)h->Pf,
                     (void*)h->FLy, (void*)h->FdLy, (void*)h->Wfsy, (void*)h->Pfy, (void*)h->Rx, (void*)h->Ry,
-                    (void*)h->R1, (void*)h->R2, (void*)h->stage})
+                    (void*)h->R1, (void*)h->stage})
         dfree(p);
     drop_graph(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
@@ -919,23 +917,20 @@ int gks_step(gks_handle* h, int32_t max_steps, int32_t* n_active)
                 if (h->last_active[p]) items += h->hcount[bn][p];
             want = 2 * items <= h->ncu;
         }
-        // three-phase steps while the 255-cell items fill the CUs
-        // several times; the lane-pair steps take precedence
+        // two-kernel steps while the 255-cell items fill the CUs several
+        // times; the lane-pair steps take precedence
         int wantp = 0;
         if (!want && h->phases_mode != 0) {
             long long items = 0;
             for (int p = 0; p < h->nprob; ++p)
                 if (h->last_active[p]) items += h->hcount[2][p];
-            // automatic only in FP64: the FP32 fused kernel already runs two
-            // waves per SIMD and is the faster form there
-            wantp = h->phases_mode == 2 || (h->precision == GKS_PREC_FP64 && items >= kPhaseItemsPerCU * h->ncu);
+            wantp = h->phases_mode == 2 || items >= kPhaseItemsPerCU * h->ncu;
         }
         if (wantp && !h->R1) {
-            // the face buffers, allocated on first use; without them the
-            // steps stay fused
-            if (dalloc(&h->R1, 21 * (size_t)h->F) != hipSuccess || dalloc(&h->R2, 9 * (size_t)h->F) != hipSuccess) {
+            // the face buffer, allocated on first use; without it the steps
+            // stay fused
+            if (dalloc(&h->R1, 21 * (size_t)h->F) != hipSuccess) {
                 (void)hipGetLastError();
-                dfree(h->R1);
                 h->R1 = nullptr;
                 h->phases_mode = 0;
                 wantp = 0;
@@ -1080,14 +1075,11 @@ const char* gks_launch_config(const gks_handle* hc)
         const int n = h->nItems[h->blk == 64 ? 0 : (h->blk == 128 ? 1 : 2)];
         char buf[320];
         snprintf(buf, sizeof buf,
-                 "; blk %d gmul %d: %d workgroups for %d work items; lane-pair steps %s (%s); three-phase steps %s (%s)",
+                 "; blk %d gmul %d: %d workgroups for %d work items; lane-pair steps %s (%s); two-kernel steps %s (%s)",
                  h->blk, h->gmul, h->gmul == 0 ? n : std::min(n, h->gmul * h->ncu), n, h->split ? "on" : "off",
                  h->split_mode == 0 ? "never" : (h->split_mode == 2 ? "always" : "while items <= CUs / 2"),
                  h->phases ? "on" : "off",
-                 h->phases_mode == 0 ? "never"
-                 : h->phases_mode == 2 ? "always"
-                 : h->precision == GKS_PREC_FP64 ? "while 255-cell items >= 2 per CU"
-                                                  : "FP64 only");
+                 h->phases_mode == 0 ? "never" : (h->phases_mode == 2 ? "always" : "while 255-cell items >= 2 per CU"));
         h->cfg_text = h->tune_note + buf;
     }
     return h->cfg_text.c_str();

@@ -21,7 +21,7 @@
 namespace gks {
 // Multiply-adds are contracted into FMAs only within one statement, so a
 // function rounds the same way wherever it is inlined (the single-lane,
-// lane-pair and three-phase forms of the batched 1-D step agree bit for bit).
+// lane-pair and two-kernel forms of the batched 1-D step agree bit for bit).
 #pragma clang fp contract(on)
 
 struct ProbParam {
@@ -725,23 +725,22 @@ __global__ void __launch_bounds__(BLK, sizeof(T) == 4 ? 2 : 1) stage1d_kernel(co
 }
 
 // ---------------------------------------------------------------------------
-// Batched 1-D, three-phase form of a stage: the fused kernel's face
-// reconstruction, interface point and cell update as three launches over
-// the same 255-cell work items (one workgroup per item, workgroups beyond
-// the active items leaving at once), with the face values passed through
-// HBM.  In FP64 each phase fits in 256 registers, so two waves share a
-// SIMD, where the fused kernel (366 registers) runs one; in FP32 the phases
-// run three or more waves per SIMD, the fused kernel two.  The results are
-// those of the fused kernel bit for bit.  Face buffers (F faces, component
-// stride F):
-//   R1[21]: quantity q (face_recon order) of component k in row 3 q + k',
-//           k' = 0, 1, 2 for the components rho, rho U, rho E (type T);
-//   R2[9]:  rows 0-2 F^L, 3-5 its time derivative, 6-8 the face state W_f.
+// Batched 1-D, two-kernel form of a stage: the fused kernel split after the
+// face reconstruction, over the same 255-cell work items (one workgroup per
+// item, workgroups beyond the active items leaving at once): face1d_kernel
+// reconstructs the item's own faces into HBM, pointcell1d_kernel evaluates
+// the interface point of every face of the item and updates its cells.
+// Each fits in fewer registers than the fused kernel (FP64: 206 and 168
+// against 366), so more waves share a SIMD.  The results are those of the
+// fused kernel bit for bit.  Face buffer R1[21] (F faces, component stride
+// F): quantity q (face_recon order) of component k in row 3 q + k',
+// k' = 0, 1, 2 for the components rho, rho U, rho E (type T).
 // ---------------------------------------------------------------------------
 constexpr int kPhaseBlk = 256;
 
-// Phase 1: gather and reconstruction of the item's own faces (all but its
-// last face, plus the problem's last face), stored in T.
+// First kernel of the two-kernel form: gather and reconstruction of the
+// item's own faces (all but its last face, plus the problem's last face),
+// stored in T.
 template <typename T, int STAGE>
 __global__ void __launch_bounds__(kPhaseBlk, 2)
     face1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
@@ -768,90 +767,84 @@ __global__ void __launch_bounds__(kPhaseBlk, 2)
     if (!ok) atomicOr(&S.err, 1);
 }
 
-// Phase 2: the interface point of each own face (in T) and the MSMD face
-// values (FP64).
+// Second kernel of the two-kernel form: the interface point of every face
+// of the item (its last face, owned by the next item, too, as in the fused
+// kernel), the MSMD face values kept in LDS, then the item's cells; after
+// stage 2 their signal speeds.
 template <typename T, int STAGE>
 __global__ void __launch_bounds__(kPhaseBlk, 3)
-    point1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
-                   const int* __restrict__ nitems_p, const T* __restrict__ R1, double* __restrict__ R2,
-                   double* __restrict__ Pf, long long F)
+    pointcell1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
+                       const int* __restrict__ nitems_p, const T* __restrict__ R1, double* __restrict__ W,
+                       double* __restrict__ Wx, double* __restrict__ PW, double* __restrict__ Pf, long long Ntot,
+                       long long F)
 {
+    __shared__ double sh_FL[3][kPhaseBlk], sh_FdL[3][kPhaseBlk], sh_Wf[3][kPhaseBlk];
     if ((int)blockIdx.x >= *nitems_p) return;
     const Tile tl = items[blockIdx.x];
     const ProbParam& P = PP[tl.p];
     ProbState& S = PS[tl.p];
     if (!S.active) return;
     const int j = threadIdx.x, f = tl.start + j;
-    if (f > P.nx || (j == kPhaseBlk - 1 && f != P.nx)) return;
-    const long long g = P.foff + f;
     const double dt = S.dt;
-    T o[7][4];
+    if (f <= P.nx) {
+        const long long g = P.foff + f;
+        T o[7][4];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        o[q][0] = R1[(q * 3) * F + g];
-        o[q][1] = R1[(q * 3 + 1) * F + g];
-        o[q][2] = T(0);
-        o[q][3] = R1[(q * 3 + 2) * F + g];
-    }
-    PointIn<T> in;
-    PointOut<T> out;
-    NonEq<T, 1, T> ne;
-    const PointPar par = point_par<1>(P.gamma, P.K, P.mu, dt);
+        for (int q = 0; q < 7; ++q) {
+            o[q][0] = R1[(q * 3) * F + g];
+            o[q][1] = R1[(q * 3 + 1) * F + g];
+            o[q][2] = T(0);
+            o[q][3] = R1[(q * 3 + 2) * F + g];
+        }
+        PointIn<T> in;
+        PointOut<T> out;
+        NonEq<T, 1, T> ne;
+        const PointPar par = point_par<1>(P.gamma, P.K, P.mu, dt);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        in.W0x[k] = o[1][k]; in.W0xx[k] = o[2][k];
-        in.W0y[k] = in.W0xy[k] = in.W0yy[k] = T(0);
-        in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
-        in.Wly[k] = in.Wry[k] = T(0);
-    }
-    bool ok = noneq_states<T, 1, T>(o[3], o[4], T(P.gamma), T(P.K), T(par.iN), ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
-    if (ok) ok = gks_point<T, 1, T>(par, in, P.recon ? ne.Xs : o[0], ne, out);
-    if (!ok) {
-        atomicOr(&S.err, 1);
+        for (int k = 0; k < 4; ++k) {
+            in.W0x[k] = o[1][k]; in.W0xx[k] = o[2][k];
+            in.W0y[k] = in.W0xy[k] = in.W0yy[k] = T(0);
+            in.Wlx[k] = o[5][k]; in.Wrx[k] = o[6][k];
+            in.Wly[k] = in.Wry[k] = T(0);
+        }
+        bool ok = noneq_states<T, 1, T>(o[3], o[4], T(P.gamma), T(P.K), T(par.iN), ne, in.Wlx, in.Wly, in.Wrx, in.Wry);
+        if (ok) ok = gks_point<T, 1, T>(par, in, P.recon ? ne.Xs : o[0], ne, out);
+        if (!ok) {
+            atomicOr(&S.err, 1);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = T(0);
-    }
-    const int slot[3] = {0, 1, 3};
+            for (int k = 0; k < 4; ++k) out.FL[k] = out.FdL[k] = out.S0[k] = out.S1[k] = out.S2[k] = T(0);
+        }
+        const bool own = (j < kPhaseBlk - 1) || (f == P.nx);
+        const int slot[3] = {0, 1, 3};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int sl = slot[k];
-        R2[(3 + k) * F + g] = double(out.FdL[sl]);
-        if (STAGE == 1) {
-            const double s0 = double(out.S0[sl]), s1 = double(out.S1[sl]), s2 = double(out.S2[sl]);
-            R2[k * F + g] = double(out.FL[sl]);
-            R2[(6 + k) * F + g] = msmd_half(s0, s1, s2, dt);
-            Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
-        } else {
-            R2[(6 + k) * F + g] = msmd_corr(Pf[k * F + g], double(out.S2[sl]), dt);
+        for (int k = 0; k < 3; ++k) {
+            const int sl = slot[k];
+            sh_FdL[k][j] = double(out.FdL[sl]);
+            if (STAGE == 1) {
+                const double s0 = double(out.S0[sl]), s1 = double(out.S1[sl]), s2 = double(out.S2[sl]);
+                sh_FL[k][j] = double(out.FL[sl]);
+                sh_Wf[k][j] = msmd_half(s0, s1, s2, dt);
+                if (own) Pf[k * F + g] = msmd_pred(s0, s1, s2, dt);
+            } else {
+                sh_Wf[k][j] = msmd_corr(Pf[k * F + g], double(out.S2[sl]), dt);
+            }
         }
     }
-}
-
-// Phase 3: the item's cells; after stage 2 their signal speeds.  The step
-// is committed by commit1d_kernel, launched after it.
-template <int STAGE>
-__global__ void __launch_bounds__(kPhaseBlk)
-    cell1d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS, const Tile* __restrict__ items,
-                  const int* __restrict__ nitems_p, double* __restrict__ W, double* __restrict__ Wx,
-                  double* __restrict__ PW, const double* __restrict__ R2, long long Ntot, long long F)
-{
-    if ((int)blockIdx.x >= *nitems_p) return;
-    const Tile tl = items[blockIdx.x];
-    const ProbParam& P = PP[tl.p];
-    ProbState& S = PS[tl.p];
-    if (!S.active) return;
-    const int t = threadIdx.x, i = tl.start + t;
-    const bool live = t < kPhaseBlk - 1 && i < P.nx;
+    __syncthreads();
+    const int i = tl.start + j;
+    const bool live = j < kPhaseBlk - 1 && i < P.nx;
     const int cur = S.cur, half = cur == 2 ? 0 : cur + 1, next = cur == 0 ? 2 : cur - 1;
     const int wr = STAGE == 1 ? half : next;
-    const double dt = S.dt, idx = 1.0 / P.dx;
-    const long long c = P.coff + i, g = P.foff + i;
-    const double sp =
-        live ? update_cell_1d<STAGE>(
-                   P, S, c, wr, dt, idx, [&](int q, int k, int s) { return R2[(3 * q + k) * F + g + s]; },
-                   [&](int k) { return STAGE == 1 ? W[((size_t)cur * 3 + k) * Ntot + c] : PW[k * Ntot + c]; }, W, Wx,
-                   PW, Ntot)
-             : 0.0;
+    const double idx = 1.0 / P.dx;
+    const long long c = P.coff + i;
+    const double sp = live ? update_cell_1d<STAGE>(
+                                 P, S, c, wr, dt, idx,
+                                 [&](int q, int k, int s) {
+                                     return q == 0 ? sh_FL[k][j + s] : (q == 1 ? sh_FdL[k][j + s] : sh_Wf[k][j + s]);
+                                 },
+                                 [&](int k) { return STAGE == 1 ? W[((size_t)cur * 3 + k) * Ntot + c] : PW[k * Ntot + c]; },
+                                 W, Wx, PW, Ntot)
+                           : 0.0;
     if (STAGE == 2) block_max_atomic(sp, &S.smax);
 }
 

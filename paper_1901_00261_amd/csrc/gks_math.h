@@ -18,7 +18,7 @@
 namespace gks {
 // Multiply-adds are contracted into FMAs only within one statement, so a
 // function rounds the same way wherever it is inlined (the single-lane,
-// lane-pair and three-phase forms of the batched 1-D step agree bit for bit).
+// lane-pair and two-kernel forms of the batched 1-D step agree bit for bit).
 #pragma clang fp contract(on)
 
 // WENO-Z regularisation (reading of Sec. 3.3: 1e-6 reproduces Tables 3-4)

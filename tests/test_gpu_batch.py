@@ -86,19 +86,19 @@ def test_lane_pair_steps_bit_identical(batch, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_three_phase_steps_bit_identical(batch, precision):
-    """Three-phase steps (face, point and cell kernels, the face values
-    through HBM) reproduce the fused kernel bit for bit: on for the whole
-    run against off."""
+def test_two_kernel_steps_bit_identical(batch, precision):
+    """Two-kernel steps (face kernel, the reconstructed faces through HBM,
+    then the point-and-cell kernel) reproduce the fused kernel bit for bit:
+    on for the whole run against off."""
     ref, cfg0 = run(batch, split="0", phases="0", precision=precision)
     got, cfg = run(batch, split="0", phases="2", precision=precision)
-    assert "three-phase steps off" in cfg0 and "three-phase steps on" in cfg
+    assert "two-kernel steps off" in cfg0 and "two-kernel steps on" in cfg
     for a, b in zip(ref, got):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]
 
 
 def test_step_form_switches_during_a_run():
-    """The 256-problem uneven batch: three-phase steps while its work items
+    """The 256-problem uneven batch: two-kernel steps while its work items
     fill the CUs, fused steps below that, lane-pair steps once the items are
     at most half the CUs; every problem ends bit-identical to a run in the
     fused form throughout."""
@@ -134,9 +134,9 @@ def test_step_form_switches_during_a_run():
 
     ref, _, cfg0 = go("0", "0")
     got, cfg1, cfg = go("1", "1")
-    assert "lane-pair steps off" in cfg0 and "three-phase steps off" in cfg0
-    assert "three-phase steps on" in cfg1
-    assert "lane-pair steps on" in cfg and "three-phase steps off" in cfg
+    assert "lane-pair steps off" in cfg0 and "two-kernel steps off" in cfg0
+    assert "two-kernel steps on" in cfg1
+    assert "lane-pair steps on" in cfg and "two-kernel steps off" in cfg
     assert sum(r[5] == g.GKS_ENONPHYS for r in ref) == 3
     for a, b in zip(ref, got):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[4] == b[4] and a[3] == b[3]

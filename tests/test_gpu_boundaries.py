@@ -119,10 +119,10 @@ def test_inflow_and_batch_of_boundary_kinds():
         check(p, r, oracle_run(p))
 
 
-def test_boundary_kinds_in_three_phase_steps():
+def test_boundary_kinds_in_two_kernel_steps():
     """The batch of boundary kinds (inflow, characteristic ends, walls with
     the blast wave's positivity fallbacks, extrapolation) in FP64
-    three-phase steps (face, point and cell kernels) equals the fused steps
+    two-kernel steps (face, point and cell kernels) equals the fused steps
     bit for bit."""
     import os
     a = wl.riemann_1d(60, *wl.SOD, t_end=0.05)
