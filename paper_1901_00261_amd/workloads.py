@@ -180,6 +180,36 @@ def shu_osher_1d(n=200, *, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=1.8):
                    (1, 1, 0, 0), W, Wx, None, name=f"shu_osher_n{n}")
 
 
+def titarev_toro_1d(n=1000, *, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=5.0):
+    """Shock / high-frequency entropy-wave interaction (Sec. 4.2, after
+    Titarev and Toro): (rho, U, p) = (1.515695, 0.523346, 1.805) for
+    x <= -4.5 and (1 + 0.1 sin 20 pi x, 0, 1) beyond, on [-5, 5]; a
+    characteristic non-reflecting left end and, on the right (where the gas
+    stays at rest until t = 5), the extrapolated profile.  With n a multiple
+    of 20 the shock sits on a face."""
+    xlo, xhi = -5.0, 5.0
+    left = (1.515695, 0.523346, 1.805)
+
+    def fn(x):
+        post = x <= -4.5
+        rho = np.where(post, left[0], 1.0 + 0.1 * np.sin(20.0 * math.pi * x))
+        U = np.where(post, left[1], 0.0)
+        p = np.where(post, left[2], 1.0)
+        return prim_to_cons(rho, U, p, gamma)
+
+    W, Wx = _cell_quadrature_1d(fn, n, xlo, xhi)
+    dx = (xhi - xlo) / n
+    jshock = int(round((-4.5 - xlo) / dx))
+    Wx[:jshock] = 0.0  # constant post-shock state
+    # the first pre-shock cell's gradient from its own (smooth) side only
+    xa, xb = xlo + jshock * dx, xlo + (jshock + 1) * dx
+    Wa = prim_to_cons(1.0 + 0.1 * np.sin(20.0 * math.pi * xa), 0.0, 1.0, gamma)
+    Wb = prim_to_cons(1.0 + 0.1 * np.sin(20.0 * math.pi * xb), 0.0, 1.0, gamma)
+    Wx[jshock] = (Wb - Wa) / dx
+    return Problem(1, n, 1, xlo, xhi, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   (5, 1, 0, 0), W, Wx, None, name=f"titarev_toro_n{n}")
+
+
 ACOUSTIC = dict(eps=1e-5, omega=6.0 * math.pi, rho_inf=1.1771, p_inf=101325.0)
 
 

@@ -85,6 +85,17 @@ def test_shu_osher_characteristic_ends():
     assert np.abs(U[-10:]).max() < 2e-3
 
 
+@pytest.mark.parametrize("order", [8, 6])
+def test_titarev_toro_full_run(order):
+    """Sec. 4.2 Titarev-Toro problem as the paper runs it: 1000 cells to
+    t = 5 (about 3 170 steps), characteristic non-reflecting left end,
+    extrapolated right end where the gas is at rest."""
+    p = wl.titarev_toro_1d(1000, order=order)
+    got = gpu_run([p])[0]
+    check(p, got, oracle_run(p))
+    assert got[5] == 1  # reached t = 5
+
+
 def test_pulse_leaves_through_characteristic_ends():
     """An acoustic pulse half out (t = 0.35) and all out (t = 0.8) of a
     domain with characteristic ends.  The pulse (1e-3) rides on an O(1)

@@ -137,3 +137,18 @@ def test_double_mach_reflection_boundaries():
     assert not Wx[:, 30:].any() and not Wy[:, 30:].any()
     assert rho.sum() > p.W[..., 0].sum()
     print("double Mach 48x12, 4 steps: fallbacks", oracle.fallbacks())
+
+
+def test_titarev_toro_initial_data():
+    """Sec. 4.2 Titarev-Toro initial data: the cell averages carry the
+    closed-form mass and momentum of the two regions (the sine wave has an
+    integer number of periods over (-4.5, 5], so it adds no mass), the shock
+    sits on face 100 of 2000 cells, and the ends are characteristic (left)
+    and extrapolated (right)."""
+    p = wl.titarev_toro_1d(2000)
+    dx = (p.xhi - p.xlo) / p.nx
+    rho_l, u_l = 1.515695, 0.523346
+    assert abs(p.W[:, 0].sum() * dx - (0.5 * rho_l + 9.5)) < 1e-12
+    assert abs(p.W[:, 1].sum() * dx - 0.5 * rho_l * u_l) < 1e-12
+    assert np.all(p.W[:100, 0] == p.W[0, 0]) and abs(p.W[0, 0] - rho_l) < 1e-15
+    assert np.all(p.W[100:, 1] == 0.0) and tuple(p.bc[:2]) == (5, 1)
