@@ -210,6 +210,34 @@ def titarev_toro_1d(n=1000, *, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=5.0):
                    (5, 1, 0, 0), W, Wx, None, name=f"titarev_toro_n{n}")
 
 
+def shock_velocity_wave_1d(n=400, *, order=8, recon=1, gamma=1.4, cfl=0.3, t_end=0.8):
+    """Mach-10 shock crossing a velocity perturbation (Sec. 4.4): (rho, U,
+    p) = (8, 8.25, 116.5) for x <= 1 and (1.4, 0.2 sin 2 pi (x - 1), 1)
+    beyond, on [0, 10]; characteristic non-reflecting ends.  With n a
+    multiple of 10 the shock sits on a face."""
+    xlo, xhi = 0.0, 10.0
+    left = (8.0, 8.25, 116.5)
+
+    def fn(x):
+        post = x <= 1.0
+        rho = np.where(post, left[0], 1.4)
+        U = np.where(post, left[1], 0.2 * np.sin(2.0 * math.pi * (x - 1.0)))
+        p = np.where(post, left[2], 1.0)
+        return prim_to_cons(rho, U, p, gamma)
+
+    W, Wx = _cell_quadrature_1d(fn, n, xlo, xhi)
+    dx = (xhi - xlo) / n
+    jshock = int(round((1.0 - xlo) / dx))
+    Wx[:jshock] = 0.0  # constant post-shock state
+    # the first pre-shock cell's gradient from its own (smooth) side only
+    xa, xb = xlo + jshock * dx, xlo + (jshock + 1) * dx
+    Wa = prim_to_cons(1.4, 0.2 * np.sin(2.0 * math.pi * (xa - 1.0)), 1.0, gamma)
+    Wb = prim_to_cons(1.4, 0.2 * np.sin(2.0 * math.pi * (xb - 1.0)), 1.0, gamma)
+    Wx[jshock] = (Wb - Wa) / dx
+    return Problem(1, n, 1, xlo, xhi, 0.0, 1.0, gamma, 0.0, cfl, 0.0, t_end, order, recon,
+                   (5, 5, 0, 0), W, Wx, None, name=f"shock_velocity_wave_n{n}")
+
+
 ACOUSTIC = dict(eps=1e-5, omega=6.0 * math.pi, rho_inf=1.1771, p_inf=101325.0)
 
 

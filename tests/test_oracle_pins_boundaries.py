@@ -152,3 +152,21 @@ def test_titarev_toro_initial_data():
     assert abs(p.W[:, 1].sum() * dx - 0.5 * rho_l * u_l) < 1e-12
     assert np.all(p.W[:100, 0] == p.W[0, 0]) and abs(p.W[0, 0] - rho_l) < 1e-15
     assert np.all(p.W[100:, 1] == 0.0) and tuple(p.bc[:2]) == (5, 1)
+
+
+def test_shock_velocity_wave_initial_data():
+    """Sec. 4.4 initial data: closed-form mass, momentum and energy of the
+    two regions (the velocity wave has whole periods over (1, 10], so its
+    momentum integrates to zero and its kinetic energy to 0.2^2/4 per unit
+    length times the density), the shock on face 40 of 400 cells, and
+    characteristic ends."""
+    p = wl.shock_velocity_wave_1d(400)
+    dx = (p.xhi - p.xlo) / p.nx
+    g = p.gamma
+    E_l = 116.5 / (g - 1.0) + 0.5 * 8.0 * 8.25 ** 2
+    E_r = 9.0 * (1.0 / (g - 1.0) + 0.5 * 1.4 * 0.2 ** 2 / 2.0)
+    assert abs(p.W[:, 0].sum() * dx - (8.0 + 9.0 * 1.4)) < 1e-12
+    assert abs(p.W[:, 1].sum() * dx - 8.0 * 8.25) < 1e-12
+    assert abs(p.W[:, 2].sum() * dx - (E_l + E_r)) < 1e-11
+    assert np.abs(p.W[:40, 0] - 8.0).max() < 1e-14 and np.abs(p.W[40:, 0] - 1.4).max() < 1e-14
+    assert tuple(p.bc[:2]) == (5, 5)
