@@ -411,6 +411,53 @@ GKS_HD void tan_weno_pair(const T* ql, const T* qr, int g, T& vl, T& vr)
     vr = nr * dl * r;
 }
 
+// erfc(z) from q = exp(-z^2), which the half-range moments form anyway.
+// For a = |z|: erfc(a) = q p(t) / (1 + 2a), t = (a - K) / (a + K) in
+// [-1, 1), where p is a polynomial fitted to (1 + 2a) exp(a^2) erfc(a), a
+// function analytic in t (the mapping of J. L. Schonfelder, Math. Comp. 32,
+// 1978); then erfc(-a) = 2 - erfc(a).  One reciprocal and no branch, where
+// the library's erfc picks among argument ranges (lanes of a wave in
+// different ranges run several of them).  The even and odd parts of p are
+// two interleaved Horner chains in t^2.  Coefficients and their error (at
+// most 2.9 ulp of exp(a^2) erfc(a) over [0, 30] in either precision) from
+// erfc_fit.py; other types (the operation counter) call the library.
+constexpr double kErfcK64 = 3.0;
+constexpr double kErfcP64[25] = {
+    1.2530080582697296,     -0.13562110612458117,   -0.04756229435345087,   0.1296451587027606,
+    -0.11927366341530699,   0.06830802734397848,    -0.023770514918645888,  0.002529391816066239,
+    0.0018886903591561553,  -0.0007798322721083991, -0.00010515979981501177, 0.00012509935235563107,
+    4.949484992570595e-06,  -2.0100567931289227e-05, -7.315105164159062e-07, 3.472414602875686e-06,
+    3.5683839153992204e-07, -6.166496077604353e-07, -1.4160064940265987e-07, 1.0187000600072885e-07,
+    4.180784698845582e-08,  -1.3326364813003834e-08, -8.500397929772615e-09, 9.885798831139365e-10,
+    8.864219016427092e-10};
+constexpr float kErfcK32 = 2.0f;
+constexpr float kErfcP32[11] = {
+    1.2769783735275269f,   -0.0927630364894867f,    -0.16603060066699982f, 0.16403527557849884f,
+    -0.05421590059995651f, -0.007940706796944141f,  0.008700217120349407f, 0.0010404807981103659f,
+    -0.0014083577552810311f, -0.00018247801926918328f, 0.00016586757556069642f};
+
+template <typename T, int N>
+GKS_HD T erfc_mapped(T z, T q, const T (&c)[N], T K)
+{
+    const T a = tabs(z);
+    const T b = fmadd(T(2), a, T(1));
+    const T r = rcp((a + K) * b);
+    const T t = (a - K) * b * r;
+    const T w = (a + K) * r; // 1 / (1 + 2a)
+    const T t2 = t * t;
+    constexpr int je = (N - 1) & ~1, jo = ((N - 2) & ~1) + 1;
+    T ev = c[je], od = c[jo];
+#pragma unroll
+    for (int j = je - 2; j >= 0; j -= 2) ev = fmadd(ev, t2, c[j]);
+#pragma unroll
+    for (int j = jo - 2; j >= 1; j -= 2) od = fmadd(od, t2, c[j]);
+    const T v = q * (fmadd(od, t, ev) * w);
+    return z < T(0) ? T(2) - v : v;
+}
+template <typename T> GKS_HD T erfc_q(T z, T) { return erfc(z); }
+template <> GKS_HD double erfc_q<double>(double z, double q) { return erfc_mapped(z, q, kErfcP64, kErfcK64); }
+template <> GKS_HD float erfc_q<float>(float z, float q) { return erfc_mapped(z, q, kErfcP32, kErfcK32); }
+
 // ---------------------------------------------------------------------------
 // Maxwellian moments (Sec. 2.1).  For g = rho (lam/pi)^{(K+D)/2}
 // exp(-lam((u-U)^2 + (v-V)^2 + xi^2)) with unit density:
@@ -436,12 +483,13 @@ GKS_HD void make_moments(T U, T V, T lam, T h, T K, int half, Moments<T, DIM, NU
         m.mu[1] = U;
     } else {
         const T sl = sqrt(lam);
+        const T q = exp(-lam * U * U);
         // (1/2) / sqrt(pi lam) = h sqrt(lam) / sqrt(pi)
-        const T e = exp(-lam * U * U) * (h * sl) * T(0.56418958354775628695);
+        const T e = q * (h * sl) * T(0.56418958354775628695);
         // u > 0 (half = +1) or u < 0 (half = -1), without a branch: the two
         // states of a lane pair run the same instructions
         const T s = half > 0 ? T(1) : T(-1);
-        m.mu[0] = T(0.5) * erfc(-s * sl * U);
+        m.mu[0] = T(0.5) * erfc_q(-s * sl * U, q);
         m.mu[1] = fmadd(U, m.mu[0], s * e);
     }
 #pragma unroll
