@@ -500,30 +500,34 @@ def study_equal_l1(args):
                    "Linf_rho": linf, "seconds": el, "cell_updates_per_s": N * N * n / el}
             rows.append(row)
             log(json.dumps(row))
-    # equal-L1 pairs: FP64 grid with the same L1 (log-log interpolation in N) and its time to solution
+    return {"study": "equal-L1", "workload": name, "T3": T3, "reference": {"N": 2048, "steps": nr, "seconds": elr},
+            "rows": rows, "equal_L1_pairs": equal_l1_pairs(rows)}
+
+
+def equal_l1_pairs(rows):
+    """For each mixed run, the FP64 grid with the same L1 (log-log
+    interpolation in N over the FP64 runs, whose L1 falls with N) and the
+    FP64 time to solution there.  A target within 1e-4 (relative) of the
+    coarsest or finest FP64 L1 takes that grid; beyond the range: NaN."""
+    import numpy as np
     f64 = [r for r in rows if r["precision"] == "fp64"]
+    Ns = np.log([x["N"] for x in f64])
+    Ls = np.log([x["L1_rho"] for x in f64])
+    ts = np.log([x["seconds"] for x in f64])
+    order = np.argsort(Ls)
     pairs = []
     for r in rows:
         if r["precision"] != "mixed":
             continue
-        target = r["L1_rho"]
-        Ns = np.log([x["N"] for x in f64])
-        Ls = np.log([x["L1_rho"] for x in f64])
-        ts = np.log([x["seconds"] for x in f64])
-        # FP64 L1 decreases with N; find N' with L1(N') = target
-        if target >= math.exp(Ls[0]):
-            n_eq, t_eq = float("nan"), float("nan")
-        elif target <= math.exp(Ls[-1]):
-            n_eq, t_eq = float("nan"), float("nan")
+        lt = math.log(r["L1_rho"])
+        if Ls.min() - 1e-4 <= lt <= Ls.max() + 1e-4:
+            ln = float(np.interp(min(max(lt, Ls.min()), Ls.max()), Ls[order], Ns[order]))
+            n_eq, t_eq = math.exp(ln), math.exp(float(np.interp(ln, Ns, ts)))
         else:
-            order = np.argsort(Ls)
-            ln = float(np.interp(math.log(target), Ls[order], Ns[order]))
-            n_eq = math.exp(ln)
-            t_eq = math.exp(float(np.interp(ln, Ns, ts)))
-        pairs.append({"mixed_N": r["N"], "mixed_L1": target, "mixed_seconds": r["seconds"],
+            n_eq, t_eq = float("nan"), float("nan")
+        pairs.append({"mixed_N": r["N"], "mixed_L1": r["L1_rho"], "mixed_seconds": r["seconds"],
                       "fp64_N_at_equal_L1": n_eq, "fp64_seconds_at_equal_L1": t_eq})
-    return {"study": "equal-L1", "workload": name, "T3": T3, "reference": {"N": 2048, "steps": nr, "seconds": elr},
-            "rows": rows, "equal_L1_pairs": pairs}
+    return pairs
 
 
 def main():

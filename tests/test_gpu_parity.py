@@ -442,10 +442,7 @@ def test_vortex_128_to_t02_fp64():
 def test_riemann_2d_256_500_steps_fp64():
     """The four-quadrant Riemann workload (seed 5) on 256^2 cells for 500
     CFL-0.3 steps, against the oracle's run (sampled cells and sums)."""
-    path = os.path.join(GOLDEN, "riemann2d_256_s500.npz")
-    if not os.path.exists(path):
-        pytest.skip("oracle reference not written yet (tests/golden/make_oracle_refs.py riemann2d_256_s500)")
-    ref = np.load(path)
+    ref = np.load(os.path.join(GOLDEN, "riemann2d_256_s500.npz"))
     p = wl.riemann_2d(256, seed=5, order=8, recon=1, cfl=0.3)
     g = gks()
     S = g.Solver(p)
