@@ -670,13 +670,34 @@ template <typename T> GKS_HD bool physical(const T* W, T gamma, int dim)
 // integrals over [0, dt/2] and [0, dt] are matched by a + b t), FP64.
 // ke, kte: value coefficients of the e and t*e parts; kde, kdte: slopes.
 // ---------------------------------------------------------------------------
+// e^{-x} and 1 - e^{-x} for x >= 0.  In FP64 one library call: the smaller
+// of the two (at most 1/2, x > ln 2 or not) is evaluated and the other is 1
+// minus it, which rounds once (half an ulp).  Other types (the operation
+// counter) evaluate both.
+template <typename D> GKS_HD void exp_pair(D x, D& q, D& om)
+{
+    q = exp(-x);
+    om = -expm1(-x);
+}
+template <> GKS_HD void exp_pair<double>(double x, double& q, double& om)
+{
+    if (x > 0.69314718055994531) {
+        q = exp(-x);
+        om = 1.0 - q;
+    } else {
+        om = -expm1(-x);
+        q = 1.0 - om;
+    }
+}
+
 template <typename D>
 GKS_HD void exp_fit(D tau_n, D dt, D idt, D& ke, D& kte, D& kde, D& kdte)
 {
     const D x2 = dt * rcp(tau_n), x1 = D(0.5) * x2;
     // e^{-x2} = (e^{-x1})^2 and 1 - e^{-x2} = (1 - e^{-x1})(1 + e^{-x1})
-    const D q1 = exp(-x1), q2 = q1 * q1;
-    const D om1 = -expm1(-x1), om2 = om1 * (D(1) + q1); // 1 - e^{-x}
+    D q1, om1; // e^{-x1}, 1 - e^{-x1}
+    exp_pair(x1, q1, om1);
+    const D q2 = q1 * q1, om2 = om1 * (D(1) + q1);
     const D Ie1 = tau_n * om1, Ie2 = tau_n * om2;
     const D It1 = tau_n * tau_n * om1 - tau_n * (D(0.5) * dt) * q1;
     const D It2 = tau_n * tau_n * om2 - tau_n * dt * q2;
