@@ -127,6 +127,34 @@ def test_2d_vortex_navier_stokes_small():
     check(p, got, want)
 
 
+@pytest.mark.parametrize("dim", [1, 2])
+def test_strongly_viscous_time_coefficients(dim):
+    """Navier-Stokes with a viscosity large enough that x = dt / (2 tau)
+    of the time coefficients (Sec. 2.1; tau = mu/p) stays below ln 2 at
+    every point, where the kernels take 1 - e^{-x} from expm1 and e^{-x} as
+    1 minus it (elsewhere the other way round): 1-D sine wave and the 2-D
+    vortex, 10 steps, against the oracle."""
+    import dataclasses
+    if dim == 1:
+        p = dataclasses.replace(wl.sine_wave_1d(32, order=8, recon=1), mu=0.05)
+    else:
+        p = wl.isentropic_vortex_2d(20, ny=16, mu=0.3, acoustic_amp=1e-2)
+    want = oracle_run(p, max_steps=10)
+    dt0 = float(oracle_run(p, max_steps=1)[3])
+    W = p.W.reshape(-1, p.dim + 2)
+    rho, E = W[:, 0], W[:, -1]
+    kin = 0.5 * (W[:, 1:-1] ** 2).sum(axis=1) / rho
+    pmax = float(((p.gamma - 1.0) * (E - kin)).max())
+    # tau >= mu / p: the largest x of the first step
+    assert dt0 * pmax / (2.0 * p.mu) < math.log(2.0), (dt0, pmax)
+    g = gks()
+    S = g.Solver(p)
+    S.step(10)
+    got = S.state(0)
+    S.close()
+    check(p, got, want)
+
+
 @pytest.mark.parametrize("order,recon", [(6, 0), (8, 1)])
 def test_2d_vortex_euler_small(order, recon):
     p = wl.isentropic_vortex_2d(16, ny=18, mu=0.0, order=order, recon=recon)
