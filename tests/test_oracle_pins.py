@@ -344,6 +344,37 @@ def test_maxwellian_moments():
     assert abs(oracle.raw_moment(1, g, W, 0, 0, 2) / rho - K * (K + 2) / (4 * lam * lam)) < 1e-12
 
 
+@pytest.mark.parametrize("rho,U,p", [(8.0, 8.25, 116.5), (1.0, 4.0, 1.0), (0.5, -2.0, 0.1), (1.0, -5.5, 1.0)])
+def test_half_range_moments_supersonic(rho, U, p):
+    """Half-range moments with sqrt(lam) |U| from 1.5 (the post-shock state
+    of the Mach-10 problem of Sec. 4.4) to 3.9: the erfc tail and the
+    exp(-lam U^2) term against adaptive quadrature with a relative
+    tolerance only, and the two halves summing to the full moment.  The
+    higher moments of the small half follow from the lower ones by the
+    recursion <u^n> = U <u^(n-1)> + (n-1) <u^(n-2)> / (2 lam), whose two terms
+    nearly cancel there (relative errors up to a few 1e-10 at n = 6 on tails
+    of 1e-10, 1e-19 absolute): the bar is 1e-10 of the half plus 1e-15 of
+    the full moment."""
+    from scipy import integrate
+    g = 1.4
+    W = np.array([rho, rho * U, p / (g - 1) + 0.5 * rho * U * U])
+    lam = rho / (2 * p)
+    assert 1.5 <= math.sqrt(lam) * abs(U) < 4.0
+    s_ = 1.0 / math.sqrt(lam)
+    for a in range(0, 7):
+        full = oracle.raw_moment(1, g, W, a, 0, 0, 0)
+        for half in (+1, -1):
+            h = oracle.raw_moment(1, g, W, a, 0, 0, half)
+            # u = U + s x: the Gaussian in x, the half range x > -U/s or x < -U/s
+            f = lambda x: rho / math.sqrt(math.pi) * math.exp(-x * x) * (U + s_ * x) ** a
+            x0 = -U / s_
+            lo, hi = (x0, np.inf) if half > 0 else (-np.inf, x0)
+            want = integrate.quad(f, lo, hi, epsabs=0.0, epsrel=1e-13, limit=200)[0]
+            assert abs(h - want) < 1e-10 * abs(want) + 1e-15 * abs(full), (a, half, h, want)
+        s = oracle.raw_moment(1, g, W, a, 0, 0, 1) + oracle.raw_moment(1, g, W, a, 0, 0, -1)
+        assert abs(s - full) < 1e-12 * abs(full)
+
+
 @pytest.mark.parametrize("dim", [1, 2])
 def test_psi_moments_recover_state_and_flux(dim):
     """<psi> of the Maxwellian of W is W; <u psi> is the Euler flux."""
