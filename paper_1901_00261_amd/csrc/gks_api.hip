@@ -40,6 +40,8 @@ struct gks_handle {
     double *W = nullptr, *Wx = nullptr, *Wy = nullptr, *PW = nullptr;
     double *FL = nullptr, *FdL = nullptr, *Wfs = nullptr, *Pf = nullptr;
     double *FLy = nullptr, *FdLy = nullptr, *Wfsy = nullptr, *Pfy = nullptr;
+    double* bmax = nullptr; // 2-D: per-workgroup signal-speed maxima of the cell update
+    int nbmax = 0;
     void *Rx = nullptr, *Ry = nullptr; // face-row buffers: double (FP64) or float (FP32-mixed)
     double* R1 = nullptr; // 1-D two-kernel steps: reconstructed faces
     double* stage = nullptr; // transpose staging
@@ -289,6 +291,9 @@ template <typename T> void launch_step_1d(gks_handle* h, hipStream_t st)
     h->act_list = b;
 }
 
+// workgroups of the 2-D cell update: tiles of 64 x 4 cells
+int cell_blocks(int nx, int ny) { return ((nx + 63) / 64) * ((ny + 3) / 4); }
+
 template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
 {
     const ProbParam& P = h->hp[0];
@@ -299,7 +304,7 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
     auto tiles = [](int ext_x, int ext_y, dim3 b) { return ((ext_x + b.x - 1) / b.x) * ((ext_y + b.y - 1) / b.y); };
     const int grx = tiles(gks::faces_computed(nx, P.bc[0]), ny + 4, br), gry = tiles(nx + 4, gks::faces_computed(ny, P.bc[2]), br);
     const int ggx = tiles(gks::faces_computed(nx, P.bc[0]), ny, bg), ggy = tiles(nx, gks::faces_computed(ny, P.bc[2]), bg);
-    const int gc = tiles(nx, ny, bc);
+    const int gc = tiles(nx, ny, bc); // == cell_blocks(nx, ny) == h->nbmax
     // The x-face and y-face kernels of a stage are independent until the cell
     // update: the y-face pair runs on the side stream, so that the two chains
     // overlap (each fills the other's partly idle last wave of workgroups).
@@ -342,13 +347,13 @@ template <typename T> void launch_step_2d(gks_handle* h, hipStream_t st)
         record(h, st, 2, true);
         if (stage == 1)
             gks::cell2d_kernel<1><<<gc, bc, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL, h->Wfs,
-                                                      h->FLy, h->FdLy, h->Wfsy);
+                                                      h->FLy, h->FdLy, h->Wfsy, h->bmax);
         else
             gks::cell2d_kernel<2><<<gc, bc, 0, st>>>(h->dP, h->dS, h->W, h->Wx, h->Wy, h->PW, h->FL, h->FdL, h->Wfs,
-                                                      h->FLy, h->FdLy, h->Wfsy);
+                                                      h->FLy, h->FdLy, h->Wfsy, h->bmax);
         record(h, st, 2, false);
     }
-    gks::finish_kernel<<<1, 64, 0, st>>>(h->dP, h->dS, 1, 1, nullptr, 2);
+    gks::finish2d_kernel<<<1, 256, 0, st>>>(h->dP, h->dS, h->bmax, gc);
 }
 
 void launch_step(gks_handle* h, hipStream_t st)
@@ -538,7 +543,7 @@ void release(gks_handle* h)
     for (void* p : {(void*)h->dP, (void*)h->dS, (void*)h->dTilesC, (void*)h->W, (void*)h->Wx,
                     (void*)h->Wy, (void*)h->PW, (void*)h->FL, (void*)h->FdL, (void*)h->Wfs, (void*)h->Pf,
                     (void*)h->FLy, (void*)h->FdLy, (void*)h->Wfsy, (void*)h->Pfy, (void*)h->Rx, (void*)h->Ry,
-                    (void*)h->R1, (void*)h->stage})
+                    (void*)h->R1, (void*)h->stage, (void*)h->bmax})
         dfree(p);
     drop_graph(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
@@ -734,6 +739,8 @@ int init_common(const gks_problem* probs, int32_t nprob, int32_t precision, cons
             HIP_TRY(h, dalloc(&h->FdLy, 4 * nfy));
             HIP_TRY(h, dalloc(&h->Wfsy, 4 * nfy));
             HIP_TRY(h, dalloc(&h->Pfy, 4 * nfy));
+            h->nbmax = cell_blocks((int)nx, (int)ny);
+            HIP_TRY(h, dalloc(&h->bmax, h->nbmax));
             const int es = precision == GKS_PREC_FP64 ? 8 : 4;
             HIP_TRY(h, hipMalloc(&h->Rx, (size_t)gks::row_buffer_elems((int)nx, (int)ny, 0, es) * es));
             HIP_TRY(h, hipMalloc(&h->Ry, (size_t)gks::row_buffer_elems((int)nx, (int)ny, 1, es) * es));

@@ -212,6 +212,20 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* d
     }
 }
 
+// block-wide maximum of a value (every thread receives it)
+__device__ __forceinline__ double block_max(double v)
+{
+    __shared__ double red[16];
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wid = (threadIdx.x + threadIdx.y * blockDim.x) >> 6;
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double m = red[0];
+    for (int w = 1; w < nw; ++w) m = fmax(m, red[w]);
+    return m;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (bid % 8), each with
 // its own L2.  Give every XCD a contiguous range of tiles (a band of tile
 // rows) so that the stencil neighbours of a tile are cached in the same L2.
@@ -1364,7 +1378,8 @@ __global__ void __launch_bounds__(256) cell2d_kernel(const ProbParam* __restrict
                                                      double* __restrict__ Wy, double* __restrict__ PW,
                                                      const double* __restrict__ FLx, const double* __restrict__ FdLx,
                                                      const double* __restrict__ Wfx, const double* __restrict__ FLy,
-                                                     const double* __restrict__ FdLy, const double* __restrict__ Wfy)
+                                                     const double* __restrict__ FdLy, const double* __restrict__ Wfy,
+                                                     double* __restrict__ bmax)
 {
     const ProbParam& P = PP[0];
     ProbState& S = PS[0];
@@ -1415,7 +1430,27 @@ __global__ void __launch_bounds__(256) cell2d_kernel(const ProbParam* __restrict
                 s = fmax((fabs(U) + c) * idx, (fabs(V) + c) * idy);
             }
         }
-        block_max_atomic(s, &S.smax);
+        // one plain store per workgroup; finish2d_kernel takes the maximum
+        // (thousands of atomics on one address would queue at the memory side)
+        const double m = block_max(s);
+        if (threadIdx.x + threadIdx.y * blockDim.x == 0) bmax[blockIdx.x] = m;
+    }
+}
+
+// Commit of a 2-D step (one workgroup): the largest signal speed over the
+// second-stage cell-update workgroups' maxima bmax[0..nb), then the step as
+// finish_kernel commits it.
+__global__ void __launch_bounds__(256) finish2d_kernel(const ProbParam* __restrict__ PP, ProbState* __restrict__ PS,
+                                                       const double* __restrict__ bmax, int nb)
+{
+    ProbState& S = PS[0];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v = fmax(v, bmax[b]);
+    const double m = block_max(v);
+    if (threadIdx.x == 0 && S.active) {
+        const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+        if (m > 0.0 && mb > S.smax) S.smax = mb;
+        finish_problem(PP[0], S, 1, 2);
     }
 }
 
